@@ -1,0 +1,148 @@
+"""Checks that pin the oracle to the mathematics, not to itself.
+
+Each check is a function of an oracle module so the mutation tests can run the
+same checks against deliberately broken copies of the oracle.  None of them
+retypes the oracle's formulas: they use closed forms, optimality conditions
+written directly on W = inv(A) (computed here with numpy.linalg.inv), an
+independent proximal-gradient solver, and brute-force search.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# ----------------------------------------------------------------- independent pieces
+def st(x, tau):
+    return np.sign(x) * np.maximum(np.abs(x) - tau, 0.0)
+
+
+def f_direct(S, A, lam):
+    """F(A) via slogdet (not the oracle's Cholesky path)."""
+    sign, ld = np.linalg.slogdet(A)
+    if sign <= 0:
+        return np.inf
+    return -ld + np.trace(S @ A) + lam * np.abs(A).sum()
+
+
+def kkt_violation(S, A, lam):
+    """Largest violation of the GLASSO optimality conditions, written on
+    W = inv(A): W_ii = S_ii + lam; W_ij - S_ij = lam sign(A_ij) where A_ij != 0;
+    |W_ij - S_ij| <= lam where A_ij == 0."""
+    W = np.linalg.inv(A)
+    W = 0.5 * (W + W.T)
+    R = W - S
+    n = A.shape[0]
+    viol = 0.0
+    for i in range(n):
+        for j in range(n):
+            if A[i, j] != 0:
+                viol = max(viol, abs(R[i, j] - lam * np.sign(A[i, j])))
+            else:
+                viol = max(viol, max(0.0, abs(R[i, j]) - lam))
+    return viol
+
+
+def gista(S, lam, tol=1e-12, max_iter=20000):
+    """Proximal gradient (G-ISTA, H = I in eq. proximal_gen) with the classical safe
+    step t = 0.9 lambda_min(A)^2 (inverse Lipschitz constant of grad f near A),
+    halved while the step leaves the PD cone or fails to decrease F.  Independent
+    of the oracle's code."""
+    A = np.diag(1.0 / (np.diag(S) + lam))
+    F = f_direct(S, A, lam)
+    for _ in range(max_iter):
+        W = np.linalg.inv(A)
+        g = S - W
+        t = 0.9 * np.linalg.eigvalsh(A)[0] ** 2
+        while True:
+            An = st(A - t * g, t * lam)
+            An = 0.5 * (An + An.T)
+            Fn = f_direct(S, An, lam)
+            if np.isfinite(Fn) and Fn <= F + 1e-14 * abs(F):
+                break
+            t *= 0.5
+        D = An - A
+        A, F = An, Fn
+        if np.abs(D).max() < tol:
+            break
+    return A
+
+
+def n2_closed_form(S, lam):
+    """n = 2: W* = [[S11+lam, ST(S12, lam)], [ST(S12, lam), S22+lam]], A* = inv(W*)."""
+    w12 = st(S[0, 1], lam)
+    W = np.array([[S[0, 0] + lam, w12], [w12, S[1, 1] + lam]])
+    return np.linalg.inv(W)
+
+
+def random_psd(n, m, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, m))
+    S = X @ X.T / m
+    return 0.5 * (S + S.T)
+
+
+# ----------------------------------------------------------------- pin checks
+def check_scalar_lemma(orc, trials=200, seed=0):
+    """App. A lemma: D = -A + ST(A - tB, tC) solves x/t + B + C T(A + x) = 0 and
+    minimises x^2/(2t) + Bx + C|A + x| (brute force on a fine grid)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(trials):
+        a, b = rng.normal(scale=2.0, size=2)
+        c = rng.uniform(0.01, 2.0)
+        t = rng.uniform(0.05, 2.0)
+        x = float(orc.direction(np.array([[a]]), np.array([[b]]), np.array([[c]]), t)[0, 0])
+        grid = np.linspace(x - 3.0, x + 3.0, 60001)
+        h = grid ** 2 / (2 * t) + b * grid + c * np.abs(a + grid)
+        hx = x ** 2 / (2 * t) + b * x + c * abs(a + x)
+        if hx > h.min() + 1e-9:
+            return False
+        if abs(grid[np.argmin(h)] - x) > 2e-4:
+            return False
+    return True
+
+
+def check_n2_closed_form(orc, seeds=range(6), lams=(0.05, 0.2, 0.6)):
+    for seed in seeds:
+        S = random_psd(2, 3, seed)
+        for lam in lams:
+            r = orc.pista(S, lam, 1e-12, max_iter=2000)
+            A_ref = n2_closed_form(S, lam)
+            if not np.allclose(r.A, A_ref, rtol=1e-8, atol=1e-10):
+                return False
+    return True
+
+
+def check_kkt_invariants(orc, n=20, seed=3, lam=0.15, tol=1e-9):
+    S = random_psd(n, n // 2, seed)
+    r = orc.pista(S, lam, tol, max_iter=3000)
+    if r.status != orc.CONVERGED:
+        return False
+    if kkt_violation(S, r.A, lam) > 1e-6:
+        return False
+    gap = np.trace(S @ r.A) + lam * np.abs(r.A).sum() - n
+    return abs(gap) < 1e-6 * n
+
+
+def check_against_gista(orc, n=12, seed=5, lam=0.1):
+    S = random_psd(n, n, seed)
+    r = orc.pista(S, lam, 1e-10, max_iter=3000)
+    A_g = gista(S, lam)
+    return np.allclose(r.A, A_g, rtol=1e-6, atol=1e-8)
+
+
+def check_diagonal_solution(orc, n=15, seed=7):
+    S = random_psd(n, 3 * n, seed)
+    lam = np.abs(S - np.diag(np.diag(S))).max() * 1.01
+    r = orc.pista(S, lam, 1e-12)
+    A_ref = np.diag(1.0 / (np.diag(S) + lam))
+    return r.iterations == 0 and np.allclose(r.A, A_ref, rtol=1e-14, atol=0)
+
+
+def all_pins(orc):
+    return {
+        "scalar_lemma": check_scalar_lemma(orc, trials=40),
+        "n2_closed_form": check_n2_closed_form(orc, seeds=range(3)),
+        "kkt_invariants": check_kkt_invariants(orc),
+        "against_gista": check_against_gista(orc),
+        "diagonal": check_diagonal_solution(orc),
+    }
