@@ -1,0 +1,156 @@
+/*
+ * libglasso -- pISTA for the graphical lasso on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Shalom, Treister & Yavneh, arXiv 2205.10027, Sec. 2.1, eqs. log_MLE
+ * and sparse_obj):
+ *
+ *     minimise  F(A) = -log det A + tr(S A) + lambda * sum_{i,j} |A_ij|   over A > 0,
+ *
+ * the diagonal being penalised.  The solver is Algorithm 1 (pISTA) with the
+ * initialisation, line search and stopping rule of Sec. 5.
+ *
+ * Conventions for every entry point below
+ *  - Matrices are dense, FP64, n x n, row-major with leading dimension n, in
+ *    DEVICE memory owned by the caller (e.g. a torch tensor's data_ptr()).
+ *    Symmetric inputs are read through their lower triangle only.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All work is enqueued
+ *    on it; calls return after the work they need to inspect has completed.
+ *  - Every call returns a glasso_err and never aborts the process.
+ *  - A handle owns a cached device workspace (grown on demand, freed by
+ *    glasso_destroy).  A handle is not thread-safe: use one per host thread.
+ */
+#ifndef GLASSO_H
+#define GLASSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct glasso_handle_s* glasso_handle;
+
+typedef enum {
+  GLASSO_OK = 0,
+  GLASSO_ERR_INVALID_ARG = 1, /* bad size, lambda, tol, NULL pointer, non-finite S, S_ii + lambda <= 0 */
+  GLASSO_ERR_NOT_PD = 2,      /* the warm start (or a Cholesky input) is not positive definite */
+  GLASSO_ERR_OOM = 3,         /* device workspace allocation failed */
+  GLASSO_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+  GLASSO_ERR_INTERNAL = 5
+} glasso_err;
+
+typedef enum {
+  GLASSO_CONVERGED = 0, /* ||Z||_1 <= tol * ||A||_1 (stopping rule, Sec. 5) */
+  GLASSO_MAX_ITER = 1,  /* max_iter accepted steps without meeting tol */
+  GLASSO_LS_FAILED = 2  /* no step size down to t_min was PD with a strict decrease */
+} glasso_status;
+
+typedef enum {
+  GLASSO_FP64 = 0,        /* every step in FP64 */
+  GLASSO_MIXED_FP32 = 1,  /* A Z A products in FP32 MFMA; factor, log det, PD test, W, KKT in FP64 */
+  GLASSO_MIXED_BF16X3 = 2 /* A Z A products as three BF16 split products, FP32 accumulation */
+} glasso_precision;
+
+typedef struct {
+  int precision;   /* glasso_precision; default GLASSO_FP64 */
+  int max_iter;    /* accepted steps before GLASSO_MAX_ITER; default 500 */
+  double t0;       /* first step size of every line search; default 1 (Alg. 1) */
+  double shrink;   /* backtracking factor; default 0.5 (Sec. 3.3.2) */
+  double t_floor;  /* below it, t = min(t, (0.9/cond A)^2) (Sec. 5); default 1e-4 */
+  double t_min;    /* the line search fails below it; default 1e-12 */
+  int warm_start;  /* nonzero: A holds the starting iterate (Alg. 1 takes A^(0)) */
+  int reserved;
+} glasso_options;
+
+typedef struct {
+  double objective; /* F(A) of the returned A */
+  double kkt_rel1;  /* ||Z||_1 / ||A||_1, Z the minimum-norm subgradient (Sec. 3.3.1, Sec. 5) */
+  double kkt_fro;   /* ||Z||_F (the measure the paper's tables report) */
+  double kkt_max;   /* max |Z_ij| */
+  int64_t nnz;      /* nonzeros of the returned A (full count, diagonal included) */
+  int iterations;   /* accepted steps */
+  int ls_trials;    /* trial points factored by the line search, over all iterations */
+  int status;       /* glasso_status */
+  int fallback_steps; /* line searches that reached t_floor and used the cond-based step */
+  double time_ms[8];  /* [0] total, [1] W = A^-1, [2] gradient pass, [3] A Z A, [4] line search */
+} glasso_info;
+
+/* Fill *opt with the defaults listed above. */
+glasso_err glasso_default_options(glasso_options* opt);
+
+/* Create a handle bound to the current HIP device.  opt may be NULL (defaults).
+ * The options are copied.  Errors: INVALID_ARG for h == NULL or out-of-range options. */
+glasso_err glasso_create(glasso_handle* h, const glasso_options* opt);
+
+/* Release the handle and its device workspace.  NULL is accepted. */
+glasso_err glasso_destroy(glasso_handle h);
+
+/* Static description of an error code. */
+const char* glasso_error_string(glasso_err e);
+
+/* Device bytes of workspace a solve of size n needs with `precision` (for
+ * admission by HBM footprint).  Errors: INVALID_ARG for n < 1 or bytes == NULL. */
+glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
+
+/* Solve the graphical lasso for one S (Alg. 1 of the paper, Sec. 5 settings).
+ *   S      n x n empirical covariance (device, read-only, lower triangle read)
+ *   lambda regularisation weight (alpha in the paper), > 0
+ *   tol    stopping tolerance on ||Z||_1 / ||A||_1, > 0
+ *   A      n x n output (device): the solution, full symmetric.  With
+ *          opt.warm_start it is also the input iterate A^(0).
+ *   W      n x n output (device, may be NULL): A^{-1}, full symmetric, FP64
+ *   info   output (host, may be NULL)
+ * Reaching max_iter or failing the line search is reported in info->status and
+ * is not an error; the last accepted iterate is returned.
+ * Errors: INVALID_ARG (n < 1, lambda <= 0, tol <= 0, NULL S/A, non-finite S,
+ * S_ii + lambda <= 0), NOT_PD (warm start not PD), OOM, HIP. */
+glasso_err glasso_solve(glasso_handle h, const double* S, int64_t n, double lambda, double tol,
+                        double* A, double* W, glasso_info* info, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Step-level entry points: each runs one step of the per-iteration path on
+ * caller buffers (device, n x n, row-major, ld n), so every step can be checked
+ * on its own.  They use the handle's workspace and synchronise the stream.
+ * -------------------------------------------------------------------------- */
+
+/* Lower Cholesky factor L of SPD A (the PD test of condition t_cond_pd,
+ * Sec. 3.3.2): L (n x n, output) gets L in its lower triangle and zeros above.
+ * *info = 0 on success, else the 1-based column of the first non-positive or
+ * non-finite pivot.  *logdet (may be NULL) = 2 sum log L_ii (eq. log_MLE). */
+glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* L, int64_t* info,
+                           double* logdet, void* stream);
+
+/* W = A^{-1} (full symmetric) from the Cholesky factor of A (eq. grad_hessian
+ * needs it for g = S - W).  Errors: NOT_PD when A is not PD. */
+glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W, void* stream);
+
+/* One gradient pass (Sec. 3.1 eqs. grad_hessian, free_set, M; eq. G+):
+ * g = S - W, M = (A != 0) | (|g| > lambda), G = sign(A) where A != 0 else
+ * -sign(g); outputs Z = (g + lambda G) (.) M (n x n, full symmetric) and
+ * GM = G (.) M (n x n int8).  kkt (host, 4 doubles, may be NULL) receives
+ * ||Z||_1, ||A||_1, ||Z||_F, max|Z|.  S, W, A are read through their lower triangles. */
+glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* W, const double* A,
+                                int64_t n, double lambda, double* Z, int8_t* GM, double* kkt,
+                                void* stream);
+
+/* Preconditioned product P = A Z A (eq. b's first two terms:
+ * A(g.M)A + lambda A(G.M)A = A Z A), lower triangle exact, full symmetric output.
+ * precision selects the FP64, FP32 or BF16x3 product. */
+glasso_err glasso_precond_product(glasso_handle h, const double* A, const double* Z, int64_t n,
+                                  int precision, double* P, void* stream);
+
+/* Trial point of the line search (eqs. c, b, d_sol; masked update of Alg. 1):
+ * C_ij = lambda (A_ii A_jj + A_ij^2) (i != j), lambda A_ii^2 (i = j);
+ * B = P - C (.) GM;  At = M (.) SoftThreshold(A - t B, t C), M = (GM != 0).
+ * sums (host, 2 doubles, may be NULL) receive sum S (.) (At - A) and
+ * sum (|At| - |A|).  At is n x n full symmetric. */
+glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P, const double* S,
+                              const int8_t* GM, int64_t n, double lambda, double t, double* At,
+                              double* sums, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLASSO_H */

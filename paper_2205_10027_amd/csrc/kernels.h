@@ -1,0 +1,89 @@
+// Host-side launchers of the gfx950 kernels (internal to libglasso).
+// All matrices are row-major with leading dimensions in elements; every launcher
+// enqueues work on `stream` and returns 0 on success, -1 on a shape error and -2
+// when the launch itself failed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace glasso {
+
+// ---------------------------------------------------------------- dense kernels
+int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
+             const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+             int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag,
+             int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+
+// In-place lower Cholesky of the n x n (n multiple of 128) matrix A.  Writes the
+// diagonal of L to dL, the inverses of its 128x128 diagonal blocks to Dinv
+// (n/128 blocks of 128x128, zeros above the diagonal) and, on a non-positive or
+// non-finite pivot, info = global column + 1 (later kernels then skip).
+int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv,
+                int* info);
+
+// In-place inverse of the lower-triangular n x n factor L given its diagonal-block
+// inverses (from potrf_lower).  tmp needs n*n/4 doubles.
+int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* Dinv, double* tmp,
+                const int* abort_flag);
+
+// W (lower triangle) = V^T V for lower-triangular V (the LAUUM product).
+int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int64_t ldw, int n);
+
+// ---------------------------------------------------------------- elementwise passes
+int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst, int64_t np,
+                   int64_t* bad_count_dev, double lam, int check);
+int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A,
+              double* L);
+int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst,
+                 double* dst2, int pad_diag);
+int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, int8_t* dst);
+int unpad_copy_i8(hipStream_t stream, const int8_t* src, int64_t np, int8_t* dst, int64_t n);
+int sum_log(hipStream_t stream, const double* d, int64_t n, double* out);
+// nlog: number of diagonal entries of the factor that enter log det (n in the solver)
+int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A,
+              const double* dL, int64_t n, int64_t nlog, int64_t np, double lam, double* Z,
+              int8_t* GM, double* part, double* scal);
+int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S,
+               const int8_t* GM, int64_t n, int64_t np, double lam, double t, double* At,
+               double* Lt, double* part, int* info_reset);
+int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL,
+                 const double* dLt, const int* info, int64_t n, double lam, double* scal);
+int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
+                 int mode);
+int mirror_lower(hipStream_t stream, double* M, int64_t np);
+int power_iteration(hipStream_t stream, const double* M, int64_t n, int64_t np, double* vec,
+                    double* out, int iters);
+
+// device scalar slots written by the passes
+enum ScalarSlot {
+  SC_SUM_ABS_Z = 0,
+  SC_SUM_Z2,
+  SC_MAX_ABS_Z,
+  SC_SUM_ABS_A,
+  SC_NNZ_A,
+  SC_SUM_SA,
+  SC_LOGDET,
+  SC_OBJECTIVE,
+  SC_KKT_REL1,
+  SC_KKT_FRO,
+  SC_DF,
+  SC_DTR,
+  SC_DL1,
+  SC_DLOG,
+  SC_TRIAL_INFO,
+  SC_NNZ_AT,
+  SC_POWER_A,
+  SC_POWER_W,
+  SC_COUNT = 24
+};
+
+constexpr int GRAD_PARTS = 6;   // per-workgroup partials of pass_grad
+constexpr int TRIAL_PARTS = 3;  // per-workgroup partials of pass_trial
+
+inline int64_t pass_tiles(int64_t np) {
+  const int64_t T = np / 64;
+  return T * (T + 1) / 2;
+}
+
+}  // namespace glasso

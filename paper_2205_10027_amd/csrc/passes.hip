@@ -1,0 +1,540 @@
+// HBM-bound elementwise passes of pISTA (FP64, gfx950) and their deterministic
+// reductions.
+//
+// pass_grad  (Sec. 3.1, eqs. grad_hessian, free_set, M, G+; stopping rule of Sec. 5):
+//   g = S - W, M = (A != 0) | (|g| > lam), G = sign(A) or -sign(g),
+//   Z = (g + lam G) (.) M  -- the minimum-norm subgradient, the input of A Z A,
+//   GM = G (.) M as int8 (both full symmetric), and sums for ||Z||_1, ||Z||_F, max|Z|, ||A||_1, nnz(A),
+//   tr(SA); a one-workgroup kernel then forms KKT = ||Z||_1/||A||_1 and F(A).
+// pass_trial (eqs. c, b, d_sol; Alg. 1 masked update):
+//   C_ij = lam (A_ii A_jj + A_ij^2) (i != j), lam A_ii^2 (i = j);
+//   B = P - C (.) GM with P = A Z A;  At = M (.) ST(A - tB, tC);
+//   sums of S (.) (At - A) and |At| - |A| for the difference-form decrease.
+//
+// Both passes visit only the tiles on or below the diagonal (64x64 tiles of the
+// padded matrix), read lower triangles, and write symmetric outputs through an
+// LDS transpose.  Off-diagonal elements carry weight 2 in every sum.
+// Floating-point contraction is disabled so each element is computed with the
+// same sequence of IEEE operations as the plain formulas.
+#pragma clang fp contract(off)
+
+#include <float.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace glasso {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Sum (or max) over a 256-thread block in a fixed order; result valid in every thread.
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
+
+// ------------------------------------------------------------------ gradient pass
+__global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict__ S,
+                                                        const double* __restrict__ W,
+                                                        const double* __restrict__ A,
+                                                        const double* __restrict__ dL, int64_t n,
+                                                        int64_t np, double lam, double* __restrict__ Z,
+                                                        int8_t* __restrict__ GM, double* part, int T) {
+  __shared__ double zt[64][65];
+  __shared__ int8_t gt[64][68];
+  __shared__ double sh[4];
+  int ti, tj;
+  lower_tile(xcd_remap(blockIdx.x, gridDim.x), T, ti, tj);
+  const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
+  const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
+  const bool diag = (ti == tj);
+
+  double s_absz = 0.0, s_z2 = 0.0, m_absz = 0.0, s_absa = 0.0, s_nnz = 0.0, s_sa = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    const int64_t i = i0 + r, j = j0 + c;
+    const int64_t off = i * np + j;
+    double z = 0.0;
+    int8_t gm = 0;
+    if (!diag || c <= r) {
+      if (i < n && j < n) {
+        const double a = A[off], s = S[off], w = W[off];
+        const double g = s - w;
+        const bool nz = (a != 0.0);
+        const double G = nz ? sign_of(a) : -sign_of(g);
+        const bool M = nz || (fabs(g) > lam);
+        if (M) {
+          z = g + lam * G;
+          gm = (int8_t)G;
+        }
+        const double wgt = (i == j) ? 1.0 : 2.0;
+        s_absz += wgt * fabs(z);
+        s_z2 += wgt * (z * z);
+        m_absz = fmax(m_absz, fabs(z));
+        s_absa += wgt * fabs(a);
+        s_nnz += nz ? wgt : 0.0;
+        s_sa += wgt * (s * a);
+      }
+      Z[off] = z;
+      GM[off] = gm;
+    }
+    zt[r][c] = z;
+    gt[r][c] = gm;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    if (!diag) {
+      Z[(j0 + r) * np + i0 + c] = zt[c][r];
+      GM[(j0 + r) * np + i0 + c] = gt[c][r];
+    } else if (c > r) {
+      Z[(i0 + r) * np + j0 + c] = zt[c][r];
+      GM[(i0 + r) * np + j0 + c] = gt[c][r];
+    }
+  }
+
+  const double b0 = block_sum(s_absz, sh);
+  const double b1 = block_sum(s_z2, sh);
+  const double b2 = block_max(m_absz, sh);
+  const double b3 = block_sum(s_absa, sh);
+  const double b4 = block_sum(s_nnz, sh);
+  const double b5 = block_sum(s_sa, sh);
+  if (tid == 0) {
+    double* pp = part + (int64_t)blockIdx.x * GRAD_PARTS;
+    pp[0] = b0;
+    pp[1] = b1;
+    pp[2] = b2;
+    pp[3] = b3;
+    pp[4] = b4;
+    pp[5] = b5;
+  }
+}
+
+// fixed-order reduction of the gradient-pass partials, then KKT and F(A)
+__global__ __launch_bounds__(256) void finish_grad_kernel(const double* part, int nparts, const double* dL,
+                                                          int64_t nlog, double lam, double* scal) {
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
+  for (int b = tid; b < nparts; b += 256) {
+    const double* pp = part + (int64_t)b * GRAD_PARTS;
+    t0 += pp[0];
+    t1 += pp[1];
+    t2 = fmax(t2, pp[2]);
+    t3 += pp[3];
+    t4 += pp[4];
+    t5 += pp[5];
+  }
+  double tl = 0.0;
+  for (int64_t i = tid; i < nlog; i += 256) tl += log(dL[i]);
+  const double sz = block_sum(t0, sh);
+  const double sz2 = block_sum(t1, sh);
+  const double mz = block_max(t2, sh);
+  const double sa = block_sum(t3, sh);
+  const double nnz = block_sum(t4, sh);
+  const double ssa = block_sum(t5, sh);
+  const double ld = 2.0 * block_sum(tl, sh);
+  if (tid == 0) {
+    scal[SC_SUM_ABS_Z] = sz;
+    scal[SC_SUM_Z2] = sz2;
+    scal[SC_MAX_ABS_Z] = mz;
+    scal[SC_SUM_ABS_A] = sa;
+    scal[SC_NNZ_A] = nnz;
+    scal[SC_SUM_SA] = ssa;
+    scal[SC_LOGDET] = ld;
+    scal[SC_OBJECTIVE] = -ld + ssa + lam * sa;
+    scal[SC_KKT_REL1] = sz / sa;
+    scal[SC_KKT_FRO] = sqrt(sz2);
+  }
+}
+
+// ------------------------------------------------------------------ trial pass
+__global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restrict__ A,
+                                                         const double* __restrict__ P,
+                                                         const double* __restrict__ S,
+                                                         const int8_t* __restrict__ GM, int64_t n, int64_t np,
+                                                         double lam, double t, double* __restrict__ At,
+                                                         double* __restrict__ Lt, double* part, int* info_reset,
+                                                         int T) {
+  __shared__ double tt[64][65];
+  __shared__ double di[64], dj[64];
+  __shared__ double sh[4];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *info_reset = 0;
+  int ti, tj;
+  lower_tile(xcd_remap(blockIdx.x, gridDim.x), T, ti, tj);
+  const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
+  const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
+  const bool diag = (ti == tj);
+  if (tid < 64)
+    di[tid] = A[(i0 + tid) * (np + 1)];
+  else if (tid < 128)
+    dj[tid - 64] = A[(j0 + tid - 64) * (np + 1)];
+  __syncthreads();
+
+  double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    const int64_t i = i0 + r, j = j0 + c;
+    const int64_t off = i * np + j;
+    double at = 0.0;
+    if (!diag || c <= r) {
+      if (i < n && j < n) {
+        // off the free set A_ij = 0 and At_ij = 0: nothing else to read
+        const int8_t gm = GM[off];
+        if (gm != 0) {
+          const double a = A[off];
+          const double p = P[off];
+          const double Cij = (i == j) ? lam * (di[r] * di[r]) : lam * ((di[r] * dj[c]) + (a * a));
+          const double B = p - Cij * (double)gm;
+          const double x = a - t * B;
+          const double tau = t * Cij;
+          const double m = fmax(fabs(x) - tau, 0.0);
+          at = sign_of(x) * m;
+          const double s = S[off];
+          const double wgt = (i == j) ? 1.0 : 2.0;
+          s_tr += wgt * (s * (at - a));
+          s_l1 += wgt * (fabs(at) - fabs(a));
+          s_nnz += (at != 0.0) ? wgt : 0.0;
+        }
+      } else {
+        at = (i == j) ? 1.0 : 0.0;
+      }
+      At[off] = at;
+      Lt[off] = at;
+    }
+    tt[r][c] = at;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    if (!diag)
+      At[(j0 + r) * np + i0 + c] = tt[c][r];
+    else if (c > r)
+      At[(i0 + r) * np + j0 + c] = tt[c][r];
+  }
+  const double b0 = block_sum(s_tr, sh);
+  const double b1 = block_sum(s_l1, sh);
+  const double b2 = block_sum(s_nnz, sh);
+  if (tid == 0) {
+    double* pp = part + (int64_t)blockIdx.x * TRIAL_PARTS;
+    pp[0] = b0;
+    pp[1] = b1;
+    pp[2] = b2;
+  }
+}
+
+// After the trial's Cholesky: dF = 2 sum log(L_ii / Lt_ii) + sum S(At-A) + lam sum(|At|-|A|).
+__global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, int nparts, const double* dL,
+                                                           const double* dLt, const int* info, int64_t n,
+                                                           double lam, double* scal) {
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  const int inf = *info;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, tl = 0.0;
+  for (int b = tid; b < nparts; b += 256) {
+    t0 += part[(int64_t)b * TRIAL_PARTS + 0];
+    t1 += part[(int64_t)b * TRIAL_PARTS + 1];
+    t2 += part[(int64_t)b * TRIAL_PARTS + 2];
+  }
+  if (inf == 0)
+    for (int64_t i = tid; i < n; i += 256) tl += log(dL[i] / dLt[i]);
+  const double dtr = block_sum(t0, sh);
+  const double dl1 = block_sum(t1, sh);
+  const double nnz = block_sum(t2, sh);
+  const double dlog = 2.0 * block_sum(tl, sh);
+  if (tid == 0) {
+    scal[SC_DTR] = dtr;
+    scal[SC_DL1] = dl1;
+    scal[SC_DLOG] = dlog;
+    scal[SC_DF] = dlog + dtr + lam * dl1;
+    scal[SC_TRIAL_INFO] = (double)inf;
+    scal[SC_NNZ_AT] = nnz;
+  }
+}
+
+// ------------------------------------------------------------------ copies
+__global__ void copy_in_kernel(const double* __restrict__ src, int64_t n, double* __restrict__ dst, int64_t np,
+                               unsigned long long* bad, double lam, int check) {
+  const int64_t total = np * np;
+  unsigned long long nbad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    double v = 0.0;
+    if (i < n && j < n) {
+      v = src[i * n + j];
+      if (check && j <= i) {
+        if (!(fabs(v) <= DBL_MAX)) ++nbad;
+        if (i == j && !(v + lam > 0.0)) ++nbad;
+      }
+    }
+    dst[e] = v;
+  }
+  if (check && nbad) atomicAdd(bad, nbad);
+}
+
+__global__ void init_diag_kernel(const double* __restrict__ Sp, int64_t n, int64_t np, double lam,
+                                 double* __restrict__ A, double* __restrict__ L) {
+  const int64_t total = np * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    double v = 0.0;
+    if (i == j) v = (i < n) ? 1.0 / (Sp[i * np + i] + lam) : 1.0;
+    A[e] = v;
+    L[e] = v;
+  }
+}
+
+// dst (np x np) <- src (n x n, ld n); outside the n x n block: identity when
+// pad_diag, else zero.  dst2 (may be null) receives the same values.
+__global__ void pad_copy_f64_kernel(const double* __restrict__ src, int64_t n, int64_t np, double* __restrict__ dst,
+                                    double* __restrict__ dst2, int pad_diag) {
+  const int64_t total = np * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    double v;
+    if (i < n && j < n)
+      v = src[i * n + j];
+    else
+      v = (pad_diag && i == j) ? 1.0 : 0.0;
+    dst[e] = v;
+    if (dst2) dst2[e] = v;
+  }
+}
+
+__global__ void pad_copy_i8_kernel(const int8_t* __restrict__ src, int64_t n, int64_t np, int8_t* __restrict__ dst) {
+  const int64_t total = np * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    dst[e] = (i < n && j < n) ? src[i * n + j] : (int8_t)0;
+  }
+}
+
+__global__ void unpad_copy_i8_kernel(const int8_t* __restrict__ src, int64_t np, int8_t* __restrict__ dst, int64_t n) {
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e - i * n;
+    dst[e] = src[i * np + j];
+  }
+}
+
+// out = 2 sum_{i<n} log d_i
+__global__ __launch_bounds__(256) void sum_log_kernel(const double* d, int64_t n, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += log(d[i]);
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = 2.0 * t;
+}
+
+// dst (n x n, ld n) <- src (np x np).  mode 0: plain copy; mode 1: src holds only
+// its lower triangle and dst receives the symmetric matrix it stands for; mode 2:
+// lower triangle of src, zeros above.
+__global__ __launch_bounds__(256) void sym_copy_out_kernel(const double* __restrict__ src, int64_t np,
+                                                           double* __restrict__ dst, int64_t n, int mode,
+                                                           int Tn) {
+  __shared__ double tt[64][65];
+  const int bi = blockIdx.x / Tn, bj = blockIdx.x % Tn;
+  const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
+  const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
+  if (mode == 0 || bi > bj) {
+    for (int q = 0; q < 16; ++q) {
+      const int r = rw + 4 * q;
+      const int64_t i = i0 + r, j = j0 + c;
+      if (i < n && j < n) dst[i * n + j] = src[i * np + j];
+    }
+    return;
+  }
+  if (mode == 2) {
+    for (int q = 0; q < 16; ++q) {
+      const int r = rw + 4 * q;
+      const int64_t i = i0 + r, j = j0 + c;
+      if (i < n && j < n) dst[i * n + j] = (j <= i) ? src[i * np + j] : 0.0;
+    }
+    return;
+  }
+  // read the mirrored (lower) tile (bj, bi) and transpose it
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    const int64_t i = j0 + r, j = i0 + c;  // element of tile (bj, bi)
+    tt[r][c] = (i < np && j < np) ? src[i * np + j] : 0.0;
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    const int64_t i = i0 + r, j = j0 + c;
+    if (i < n && j < n) {
+      double v;
+      if (bi == bj)
+        v = (c <= r) ? tt[r][c] : tt[c][r];  // upper part of a diagonal tile mirrors (c, r)
+      else
+        v = tt[c][r];
+      dst[i * n + j] = v;
+    }
+  }
+}
+
+// make a padded matrix symmetric from its lower triangle, in place
+__global__ __launch_bounds__(256) void mirror_lower_kernel(double* M, int64_t np, int T) {
+  __shared__ double tt[64][65];
+  int ti, tj;
+  lower_tile(blockIdx.x, T, ti, tj);
+  const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
+  const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    tt[r][c] = M[(i0 + r) * np + j0 + c];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int r = rw + 4 * q;
+    if (ti != tj)
+      M[(j0 + r) * np + i0 + c] = tt[c][r];
+    else if (c > r)
+      M[(i0 + r) * np + j0 + c] = tt[c][r];
+  }
+}
+
+// y = M x, one wave per row
+__global__ __launch_bounds__(256) void gemv_kernel(const double* __restrict__ M, int64_t np,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= np) return;
+  const double* mr = M + row * np;
+  double s = 0.0;
+  for (int64_t j = lane; j < np; j += 64) s += mr[j] * x[j];
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
+// x = y / ||y|| over the first n entries (zeros beyond), out = ||y||
+__global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict__ y, double* __restrict__ x,
+                                                        int64_t n, int64_t np, double* out, int init) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  if (!init)
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += y[i] * y[i];
+  const double nrm = init ? sqrt((double)n) : sqrt(block_sum(s, sh));
+  for (int64_t i = threadIdx.x; i < np; i += 256) x[i] = (i < n) ? (init ? 1.0 : y[i]) / nrm : 0.0;
+  if (threadIdx.x == 0 && out) *out = nrm;
+}
+
+}  // namespace
+
+int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst, int64_t np,
+                   int64_t* bad_count_dev, double lam, int check) {
+  const int64_t total = np * np;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(copy_in_kernel, dim3(blocks), dim3(256), 0, stream, src, n, dst, np,
+                     reinterpret_cast<unsigned long long*>(bad_count_dev), lam, check);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A, double* L) {
+  const int64_t total = np * np;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(init_diag_kernel, dim3(blocks), dim3(256), 0, stream, Sp, n, np, lam, A, L);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+static int grid_for(int64_t total) { return (int)std::min<int64_t>((total + 255) / 256, 16384); }
+
+int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst, double* dst2,
+                 int pad_diag) {
+  hipLaunchKernelGGL(pad_copy_f64_kernel, dim3(grid_for(np * np)), dim3(256), 0, stream, src, n, np, dst, dst2,
+                     pad_diag);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, int8_t* dst) {
+  hipLaunchKernelGGL(pad_copy_i8_kernel, dim3(grid_for(np * np)), dim3(256), 0, stream, src, n, np, dst);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int unpad_copy_i8(hipStream_t stream, const int8_t* src, int64_t np, int8_t* dst, int64_t n) {
+  hipLaunchKernelGGL(unpad_copy_i8_kernel, dim3(grid_for(n * n)), dim3(256), 0, stream, src, np, dst, n);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int sum_log(hipStream_t stream, const double* d, int64_t n, double* out) {
+  hipLaunchKernelGGL(sum_log_kernel, dim3(1), dim3(256), 0, stream, d, n, out);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A, const double* dL, int64_t n,
+              int64_t nlog, int64_t np, double lam, double* Z, int8_t* GM, double* part, double* scal) {
+  const int T = (int)(np / 64);
+  const int tiles = T * (T + 1) / 2;
+  hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z, GM, part, T);
+  hipLaunchKernelGGL(finish_grad_kernel, dim3(1), dim3(256), 0, stream, part, tiles, dL, nlog, lam, scal);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S, const int8_t* GM, int64_t n,
+               int64_t np, double lam, double t, double* At, double* Lt, double* part, int* info_reset) {
+  const int T = (int)(np / 64);
+  const int tiles = T * (T + 1) / 2;
+  hipLaunchKernelGGL(pass_trial_kernel, dim3(tiles), dim3(256), 0, stream, A, P, S, GM, n, np, lam, t, At, Lt,
+                     part, info_reset, T);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL, const double* dLt,
+                 const int* info, int64_t n, double lam, double* scal) {
+  hipLaunchKernelGGL(finish_trial_kernel, dim3(1), dim3(256), 0, stream, part, nparts, dL, dLt, info, n, lam, scal);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n, int mode) {
+  const int Tn = (int)((n + 63) / 64);
+  hipLaunchKernelGGL(sym_copy_out_kernel, dim3(Tn * Tn), dim3(256), 0, stream, src, np, dst, n, mode, Tn);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int mirror_lower(hipStream_t stream, double* M, int64_t np) {
+  const int T = (int)(np / 64);
+  hipLaunchKernelGGL(mirror_lower_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, stream, M, np, T);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int power_iteration(hipStream_t stream, const double* M, int64_t n, int64_t np, double* vec, double* out, int iters) {
+  double* x = vec;
+  double* y = vec + np;
+  hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(256), 0, stream, y, x, n, np, (double*)nullptr, 1);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)((np + 3) / 4)), dim3(256), 0, stream, M, np, x, y);
+    hipLaunchKernelGGL(normalize_kernel, dim3(1), dim3(256), 0, stream, y, x, n, np, out, 0);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace glasso

@@ -1,0 +1,163 @@
+"""Step-level parity of the HIP kernels against the CPU oracle (through the C ABI).
+
+Tolerances:
+  * elementwise passes (gradient/sign/Z, trial point): identical IEEE operations
+    in both implementations -> bit-exact outputs for identical inputs;
+  * sums over n^2 terms: summation order differs -> relative 1e-12;
+  * A Z A: each entry is two length-n dot products; the textbook bound is
+    |fl(AZA) - AZA| <= 2 n eps (|A||Z||A|) (elementwise), checked with factor 2 slack;
+  * Cholesky: backward error |L L^T - A| <= 2 n eps |L||L^T| (factor 2 slack);
+  * inverse: |W - inv(A)| <= c n eps cond(A) |inv(A)|_max with c = 4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_util import EPS, device, random_spd, sparse_sym, sym, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 5, 64, 128, 130, 300, 513]
+
+
+@pytest.fixture(scope="module")
+def solver():
+    device()
+    import paper_2205_10027_amd as g
+
+    s = g.Solver()
+    yield s
+    s.close()
+
+
+# ------------------------------------------------------------------ A Z A (MFMA GEMMs)
+@pytest.mark.parametrize("n", SIZES + [1024])
+def test_precond_product_fp64(solver, n):
+    A = sparse_sym(n, 1, density=0.3)
+    rng = np.random.default_rng(2)
+    Z = sym(rng.standard_normal((n, n)))
+    P = to_host(solver.precond_product(to_dev(A), to_dev(Z)))
+    ref = A @ Z @ A
+    bound = 4 * n * EPS * (np.abs(A) @ np.abs(Z) @ np.abs(A)) + 1e-300
+    assert np.all(np.abs(P - ref) <= bound), np.max(np.abs(P - ref) / bound)
+    assert np.array_equal(P, P.T)
+
+
+def test_precond_product_structure(solver):
+    """Identity and permutation cases pin the MFMA lane layout exactly."""
+    n = 256
+    rng = np.random.default_rng(3)
+    Z = sym(rng.integers(-3, 4, size=(n, n)).astype(np.float64))
+    P = to_host(solver.precond_product(to_dev(np.eye(n)), to_dev(Z)))
+    assert np.array_equal(P, Z)
+    perm = rng.permutation(n)
+    Pm = np.eye(n)[perm]
+    Pm = sym(Pm + Pm.T)  # symmetric 0/1/2 matrix
+    P = to_host(solver.precond_product(to_dev(Pm), to_dev(Z)))
+    assert np.array_equal(P, Pm @ Z @ Pm)  # small integers: exact
+
+
+# ------------------------------------------------------------------ Cholesky / inverse
+@pytest.mark.parametrize("n", SIZES + [1100, 2100])
+def test_cholesky(solver, n):
+    A = random_spd(n, n)
+    L, info, logdet = solver.cholesky(to_dev(A))
+    L = to_host(L)
+    assert info == 0
+    assert np.all(np.triu(L, 1) == 0)
+    back = np.abs(L @ L.T - A)
+    bound = 4 * n * EPS * (np.abs(L) @ np.abs(L.T)) + 1e-300
+    assert np.all(back <= bound), np.max(back / bound)
+    sign, ld = np.linalg.slogdet(A)
+    assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
+
+
+@pytest.mark.parametrize("n,bad", [(5, 3), (300, 200), (1100, 1030), (130, 129)])
+def test_cholesky_reports_first_bad_pivot(solver, n, bad):
+    A = np.eye(n)
+    A[bad - 1, bad - 1] = -1.0
+    _, info, _ = solver.cholesky(to_dev(A))
+    assert info == bad
+    A = random_spd(n, 7)
+    A[bad - 1, bad - 1] = np.nan
+    _, info, _ = solver.cholesky(to_dev(A))
+    assert info == bad
+
+
+@pytest.mark.parametrize("n", SIZES + [1100])
+def test_inverse(solver, n):
+    A = random_spd(n, n + 11)
+    W = to_host(solver.inverse(to_dev(A)))
+    ref = np.linalg.inv(A)
+    cond = np.linalg.cond(A)
+    assert np.array_equal(W, W.T)
+    assert np.max(np.abs(W - ref)) <= 4 * n * EPS * cond * np.max(np.abs(ref))
+
+
+def test_inverse_not_pd(solver):
+    import paper_2205_10027_amd as g
+
+    A = -np.eye(10)
+    with pytest.raises(g.GlassoError) as e:
+        solver.inverse(to_dev(A))
+    assert e.value.code == 2
+
+
+# ------------------------------------------------------------------ gradient pass
+def _grad_inputs(n, seed, lam):
+    rng = np.random.default_rng(seed)
+    A = sparse_sym(n, seed, density=0.2)
+    S = sym(rng.standard_normal((n, n)) * 0.5)
+    W = sym(rng.standard_normal((n, n)) * 0.5)
+    # plant exact ties |g| = lam and g = 0 off the support
+    if n >= 4:
+        S[2, 0] = S[0, 2] = W[2, 0] + lam
+        S[3, 1] = S[1, 3] = W[3, 1]
+        A[2, 0] = A[0, 2] = 0.0
+        A[3, 1] = A[1, 3] = 0.0
+    return S, W, A
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_gradient_pass_bit_exact(solver, n):
+    lam = 0.3
+    S, W, A = _grad_inputs(n, n, lam)
+    Z, GM, k = solver.gradient_pass(to_dev(S), to_dev(W), to_dev(A), lam)
+    Z, GM = to_host(Z), to_host(GM)
+    g = oracle.gradient(S, W)
+    M = oracle.free_set_mask(A, g, lam)
+    G = oracle.sign_guess(A, g)
+    Zr = oracle.min_norm_subgradient(g, G, M, lam)
+    assert np.array_equal(Z, Zr)
+    assert np.array_equal(GM.astype(np.float64), np.where(M, G, 0.0))
+    km = oracle.kkt_measures(Zr, A)
+    assert abs(k["sum_abs_z"] - km["sum_abs_z"]) <= 1e-12 * km["sum_abs_z"]
+    assert abs(k["sum_abs_a"] - km["sum_abs_a"]) <= 1e-12 * km["sum_abs_a"]
+    assert abs(k["kkt_fro"] - km["kkt_fro"]) <= 1e-12 * km["kkt_fro"]
+    assert k["kkt_max"] == km["kkt_max"]
+
+
+# ------------------------------------------------------------------ trial point
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("t", [1.0, 0.25, 1e-3])
+def test_trial_point_bit_exact(solver, n, t):
+    lam = 0.2
+    rng = np.random.default_rng(n + 5)
+    A = sparse_sym(n, n + 3, density=0.2)
+    g = sym(rng.standard_normal((n, n)) * 0.4)
+    P = sym(rng.standard_normal((n, n)))
+    S = sym(rng.standard_normal((n, n)))
+    M = oracle.free_set_mask(A, g, lam)
+    G = oracle.sign_guess(A, g)
+    GM = np.where(M, G, 0.0).astype(np.int8)
+    At, sums = solver.trial_point(to_dev(A), to_dev(P), to_dev(S), to_dev(GM, torch.int8), lam, t)
+    At = to_host(At)
+    C = oracle.c_matrix(A, lam)
+    B = oracle.b_from_products(P, C, G, M)
+    ref = oracle.trial_point(A, M, B, C, t)
+    assert np.array_equal(At, ref)
+    dtr = float(np.sum(S * (ref - A)))
+    dl1 = float(np.sum(np.abs(ref) - np.abs(A)))
+    assert abs(sums["dtr"] - dtr) <= 1e-12 * max(1.0, np.sum(np.abs(S * (ref - A))))
+    assert abs(sums["dl1"] - dl1) <= 1e-12 * max(1.0, np.sum(np.abs(ref)) + np.sum(np.abs(A)))
