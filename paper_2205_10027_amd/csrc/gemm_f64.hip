@@ -136,7 +136,9 @@ __device__ __forceinline__ void store_slice(double (*S)[LDK], int tid, const dou
   }
 }
 
-template <int TA, int TB>
+// ROLE only separates instantiations in profiles: 0 = factorisation/inverse
+// updates, 1 = the preconditioned product A Z A.
+template <int TA, int TB, int ROLE>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
   if (p.abort_flag && *p.abort_flag) return;
 
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
 int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag, int batch,
-             int64_t sA, int64_t sB, int64_t sC) {
+             int64_t sA, int64_t sB, int64_t sC, int role) {
   if (M <= 0 || N <= 0 || batch <= 0) return 0;
   if (M % BM || N % BN || K % BK || K < 0) return -1;
   if (lower_out && M != N) return -1;
@@ -260,14 +262,16 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
   p.abort_flag = abort_flag;
   const int tiles = lower_out ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
   dim3 grid(tiles, batch), block(256);
-  if (ta == 0 && tb == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<0, 0>), grid, block, 0, stream, p);
+  if (role == 1 && ta == 0 && tb == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 1>), grid, block, 0, stream, p);
+  else if (ta == 0 && tb == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 0>), grid, block, 0, stream, p);
   else if (ta == 0 && tb == 1)
-    hipLaunchKernelGGL((gemm_f64_kernel<0, 1>), grid, block, 0, stream, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 1, 0>), grid, block, 0, stream, p);
   else if (ta == 1 && tb == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<1, 0>), grid, block, 0, stream, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<1, 0, 0>), grid, block, 0, stream, p);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<1, 1>), grid, block, 0, stream, p);
+    hipLaunchKernelGGL((gemm_f64_kernel<1, 1, 0>), grid, block, 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -171,8 +171,8 @@ glasso_err inverse_from_factor(Workspace& w, hipStream_t st) {
 glasso_err precond_product(Workspace& w, hipStream_t st, int precision) {
   const int np = (int)w.np;
   if (precision != GLASSO_FP64) return GLASSO_ERR_INVALID_ARG;
-  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, nullptr));
-  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, nullptr));
+  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, nullptr, 1, 0, 0, 0, 1));
+  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, nullptr, 1, 0, 0, 0, 1));
   return GLASSO_OK;
 }
 

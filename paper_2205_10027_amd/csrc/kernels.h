@@ -13,7 +13,7 @@ namespace glasso {
 int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag,
-             int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+             int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0, int role = 0);
 
 // In-place lower Cholesky of the n x n (n multiple of 128) matrix A.  Writes the
 // diagonal of L to dL, the inverses of its 128x128 diagonal blocks to Dinv
