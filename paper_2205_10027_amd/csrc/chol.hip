@@ -19,71 +19,179 @@ constexpr int NB = 128;        // leaf block (= GEMM tile)
 constexpr int LDL = NB + 1;    // LDS row stride of the leaf
 constexpr int OUTER = 1024;    // outer panel width of the two-level Cholesky
 
+constexpr int PW = 32;  // panel width inside the leaf
+
+// broadcast a double from a wave-uniform lane
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// ---- in-LDS inverse of a lower-triangular 128x128 block (upper triangle = scratch)
+//
+// Stage 1: wave w inverts the 32x32 diagonal block w (lane c computes column c by
+// forward substitution).  Stage 2 doubles the inverted block size: for each group
+// [T11 0; T21 T22] of size 2S with T11, T22 already inverted,
+//   tmp = T21 inv(T11)  (stored transposed in the free upper triangle),
+//   X21 = -inv(T22) tmp (written over T21),
+// as register-tiled products, one TR x TC output tile per thread.
+template <int S, int TR, int TC>
+__device__ __forceinline__ void trtri_level(double (*a)[LDL], int tid) {
+  constexpr int TPG = (S / TR) * (S / TC);  // tiles per group
+  const int g = tid / TPG, t = tid % TPG;
+  const int o = g * 2 * S;
+  const int r0 = (t / (S / TC)) * TR, c0 = (t % (S / TC)) * TC;
+  double acc[TR][TC];
+#pragma unroll
+  for (int u = 0; u < TR; ++u)
+#pragma unroll
+    for (int v = 0; v < TC; ++v) acc[u][v] = 0.0;
+  // tmp[r][c] = sum_{k >= c} T21[r][k] inv(T11)[k][c]   (k < c terms are masked)
+#pragma unroll 4
+  for (int k = c0; k < S; ++k) {
+    double x[TR], y[TC];
+#pragma unroll
+    for (int u = 0; u < TR; ++u) x[u] = a[o + S + r0 + u][o + k];
+#pragma unroll
+    for (int v = 0; v < TC; ++v) {
+      const double b = a[o + k][o + c0 + v];
+      y[v] = (k >= c0 + v) ? b : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+      for (int v = 0; v < TC; ++v) acc[u][v] += x[u] * y[v];
+  }
+#pragma unroll
+  for (int u = 0; u < TR; ++u)
+#pragma unroll
+    for (int v = 0; v < TC; ++v) a[o + c0 + v][o + S + r0 + u] = acc[u][v];
+  __syncthreads();
+  // X21[r][c] = -sum_{k <= r} inv(T22)[r][k] tmp[k][c]   (k > r terms are masked)
+#pragma unroll
+  for (int u = 0; u < TR; ++u)
+#pragma unroll
+    for (int v = 0; v < TC; ++v) acc[u][v] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < r0 + TR; ++k) {
+    double x[TR], y[TC];
+#pragma unroll
+    for (int u = 0; u < TR; ++u) {
+      const double b = a[o + S + r0 + u][o + S + k];
+      x[u] = (k <= r0 + u) ? b : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < TC; ++v) y[v] = a[o + c0 + v][o + S + k];
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+      for (int v = 0; v < TC; ++v) acc[u][v] += x[u] * y[v];
+  }
+#pragma unroll
+  for (int u = 0; u < TR; ++u)
+#pragma unroll
+    for (int v = 0; v < TC; ++v) a[o + S + r0 + u][o + c0 + v] = -acc[u][v];
+  __syncthreads();
+}
+
+__device__ void lds_trtri128(double (*a)[LDL], int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane < PW) {
+    const int o = PW * wave;
+    double x[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      double s = (i == lane) ? 1.0 : 0.0;
+      // Row i's loads may not start before x[i-2] exists: without this ordering the
+      // compiler hoists all 528 loads of the block and spills.
+      int rb = (o + i) * LDL + o;
+      if (i >= 2) asm volatile("" : "+v"(rb) : "v"(x[i - 2]));
+      const double* arow = &a[0][0] + rb;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= arow[k] * x[k];
+      x[i] = s / arow[i];
+    }
+    // x[i] = 0 for i < lane: only the lower part of column `lane` is written
+#pragma unroll
+    for (int i = 0; i < PW; ++i)
+      if (i >= lane) a[o + i][o + lane] = x[i];
+  }
+  __syncthreads();
+  trtri_level<32, 2, 4>(a, tid);
+  trtri_level<64, 4, 4>(a, tid);
+}
+
 // Factor the 128x128 diagonal block at A (lower, in place), write diag(L) to dL and
 // inv(L) (zeros above the diagonal) to Dinv (ld 128).  k0 is the block's global
 // column, used to report the first failing pivot through info.
+//
+// Four panels of 32 columns.  For a panel starting at c0, every wave holds the
+// 32x32 diagonal block in lanes 0..31 (row c0+lane, one register per column) and
+// factors it redundantly: the pivot comes from readlane, the multipliers of the
+// block rows are broadcast through the wave's own LDS row.  Lanes 32..63 of the
+// waves hold the rows below the block and are eliminated in the same steps (the
+// triangular solve of the panel).  All 4 waves then apply the rank-32 update to
+// the trailing lower triangle.  Elements above the diagonal carry garbage and are
+// never read as data.
 __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t lda, int k0,
                                                              double* dL, double* Dinv, int* info) {
   if (*info) return;
   __shared__ double a[NB][LDL];
-  __shared__ double col[NB];
-  __shared__ double piv;
-  const int tid = threadIdx.x;
+  __shared__ double mb[4][PW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  for (int e = tid; e < NB * NB; e += 256) {
+  // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 512; ++i) {
+    const int e = 2 * (tid + 256 * i);
     const int r = e >> 7, c = e & 127;
-    a[r][c] = (c <= r) ? A[(int64_t)r * lda + c] : 0.0;
+    const double2 x = *reinterpret_cast<const double2*>(A + (int64_t)r * lda + c);
+    a[r][c] = (c <= r) ? x.x : 0.0;
+    a[r][c + 1] = (c + 1 <= r) ? x.y : 0.0;
   }
   __syncthreads();
 
-  // ---- factorisation: 4 panels of 32 columns.  Thread (pr, ph) keeps row pr,
-  // columns c0+16ph .. c0+16ph+15 of the current panel in registers.
-  const int pr = tid >> 1, ph = tid & 1;
-  int fail = -1;
+  int fail = -1;  // identical in every wave: all waves factor the same block
 #pragma unroll 1
-  for (int p = 0; p < 4; ++p) {
-    const int c0 = 32 * p;
-    double v[16];
+  for (int p = 0; p < NB / PW; ++p) {
+    const int c0 = PW * p;
+    const int row = (lane < PW) ? c0 + lane : c0 + PW + wave * PW + (lane - PW);
+    const bool valid = row < NB;
+    double v[PW];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = a[pr][c0 + 16 * ph + q];
+    for (int q = 0; q < PW; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
 #pragma unroll
-    for (int jl = 0; jl < 32; ++jl) {
-      const int j = c0 + jl;
-      if (fail < 0) {  // uniform: every thread reads the same pivot
-        if (pr == j && ph == (jl >> 4)) {
-          const double d = v[jl & 15];
-          const double s = (d > 0.0 && d <= DBL_MAX) ? sqrt(d) : -1.0;
-          v[jl & 15] = s;
-          piv = s;
-        }
-        __syncthreads();
-        const double ljj = piv;
-        if (!(ljj > 0.0)) {
-          fail = j;
-        } else {
-          const double rinv = 1.0 / ljj;
-          if (pr > j && ph == (jl >> 4)) {
-            v[jl & 15] *= rinv;
-            col[pr] = v[jl & 15];
-          }
-          __syncthreads();
-          if (pr > j) {
-            const double lr = col[pr];
+    for (int j = 0; j < PW; ++j) {
+      const double piv = lane_bcast(v[j], j);
+      const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
+      if (!ok && fail < 0) fail = c0 + j;
+      const double r = rsqrt(ok ? piv : 1.0);
+      const double m = v[j] * r;  // lane j: sqrt(piv); rows below: multipliers
+      v[j] = m;
+      if (lane < PW) mb[wave][lane] = m;
+      __builtin_amdgcn_wave_barrier();
+      // next pivot column first, from a register broadcast (off the LDS round trip)
+      if (j + 1 < PW) {
+        v[j + 1] -= m * lane_bcast(m, j + 1);
+        asm volatile("" : "+v"(v[j + 1]));
+      }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-              const int c = c0 + 16 * ph + q;
-              if (c > j && c <= pr) v[q] -= lr * col[c];
-            }
-          }
-        }
+      for (int c = j + 2; c < PW; ++c) {
+        v[c] -= m * mb[wave][c];
+        // materialise the update now: left to itself the compiler defers these
+        // FMAs and keeps every step's broadcast multipliers live (spills)
+        asm volatile("" : "+v"(v[c]));
       }
     }
     if (fail >= 0) break;
+    if (valid && (lane >= PW || wave == 0)) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) a[pr][c0 + 16 * ph + q] = v[q];
+      for (int q = 0; q < PW; ++q) a[row][c0 + q] = v[q];
+    }
     __syncthreads();
     // rank-32 update of the trailing lower triangle, 4x4 register blocks
-    const int base = c0 + 32, R = NB - base;
+    const int base = c0 + PW, R = NB - base;
     if (R > 0) {
       const int nb4 = R / 4;
       const int nblk = nb4 * (nb4 + 1) / 2;
@@ -98,8 +206,8 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
-#pragma unroll 2
-        for (int k = c0; k < c0 + 32; ++k) {
+#pragma unroll 8
+        for (int k = c0; k < c0 + PW; ++k) {
           double x[4], y[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
@@ -114,8 +222,7 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int w = 0; w < 4; ++w)
-            if (s0 + w <= r0 + u) a[r0 + u][s0 + w] -= acc[u][w];
+          for (int w = 0; w < 4; ++w) a[r0 + u][s0 + w] -= acc[u][w];
       }
       __syncthreads();
     }
@@ -125,30 +232,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
     return;
   }
 
-  for (int e = tid; e < NB * NB; e += 256) {
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i;
     const int r = e >> 7, c = e & 127;
     if (c <= r) A[(int64_t)r * lda + c] = a[r][c];
   }
   if (tid < NB) dL[tid] = a[tid][tid];
-
-  // ---- in-place inverse of the lower-triangular block, last column first:
-  // column j of inv(L) = -(1/L_jj) * inv(L)[j+1:, j+1:] * L[j+1:, j].
-  for (int j = NB - 1; j >= 0; --j) {
-    if (tid < NB && tid > j) col[tid] = a[tid][j];
-    __syncthreads();
-    const double dinv = 1.0 / a[j][j];
-    const int i = j + 1 + (tid >> 1);
-    double s = 0.0;
-    if (i < NB) {
-      for (int k = j + 1 + (tid & 1); k <= i; k += 2) s += a[i][k] * col[k];
-    }
-    s += __shfl_xor(s, 1);
-    __syncthreads();
-    if (i < NB && (tid & 1) == 0) a[i][j] = -dinv * s;
-    if (tid == 0) a[j][j] = dinv;
-  }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
+  lds_trtri128(a, tid);
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i;
     const int r = e >> 7, c = e & 127;
     Dinv[e] = (c <= r) ? a[r][c] : 0.0;
   }

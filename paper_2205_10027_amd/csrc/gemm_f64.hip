@@ -62,19 +62,16 @@ __device__ __forceinline__ void load_a(const GemmF64Params& p, const double* A, 
       }
     }
   } else {
-    const int kr = tid >> 4, mq = (tid & 15) * 8;
-    const double2* src = reinterpret_cast<const double2*>(A + (int64_t)(kt + kr) * p.lda + m0 + mq);
+    // one LDS row (= one m) per thread: coalesced 8-byte loads along m, 16-byte LDS stores
+    const int mc = tid & 127, kh = (tid >> 7) * 8;
+    const double* src = A + (int64_t)(kt + kh) * p.lda + m0 + mc;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = src[i];
-      r[2 * i] = v.x;
-      r[2 * i + 1] = v.y;
-    }
+    for (int i = 0; i < 8; ++i) r[i] = src[(int64_t)i * p.lda];
     if (p.a_tri) {
-      const int k = kt + kr;
+      const int m = m0 + mc;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int m = m0 + mq + i;
+        const int k = kt + kh + i;
         if ((p.a_tri == 1 && k > m) || (p.a_tri == 2 && k < m)) r[i] = 0.0;
       }
     }
@@ -102,19 +99,15 @@ __device__ __forceinline__ void load_b(const GemmF64Params& p, const double* B, 
       }
     }
   } else {
-    const int kr = tid >> 4, nq = (tid & 15) * 8;
-    const double2* src = reinterpret_cast<const double2*>(B + (int64_t)(kt + kr) * p.ldb + n0 + nq);
+    const int nc = tid & 127, kh = (tid >> 7) * 8;
+    const double* src = B + (int64_t)(kt + kh) * p.ldb + n0 + nc;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = src[i];
-      r[2 * i] = v.x;
-      r[2 * i + 1] = v.y;
-    }
+    for (int i = 0; i < 8; ++i) r[i] = src[(int64_t)i * p.ldb];
     if (p.b_tri) {
-      const int k = kt + kr;
+      const int n = n0 + nc;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int n = n0 + nq + i;
+        const int k = kt + kh + i;
         if ((p.b_tri == 1 && k < n) || (p.b_tri == 2 && k > n)) r[i] = 0.0;
       }
     }
@@ -130,9 +123,10 @@ __device__ __forceinline__ void store_slice(double (*S)[LDK], int tid, const dou
 #pragma unroll
     for (int i = 0; i < 4; ++i) dst[i] = make_double2(r[2 * i], r[2 * i + 1]);
   } else {
-    const int kr = tid >> 4, mq = (tid & 15) * 8;
+    const int mc = tid & 127, kh = (tid >> 7) * 8;
+    double2* dst = reinterpret_cast<double2*>(&S[mc][kh]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) S[mq + i][kr] = r[i];
+    for (int i = 0; i < 4; ++i) dst[i] = make_double2(r[2 * i], r[2 * i + 1]);
   }
 }
 
@@ -149,7 +143,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  // Contiguous tile ranges per XCD share operand panels in L2, but when the K
+  // range depends on the tile (triangular operands) they would also give one XCD
+  // all the long tiles; those launches keep the hardware's round-robin order.
+  const int L = (p.a_tri || p.b_tri) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   if (p.lower_out)
     lower_tile(L, p.tiles_m, ti, tj);

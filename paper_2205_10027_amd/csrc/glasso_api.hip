@@ -133,7 +133,7 @@ glasso_err fetch(glasso_handle h, hipStream_t st) {
 int host_flag(glasso_handle h, int i) { return reinterpret_cast<int*>(h->host + SC_COUNT)[i]; }
 
 glasso_err check_options(const glasso_options* o) {
-  if (o->precision < GLASSO_FP64 || o->precision > GLASSO_MIXED_BF16X3) return GLASSO_ERR_INVALID_ARG;
+  if (o->precision != GLASSO_FP64 && o->precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
   if (o->max_iter < 0) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
@@ -167,13 +167,28 @@ glasso_err inverse_from_factor(Workspace& w, hipStream_t st) {
   return GLASSO_OK;
 }
 
-// P (lower) = A Z A: X = A Z^T (Z symmetric), P = tril(X A^T) (A symmetric)
+// P (lower) = A Z A: X = A Z^T (Z symmetric), P = tril(X A^T) (A symmetric).
+// Mixed FP32: A and Z are rounded to FP32 (A32, Z32 in the X buffer), X32 = A32 Z32^T
+// overwrites Z (no longer needed), P = tril(X32 A32^T) is written in FP64.
 glasso_err precond_product(Workspace& w, hipStream_t st, int precision) {
   const int np = (int)w.np;
-  if (precision != GLASSO_FP64) return GLASSO_ERR_INVALID_ARG;
-  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, nullptr, 1, 0, 0, 0, 1));
-  K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, nullptr, 1, 0, 0, 0, 1));
-  return GLASSO_OK;
+  if (precision == GLASSO_FP64) {
+    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, nullptr, 1, 0, 0, 0, 1));
+    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, nullptr, 1, 0, 0, 0, 1));
+    return GLASSO_OK;
+  }
+  if (precision == GLASSO_MIXED_FP32) {
+    const int64_t nn = (int64_t)np * np;
+    float* A32 = reinterpret_cast<float*>(w.X);
+    float* Z32 = A32 + nn;
+    float* X32 = reinterpret_cast<float*>(w.Z);
+    K_TRY(f64_to_f32(st, w.A, A32, nn));
+    K_TRY(f64_to_f32(st, w.Z, Z32, nn));
+    K_TRY(gemm_f32_nt(st, np, np, np, A32, np, Z32, np, X32, np, 0, 0));
+    K_TRY(gemm_f32_nt(st, np, np, np, X32, np, A32, np, w.P, np, 1, 1));
+    return GLASSO_OK;
+  }
+  return GLASSO_ERR_INVALID_ARG;
 }
 
 // cond(A) ~ lambda_max(A) * lambda_max(A^{-1}) by power iteration; t = (0.9/cond)^2.
@@ -464,7 +479,7 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
 glasso_err glasso_precond_product(glasso_handle h, const double* A, const double* Z, int64_t n, int precision,
                                   double* P, void* stream) {
   if (!h || !A || !Z || !P || n < 1) return GLASSO_ERR_INVALID_ARG;
-  if (precision != GLASSO_FP64) return GLASSO_ERR_INVALID_ARG;
+  if (precision != GLASSO_FP64 && precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, np);

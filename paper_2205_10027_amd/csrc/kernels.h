@@ -15,6 +15,13 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag,
              int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0, int role = 0);
 
+// C = A B^T on FP32 MFMA with FP32 accumulation (A: M x K, B: N x K, row-major
+// FP32); C is float or (c_is_double) double; lower_out as in gemm_f64.
+int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda,
+                const float* B, int64_t ldb, void* C, int64_t ldc, int c_is_double,
+                int lower_out);
+int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
+
 // In-place lower Cholesky of the n x n (n multiple of 128) matrix A.  Writes the
 // diagonal of L to dL, the inverses of its 128x128 diagonal blocks to Dinv
 // (n/128 blocks of 128x128, zeros above the diagonal) and, on a non-positive or

@@ -44,6 +44,23 @@ def test_precond_product_fp64(solver, n):
     assert np.array_equal(P, P.T)
 
 
+@pytest.mark.parametrize("n", [5, 128, 300, 1024])
+def test_precond_product_fp32(solver, n):
+    """FP32 MFMA product: inputs rounded to FP32 (relative 2^-24) and FP32
+    accumulation over two length-n dot products -> 4 n u32 (|A||Z||A|)."""
+    A = sparse_sym(n, 1, density=0.3)
+    rng = np.random.default_rng(2)
+    Z = sym(rng.standard_normal((n, n)))
+    P = to_host(solver.precond_product(to_dev(A), to_dev(Z), precision="fp32"))
+    ref = A @ Z @ A
+    u32 = 2.0 ** -24
+    bound = 4 * (n + 2) * u32 * (np.abs(A) @ np.abs(Z) @ np.abs(A)) + 1e-300
+    assert np.all(np.abs(P - ref) <= bound), np.max(np.abs(P - ref) / bound)
+    assert np.array_equal(P, P.T)
+    # and it is not secretly the FP64 product
+    assert np.max(np.abs(P - ref)) > 0
+
+
 def test_precond_product_structure(solver):
     """Identity and permutation cases pin the MFMA lane layout exactly."""
     n = 256

@@ -66,6 +66,21 @@ def test_random_sparse(g, n, seed, frac):
     check_against_oracle(g, S, lam, 1e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("n,seed,frac", [(130, 1, 0.25), (300, 2, 0.2)])
+def test_mixed_precision_meets_fp64_bar(g, precision, n, seed, frac):
+    """Mixed forms: A Z A in reduced precision, everything that decides acceptance
+    and stopping in FP64 -> the same FP64 acceptance bar as the plain path."""
+    S, _ = synth.random_sparse_problem(n, n // 2, seed)
+    lam = frac * synth.lambda_max(S)
+    check_against_oracle(g, S, lam, 1e-6, solver=g.Solver(precision=precision))
+
+
+def test_mixed_chain(g):
+    S, _ = synth.chain_problem(100, 50, 0)
+    res, ref = check_against_oracle(g, S, 0.2, 1e-6, solver=g.Solver(precision="fp32"))
+
+
 def test_n1_and_n2(g):
     S = np.array([[0.7]])
     res = g.Solver().solve(to_dev(S), 0.1, 1e-10)
