@@ -28,6 +28,37 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// ---- small FP64 MFMA products on LDS-resident operands
+//
+// One 16x16 output block per call: acc += A B over k in [0, K), A element (m, k)
+// at a[ar + m][ac + k]; B element (k, n) at a[br + n][bc + k] (NT: rows of B^T)
+// or at a[br + k][bc + n] (NN).  Lane l supplies A[l%16][k + l/16] and
+// B[k + l/16][l%16]; D[i][j] lands in lane j + 16 (i%4), register i/4.
+// Optional masks zero A where k > m (A lower) and B where k < n (B lower), in
+// operand-local indices (mask_a/mask_b give the offsets of the block in the
+// triangular operand).
+template <bool NN, bool LOWA, bool LOWB>
+__device__ __forceinline__ v4d mfma_block(const double (*a)[LDL], int ar, int ac, int br, int bc, int K, v4d acc,
+                                          int lane, int ma = 0, int mb = 0) {
+  const int i = lane & 15, kk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < K; k += 4) {
+    double x = a[ar + i][ac + k + kk];
+    double y = NN ? a[br + k + kk][bc + i] : a[br + i][bc + k + kk];
+    if (LOWA && (k + kk > ma + i)) x = 0.0;
+    if (LOWB && (k + kk < mb + i)) y = 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// element (4r + lane/16, lane%16) of a 16x16 MFMA block is acc[r]
+template <typename F>
+__device__ __forceinline__ void for_block(v4d acc, int lane, F f) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) f(4 * r + (lane >> 4), lane & 15, acc[r]);
+}
+
 // ---- in-LDS inverse of a lower-triangular 128x128 block (upper triangle = scratch)
 //
 // Stage 1: wave w inverts the 32x32 diagonal block w (lane c computes column c by
@@ -35,63 +66,32 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
 // [T11 0; T21 T22] of size 2S with T11, T22 already inverted,
 //   tmp = T21 inv(T11)  (stored transposed in the free upper triangle),
 //   X21 = -inv(T22) tmp (written over T21),
-// as register-tiled products, one TR x TC output tile per thread.
-template <int S, int TR, int TC>
+// as 16x16 MFMA blocks spread over the four waves.
+template <int S>
 __device__ __forceinline__ void trtri_level(double (*a)[LDL], int tid) {
-  constexpr int TPG = (S / TR) * (S / TC);  // tiles per group
-  const int g = tid / TPG, t = tid % TPG;
-  const int o = g * 2 * S;
-  const int r0 = (t / (S / TC)) * TR, c0 = (t % (S / TC)) * TC;
-  double acc[TR][TC];
-#pragma unroll
-  for (int u = 0; u < TR; ++u)
-#pragma unroll
-    for (int v = 0; v < TC; ++v) acc[u][v] = 0.0;
-  // tmp[r][c] = sum_{k >= c} T21[r][k] inv(T11)[k][c]   (k < c terms are masked)
-#pragma unroll 4
-  for (int k = c0; k < S; ++k) {
-    double x[TR], y[TC];
-#pragma unroll
-    for (int u = 0; u < TR; ++u) x[u] = a[o + S + r0 + u][o + k];
-#pragma unroll
-    for (int v = 0; v < TC; ++v) {
-      const double b = a[o + k][o + c0 + v];
-      y[v] = (k >= c0 + v) ? b : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < TR; ++u)
-#pragma unroll
-      for (int v = 0; v < TC; ++v) acc[u][v] += x[u] * y[v];
+  constexpr int NBS = S / 16;                 // 16-blocks per edge
+  constexpr int GROUPS = NB / (2 * S);
+  constexpr int JOBS = GROUPS * NBS * NBS;    // output blocks per product
+  const int lane = tid & 63, wave = tid >> 6;
+  // tmp = T21 inv(T11): block (bi, bj) sums k from 16 bj (inv(T11) is lower)
+  for (int job = wave; job < JOBS; job += 4) {
+    const int g = job / (NBS * NBS), bi = (job / NBS) % NBS, bj = job % NBS;
+    const int o = g * 2 * S;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int k0 = 16 * bj;
+    acc = mfma_block<true, false, true>(a, o + S + 16 * bi, o + k0, o + k0, o + 16 * bj, S - k0, acc, lane, 0, 0);
+    for_block(acc, lane, [&](int r, int c, double v) { a[o + 16 * bj + c][o + S + 16 * bi + r] = v; });
   }
-#pragma unroll
-  for (int u = 0; u < TR; ++u)
-#pragma unroll
-    for (int v = 0; v < TC; ++v) a[o + c0 + v][o + S + r0 + u] = acc[u][v];
   __syncthreads();
-  // X21[r][c] = -sum_{k <= r} inv(T22)[r][k] tmp[k][c]   (k > r terms are masked)
-#pragma unroll
-  for (int u = 0; u < TR; ++u)
-#pragma unroll
-    for (int v = 0; v < TC; ++v) acc[u][v] = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < r0 + TR; ++k) {
-    double x[TR], y[TC];
-#pragma unroll
-    for (int u = 0; u < TR; ++u) {
-      const double b = a[o + S + r0 + u][o + S + k];
-      x[u] = (k <= r0 + u) ? b : 0.0;
-    }
-#pragma unroll
-    for (int v = 0; v < TC; ++v) y[v] = a[o + c0 + v][o + S + k];
-#pragma unroll
-    for (int u = 0; u < TR; ++u)
-#pragma unroll
-      for (int v = 0; v < TC; ++v) acc[u][v] += x[u] * y[v];
+  // X21 = -inv(T22) tmp: block (bi, bj) sums k up to 16 bi + 15 (inv(T22) is lower)
+  for (int job = wave; job < JOBS; job += 4) {
+    const int g = job / (NBS * NBS), bi = (job / NBS) % NBS, bj = job % NBS;
+    const int o = g * 2 * S;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    acc = mfma_block<false, true, false>(a, o + S + 16 * bi, o + S, o + 16 * bj, o + S, 16 * (bi + 1), acc, lane,
+                                         16 * bi, 0);
+    for_block(acc, lane, [&](int r, int c, double v) { a[o + S + 16 * bi + r][o + 16 * bj + c] = -v; });
   }
-#pragma unroll
-  for (int u = 0; u < TR; ++u)
-#pragma unroll
-    for (int v = 0; v < TC; ++v) a[o + S + r0 + u][o + c0 + v] = -acc[u][v];
   __syncthreads();
 }
 
@@ -118,8 +118,8 @@ __device__ void lds_trtri128(double (*a)[LDL], int tid) {
       if (i >= lane) a[o + i][o + lane] = x[i];
   }
   __syncthreads();
-  trtri_level<32, 2, 4>(a, tid);
-  trtri_level<64, 4, 4>(a, tid);
+  trtri_level<32>(a, tid);
+  trtri_level<64>(a, tid);
 }
 
 // Factor the 128x128 diagonal block at A (lower, in place), write diag(L) to dL and
@@ -138,7 +138,6 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
                                                              double* dL, double* Dinv, int* info) {
   if (*info) return;
   __shared__ double a[NB][LDL];
-  __shared__ double mb[4][PW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
@@ -169,20 +168,10 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
       const double r = rsqrt(ok ? piv : 1.0);
       const double m = v[j] * r;  // lane j: sqrt(piv); rows below: multipliers
       v[j] = m;
-      if (lane < PW) mb[wave][lane] = m;
-      __builtin_amdgcn_wave_barrier();
-      // next pivot column first, from a register broadcast (off the LDS round trip)
-      if (j + 1 < PW) {
-        v[j + 1] -= m * lane_bcast(m, j + 1);
-        asm volatile("" : "+v"(v[j + 1]));
-      }
+      // the multipliers of the block rows are uniform values: broadcast each one
+      // from its lane with readlane and update every later column
 #pragma unroll
-      for (int c = j + 2; c < PW; ++c) {
-        v[c] -= m * mb[wave][c];
-        // materialise the update now: left to itself the compiler defers these
-        // FMAs and keeps every step's broadcast multipliers live (spills)
-        asm volatile("" : "+v"(v[c]));
-      }
+      for (int c = j + 1; c < PW; ++c) v[c] -= m * lane_bcast(m, c);
     }
     if (fail >= 0) break;
     if (valid && (lane >= PW || wave == 0)) {
@@ -190,39 +179,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
       for (int q = 0; q < PW; ++q) a[row][c0 + q] = v[q];
     }
     __syncthreads();
-    // rank-32 update of the trailing lower triangle, 4x4 register blocks
+    // rank-32 update of the trailing lower triangle in 16x16 MFMA blocks
     const int base = c0 + PW, R = NB - base;
     if (R > 0) {
-      const int nb4 = R / 4;
-      const int nblk = nb4 * (nb4 + 1) / 2;
-      for (int e = tid; e < nblk; e += 256) {
-        int bi = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((bi + 1) * (bi + 2) / 2 <= e) ++bi;
-        while (bi * (bi + 1) / 2 > e) --bi;
-        const int bj = e - bi * (bi + 1) / 2;
-        const int r0 = base + 4 * bi, s0 = base + 4 * bj;
-        double acc[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
-#pragma unroll 8
-        for (int k = c0; k < c0 + PW; ++k) {
-          double x[4], y[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            x[u] = a[r0 + u][k];
-            y[u] = a[s0 + u][k];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int w = 0; w < 4; ++w) acc[u][w] += x[u] * y[w];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int w = 0; w < 4; ++w) a[r0 + u][s0 + w] -= acc[u][w];
+      const int nb16 = R / 16;
+      const int nblk = nb16 * (nb16 + 1) / 2;
+      for (int job = wave; job < nblk; job += 4) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
+        const int bj = job - bi * (bi + 1) / 2;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_block<false, false, false>(a, base + 16 * bi, c0, base + 16 * bj, c0, PW, acc, lane);
+        for_block(acc, lane, [&](int r, int c, double v) { a[base + 16 * bi + r][base + 16 * bj + c] -= v; });
       }
       __syncthreads();
     }
