@@ -49,7 +49,7 @@ typedef enum {
 typedef enum {
   GLASSO_FP64 = 0,        /* every step in FP64 */
   GLASSO_MIXED_FP32 = 1,  /* A Z A products in FP32 MFMA; factor, log det, PD test, W, KKT in FP64 */
-  GLASSO_MIXED_BF16X3 = 2 /* A Z A products as three BF16 split products, FP32 accumulation */
+  GLASSO_MIXED_BF16X3 = 2 /* reserved: A Z A as three BF16 split products (not accepted yet) */
 } glasso_precision;
 
 typedef struct {
@@ -107,6 +107,24 @@ glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
  * S_ii + lambda <= 0), NOT_PD (warm start not PD), OOM, HIP. */
 glasso_err glasso_solve(glasso_handle h, const double* S, int64_t n, double lambda, double tol,
                         double* A, double* W, glasso_info* info, void* stream);
+
+/* Solve `count` independent problems (e.g. a regularisation path: one S, many
+ * lambda) in batched launches: problems of equal n advance together, one pISTA
+ * iteration per round of launches, each with its own lambda, iterate, line search
+ * (its own step size, same backtracking as glasso_solve) and stopping test;
+ * problems that stop are skipped by later launches.  Problems of different n run
+ * group after group.
+ *   S[i]   device pointer to problem i's S (n[i] x n[i]); entries may alias
+ *   n[i], lambda[i]  size and regularisation weight of problem i
+ *   A[i], W[i]       outputs as in glasso_solve (W may be NULL, or W[i] NULL);
+ *                    with opt.warm_start A[i] also holds problem i's A^(0)
+ *   info   host array of count entries (may be NULL)
+ * Results are bitwise identical to solving each problem alone with glasso_solve
+ * (every kernel treats the problems of a batch independently).
+ * Errors: as glasso_solve, for any problem. */
+glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                                const double* lambda, double tol, double* const* A, double* const* W,
+                                glasso_info* info, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Step-level entry points: each runs one step of the per-iteration path on

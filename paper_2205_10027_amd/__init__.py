@@ -130,6 +130,46 @@ class Solver:
                       info.kkt_fro, info.kkt_max, int(info.nnz), info.ls_trials,
                       info.fallback_steps, tuple(info.time_ms))
 
+    def solve_batched(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
+        """Solve len(lams) problems in batched launches (glasso_solve_batched).
+        S_list: one tensor per problem (the same tensor may repeat) or a single
+        tensor shared by all.  With a warm_start solver, A_list holds the starting
+        iterates.  Returns one Result per problem."""
+        lams = [float(x) for x in lams]
+        count = len(lams)
+        if isinstance(S_list, torch.Tensor):
+            S_list = [S_list] * count
+        if len(S_list) != count:
+            raise ValueError("one S per lambda")
+        ns = [_square(S, "S") for S in S_list]
+        for S in S_list:
+            _dev(S, "S")
+        if A_list is None:
+            if self.options.warm_start:
+                raise ValueError("warm_start solver needs A_list")
+            A_list = [torch.empty_like(S) for S in S_list]
+        for A, n in zip(A_list, ns):
+            if tuple(A.shape) != (n, n):
+                raise ValueError("A_list entries must match S")
+            _dev(A, "A")
+        W_list = [torch.empty_like(S) for S in S_list] if want_W else None
+        VP = ctypes.c_void_p
+        Sp = (VP * count)(*[S.data_ptr() for S in S_list])
+        Ap = (VP * count)(*[A.data_ptr() for A in A_list])
+        Wp = (VP * count)(*[W.data_ptr() for W in W_list]) if want_W else None
+        nn = (ctypes.c_int64 * count)(*ns)
+        ll = (ctypes.c_double * count)(*lams)
+        infos = (GlassoInfo * count)()
+        _check(_lib.glasso_solve_batched(self._h, count, Sp, nn, ll, float(tol), Ap, Wp, infos,
+                                         _stream(stream)), "glasso_solve_batched")
+        out = []
+        for i in range(count):
+            inf = infos[i]
+            out.append(Result(A_list[i], W_list[i] if want_W else None, inf.objective, inf.iterations,
+                              inf.status, inf.kkt_rel1, inf.kkt_fro, inf.kkt_max, int(inf.nnz),
+                              inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms)))
+        return out
+
     # ---------------------------------------------------------------- single steps
     def cholesky(self, A: torch.Tensor, stream=None):
         n = _square(A, "A")
@@ -189,3 +229,55 @@ def solve(S: torch.Tensor, lam: float, tol: float, **options) -> Result:
         return s.solve(S, lam, tol)
     finally:
         s.close()
+
+
+def lambda_path(S: torch.Tensor, lams, tol: float, mode: str = "waves", waves: int = 4,
+                precision: str | int = "fp64", want_W: bool = False, **options):
+    """Regularisation path: solutions for every lambda in `lams` (any order).
+
+    mode "independent": all lambdas in one batched solve from the diagonal start;
+    mode "sequential":  one solve per lambda in decreasing order, each warm-started
+                        from the previous solution;
+    mode "waves":       lambdas in decreasing order split into `waves` consecutive
+                        groups; each group is one batched solve warm-started from the
+                        solution of the smallest lambda of the previous group (the
+                        first group starts from the diagonal).
+    The minimiser of each problem is unique, so every mode returns the same
+    solutions up to the stopping tolerance.  Returns Results in the order of `lams`."""
+    lams = [float(x) for x in lams]
+    order = sorted(range(len(lams)), key=lambda i: -lams[i])
+    results = [None] * len(lams)
+    cold = Solver(precision=precision, **options)
+    warm = Solver(precision=precision, warm_start=True, **options)
+    try:
+        if mode == "independent":
+            rs = cold.solve_batched(S, lams, tol, want_W=want_W)
+            return rs
+        if mode == "sequential":
+            prev = None
+            for i in order:
+                if prev is None:
+                    r = cold.solve(S, lams[i], tol, want_W=want_W)
+                else:
+                    r = warm.solve(S, lams[i], tol, A=prev.A.clone(), want_W=want_W)
+                results[i] = r
+                prev = r
+            return results
+        if mode == "waves":
+            size = -(-len(order) // max(1, waves))
+            groups = [order[k:k + size] for k in range(0, len(order), size)]
+            prev = None
+            for grp in groups:
+                gl = [lams[i] for i in grp]
+                if prev is None:
+                    rs = cold.solve_batched(S, gl, tol, want_W=want_W)
+                else:
+                    rs = warm.solve_batched(S, gl, tol, A_list=[prev.A.clone() for _ in grp], want_W=want_W)
+                for i, r in zip(grp, rs):
+                    results[i] = r
+                prev = rs[-1]  # smallest lambda of this wave
+            return results
+        raise ValueError(f"unknown mode {mode!r}")
+    finally:
+        cold.close()
+        warm.close()

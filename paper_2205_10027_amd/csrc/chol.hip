@@ -135,7 +135,13 @@ __device__ void lds_trtri128(double (*a)[LDL], int tid) {
 // the trailing lower triangle.  Elements above the diagonal carry garbage and are
 // never read as data.
 __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t lda, int k0,
-                                                             double* dL, double* Dinv, int* info) {
+                                                             double* dL, double* Dinv, int* info,
+                                                             FactorBatch fb) {
+  // problem blockIdx.y of the batch
+  A += blockIdx.y * fb.sA;
+  dL += blockIdx.y * fb.sdL;
+  Dinv += blockIdx.y * fb.sDinv;
+  info += blockIdx.y;
   if (*info) return;
   __shared__ double a[NB][LDL];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -219,11 +225,11 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
 
 // Place the stored diagonal-block inverses on the diagonal of L.
 __global__ __launch_bounds__(256) void copy_diag_blocks_kernel(double* L, int64_t ld, const double* Dinv,
-                                                               const int* abort_flag) {
-  if (abort_flag && *abort_flag) return;
+                                                               const int* abort_flag, FactorBatch fb) {
+  if (abort_flag && abort_flag[blockIdx.y]) return;
   const int b = blockIdx.x;
-  const double* src = Dinv + (int64_t)b * NB * NB;
-  double* dst = L + (int64_t)b * NB * (ld + 1);
+  const double* src = Dinv + blockIdx.y * fb.sDinv + (int64_t)b * NB * NB;
+  double* dst = L + blockIdx.y * fb.sA + (int64_t)b * NB * (ld + 1);
   for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int r = e >> 7, c = e & 127;
     dst[(int64_t)r * ld + c] = src[e];
@@ -232,29 +238,36 @@ __global__ __launch_bounds__(256) void copy_diag_blocks_kernel(double* L, int64_
 
 }  // namespace
 
-int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv, int* info) {
+int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv, int* info,
+                const FactorBatch& fb) {
   if (n % NB) return -1;
+  if (fb.count <= 0) return 0;
+  ZBatch zA;  // operands and output inside the factored matrix
+  zA.count = fb.count;
+  zA.sA = zA.sB = zA.sC = fb.sA;
+  ZBatch zT = zA;  // triangular solve: B operand is the diagonal-block inverse
+  zT.sB = fb.sDinv;
   int rc = 0;
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
     for (int k = K0; k < K1 && rc == 0; k += NB) {
       double* Akk = A + (int64_t)k * lda + k;
-      hipLaunchKernelGGL(leaf_potrf_inv_kernel, dim3(1), dim3(256), 0, stream, Akk, lda, k, dL + k,
-                         Dinv + (int64_t)(k / NB) * NB * NB, info);
+      hipLaunchKernelGGL(leaf_potrf_inv_kernel, dim3(1, fb.count), dim3(256), 0, stream, Akk, lda, k, dL + k,
+                         Dinv + (int64_t)(k / NB) * NB * NB, info, fb);
       if (hipGetLastError() != hipSuccess) return -2;
       const int rest = n - k - NB;
       if (rest > 0) {
         // panel below the block: A21 <- A21 * inv(L11)^T (in place; one tile column)
         double* A21 = A + (int64_t)(k + NB) * lda + k;
         rc = gemm_f64(stream, 0, 0, rest, NB, NB, 1.0, A21, lda, Dinv + (int64_t)(k / NB) * NB * NB, NB,
-                      0.0, A21, lda, 0, 0, 2, info);
+                      0.0, A21, lda, 0, 0, 2, info, 1, 0, 0, 0, 0, zT);
         if (rc) return rc;
       }
       if (k + NB < K1) {
         // update of the remaining columns of the outer panel
         const double* Pk = A + (int64_t)(k + NB) * lda + k;
         rc = gemm_f64(stream, 0, 0, rest, K1 - k - NB, NB, -1.0, Pk, lda, Pk, lda, 1.0,
-                      A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info);
+                      A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
         if (rc) return rc;
       }
     }
@@ -262,18 +275,30 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
       // trailing lower triangle: A22 -= L21 L21^T with K = panel width
       const double* L21 = A + (int64_t)K1 * lda + K0;
       rc = gemm_f64(stream, 0, 0, n - K1, n - K1, K1 - K0, -1.0, L21, lda, L21, lda, 1.0,
-                    A + (int64_t)K1 * lda + K1, lda, 1, 0, 0, info);
+                    A + (int64_t)K1 * lda + K1, lda, 1, 0, 0, info, 1, 0, 0, 0, 0, zA);
     }
   }
   return rc;
 }
 
 int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* Dinv, double* tmp,
-                const int* abort_flag) {
+                const int* abort_flag, const FactorBatch& fb, int64_t sTmp) {
   if (n % NB) return -1;
+  if (fb.count <= 0) return 0;
   const int nblk = n / NB;
-  hipLaunchKernelGGL(copy_diag_blocks_kernel, dim3(nblk), dim3(256), 0, stream, L, ld, Dinv, abort_flag);
+  hipLaunchKernelGGL(copy_diag_blocks_kernel, dim3(nblk, fb.count), dim3(256), 0, stream, L, ld, Dinv, abort_flag,
+                     fb);
   if (hipGetLastError() != hipSuccess) return -2;
+  ZBatch z1;  // tmp = T21 inv(T11)
+  z1.count = fb.count;
+  z1.sA = fb.sA;
+  z1.sB = fb.sA;
+  z1.sC = sTmp;
+  ZBatch z2;  // T21 = -inv(T22) tmp
+  z2.count = fb.count;
+  z2.sA = fb.sA;
+  z2.sB = sTmp;
+  z2.sC = fb.sA;
   // doubling: at block size s, each group [T11 0; T21 T22] of size 2s gets
   // X21 = -inv(T22) * T21 * inv(T11)
   for (int64_t s = NB; s < n; s *= 2) {
@@ -282,29 +307,34 @@ int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* 
     int rc;
     if (full > 0) {
       rc = gemm_f64(stream, 0, 1, (int)s, (int)s, (int)s, 1.0, L + s * ld, ld, L, ld, 0.0, tmp, s, 0, 0, 1,
-                    abort_flag, full, gstride, gstride, s * s);
+                    abort_flag, full, gstride, gstride, s * s, 0, z1);
       if (rc) return rc;
       rc = gemm_f64(stream, 0, 1, (int)s, (int)s, (int)s, -1.0, L + s * (ld + 1), ld, tmp, s, 0.0, L + s * ld,
-                    ld, 0, 1, 0, abort_flag, full, gstride, s * s, gstride);
+                    ld, 0, 1, 0, abort_flag, full, gstride, s * s, gstride, 0, z2);
       if (rc) return rc;
     }
     const int64_t base = (int64_t)full * 2 * s;
     const int64_t n2 = n - base - s;
     if (n2 > 0) {
       rc = gemm_f64(stream, 0, 1, (int)n2, (int)s, (int)s, 1.0, L + (base + s) * ld + base, ld,
-                    L + base * (ld + 1), ld, 0.0, tmp, s, 0, 0, 1, abort_flag);
+                    L + base * (ld + 1), ld, 0.0, tmp, s, 0, 0, 1, abort_flag, 1, 0, 0, 0, 0, z1);
       if (rc) return rc;
       rc = gemm_f64(stream, 0, 1, (int)n2, (int)s, (int)n2, -1.0, L + (base + s) * (ld + 1), ld, tmp, s, 0.0,
-                    L + (base + s) * ld + base, ld, 0, 1, 0, abort_flag);
+                    L + (base + s) * ld + base, ld, 0, 1, 0, abort_flag, 1, 0, 0, 0, 0, z2);
       if (rc) return rc;
     }
   }
   return 0;
 }
 
-int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int64_t ldw, int n) {
+int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int64_t ldw, int n,
+                const int* abort_flag, const FactorBatch& fb, int64_t sW) {
   // W = V^T V: op(A) = V^T is upper triangular, op(B) = V lower; tile (i, j) sums k >= i.
-  return gemm_f64(stream, 1, 1, n, n, n, 1.0, V, ldv, V, ldv, 0.0, W, ldw, 1, 2, 1, nullptr);
+  ZBatch z;
+  z.count = fb.count;
+  z.sA = z.sB = fb.sA;
+  z.sC = sW;
+  return gemm_f64(stream, 1, 1, n, n, n, 1.0, V, ldv, V, ldv, 0.0, W, ldw, 1, 2, 1, abort_flag, 1, 0, 0, 0, 0, z);
 }
 
 }  // namespace glasso

@@ -12,8 +12,13 @@
 //   a_tri     : 1 = op(A) lower triangular (zero for k > m), 2 = upper (k < m);
 //               the K range of a tile is clipped and the straddling slices masked.
 //   b_tri     : 1 = op(B) lower triangular (zero for k < n), 2 = upper (k > n).
-//   abort_flag: when non-null and nonzero at launch, the kernel does nothing (a
-//               failed pivot earlier in the same factorisation).
+//   abort_flag: when non-null and abort_flag[z] is nonzero at launch, problem z
+//               of the batch is skipped (a failed pivot earlier in the same
+//               factorisation, or a problem that is not being iterated).
+//
+// Batching: grid.y walks a first batch dimension (strides sA, sB, sC) and grid.z
+// a second one (strides zA, zB, zC), e.g. the groups of one problem and the
+// problems of a batch.
 //
 // Workgroup: 256 threads = 4 wave64s in a 2x2 arrangement, 128x128 output tile,
 // each wave owns 64x64 = 4x4 MFMA blocks (64 FP64 accumulators per lane).  BK=16
@@ -37,7 +42,8 @@ struct GemmF64Params {
   const double* B;
   double* C;
   int64_t lda, ldb, ldc;
-  int64_t sA, sB, sC;  // batch strides (elements)
+  int64_t sA, sB, sC;  // grid.y batch strides (elements)
+  int64_t zA, zB, zC;  // grid.z batch strides (elements)
   const int* abort_flag;
 };
 
@@ -134,7 +140,7 @@ __device__ __forceinline__ void store_slice(double (*S)[LDK], int tid, const dou
 // updates, 1 = the preconditioned product A Z A.
 template <int TA, int TB, int ROLE>
 __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
-  if (p.abort_flag && *p.abort_flag) return;
+  if (p.abort_flag && p.abort_flag[blockIdx.z]) return;
 
   __shared__ __attribute__((aligned(16))) double As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) double Bs[2][BN][LDK];
@@ -154,9 +160,9 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
     grouped_tile(L, p.tiles_m, p.tiles_n, ti, tj);
   const int m0 = ti * BM, n0 = tj * BN;
 
-  const double* A = p.A + (int64_t)blockIdx.y * p.sA;
-  const double* B = p.B + (int64_t)blockIdx.y * p.sB;
-  double* C = p.C + (int64_t)blockIdx.y * p.sC;
+  const double* A = p.A + (int64_t)blockIdx.y * p.sA + (int64_t)blockIdx.z * p.zA;
+  const double* B = p.B + (int64_t)blockIdx.y * p.sB + (int64_t)blockIdx.z * p.zB;
+  double* C = p.C + (int64_t)blockIdx.y * p.sC + (int64_t)blockIdx.z * p.zC;
 
   int kbeg = 0, kend = p.K;
   if (p.a_tri == 1) kend = min(kend, m0 + BM);
@@ -232,8 +238,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
 int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag, int batch,
-             int64_t sA, int64_t sB, int64_t sC, int role) {
-  if (M <= 0 || N <= 0 || batch <= 0) return 0;
+             int64_t sA, int64_t sB, int64_t sC, int role, const ZBatch& zb) {
+  if (M <= 0 || N <= 0 || batch <= 0 || zb.count <= 0) return 0;
   if (M % BM || N % BN || K % BK || K < 0) return -1;
   if (lower_out && M != N) return -1;
   GemmF64Params p;
@@ -256,9 +262,12 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
   p.sA = sA;
   p.sB = sB;
   p.sC = sC;
+  p.zA = zb.sA;
+  p.zB = zb.sB;
+  p.zC = zb.sC;
   p.abort_flag = abort_flag;
   const int tiles = lower_out ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
-  dim3 grid(tiles, batch), block(256);
+  dim3 grid(tiles, batch, zb.count), block(256);
   if (role == 1 && ta == 0 && tb == 0)
     hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 1>), grid, block, 0, stream, p);
   else if (ta == 0 && tb == 0)

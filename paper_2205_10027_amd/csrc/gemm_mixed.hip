@@ -22,6 +22,8 @@ struct GemmF32Params {
   const float* B;
   void* C;
   int64_t lda, ldb, ldc;
+  int64_t zA, zB, zC;  // grid.z (problem) strides, elements
+  const int* skip;     // per-problem skip flags (may be null)
 };
 
 // one 128 x 32 float slice per operand: thread t loads row t/2, 16 floats
@@ -45,6 +47,10 @@ __device__ __forceinline__ void store_slice(float (*S)[LDK], int tid, const floa
 
 template <typename TC>
 __global__ __launch_bounds__(256, 2) void gemm_f32_nt_kernel(GemmF32Params p) {
+  if (p.skip && p.skip[blockIdx.z]) return;
+  p.A += blockIdx.z * p.zA;
+  p.B += blockIdx.z * p.zB;
+  p.C = reinterpret_cast<char*>(p.C) + blockIdx.z * p.zC * (int64_t)sizeof(TC);
   __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -124,8 +130,8 @@ __global__ void f64_to_f32_kernel(const double* __restrict__ src, float* __restr
 }  // namespace
 
 int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda, const float* B, int64_t ldb,
-                void* C, int64_t ldc, int c_is_double, int lower_out) {
-  if (M <= 0 || N <= 0) return 0;
+                void* C, int64_t ldc, int c_is_double, int lower_out, const ZBatch& zb, const int* skip) {
+  if (M <= 0 || N <= 0 || zb.count <= 0) return 0;
   if (M % BM || N % BN || K % BK || K <= 0) return -1;
   if (lower_out && M != N) return -1;
   GemmF32Params p;
@@ -141,11 +147,15 @@ int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t
   p.lda = lda;
   p.ldb = ldb;
   p.ldc = ldc;
+  p.zA = zb.sA;
+  p.zB = zb.sB;
+  p.zC = zb.sC;
+  p.skip = skip;
   const int tiles = lower_out ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
   if (c_is_double)
-    hipLaunchKernelGGL(gemm_f32_nt_kernel<double>, dim3(tiles), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(gemm_f32_nt_kernel<double>, dim3(tiles, 1, zb.count), dim3(256), 0, stream, p);
   else
-    hipLaunchKernelGGL(gemm_f32_nt_kernel<float>, dim3(tiles), dim3(256), 0, stream, p);
+    hipLaunchKernelGGL(gemm_f32_nt_kernel<float>, dim3(tiles, 1, zb.count), dim3(256), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <chrono>
 #include <new>
+#include <vector>
 
 #include "../../include/glasso.h"
 #include "common.h"
@@ -18,37 +19,40 @@ using namespace glasso;
 
 namespace {
 
-constexpr int FLAG_FACTOR = 0;  // info of the latest Cholesky
-constexpr int NFLAGS = 16;
-
 struct Workspace {
-  int64_t cap = 0;  // padded size the buffers were laid out for
-  int64_t np = 0;   // padded size (leading dimension) of the current problem
+  int cap_count = 0;   // problems the buffers were laid out for
+  int64_t cap_np = 0;  // padded size the buffers were laid out for
+  int count = 0;       // problems of the current call
+  int64_t np = 0;      // padded size (leading dimension) of the current call
   void* base = nullptr;
   size_t bytes = 0;
+  // per problem b: matrices at + b * np^2, diagonals at + b * np, block inverses at
+  // + b * np * 128, pass partials at + b * tiles * 8, scalar slots at + b * SC_COUNT
   double *S = nullptr, *A = nullptr, *At = nullptr, *L = nullptr, *Lt = nullptr, *W = nullptr, *Z = nullptr,
          *X = nullptr, *P = nullptr;
   int8_t* GM = nullptr;
   double *dL = nullptr, *dLt = nullptr, *Dinv = nullptr, *Dinvt = nullptr;
   double* part = nullptr;
   double* scal = nullptr;
-  int* flags = nullptr;
+  int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
+  double *lam = nullptr, *t = nullptr;
   int64_t* bad = nullptr;
   double* vec = nullptr;
+  int64_t nn() const { return np * np; }
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Carve the workspace of padded size np out of one allocation (base may be null
-// to only measure).
-size_t layout(Workspace& w, int64_t np, char* base) {
+// Carve the workspace for `count` problems of padded size np out of one
+// allocation (base may be null to only measure).
+size_t layout(Workspace& w, int count, int64_t np, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
     off += align_up(bytes);
     return p;
   };
-  const size_t mat = (size_t)np * np * sizeof(double);
+  const size_t mat = (size_t)count * np * np * sizeof(double);
   w.S = (double*)take(mat);
   w.A = (double*)take(mat);
   w.At = (double*)take(mat);
@@ -58,18 +62,32 @@ size_t layout(Workspace& w, int64_t np, char* base) {
   w.Z = (double*)take(mat);
   w.X = (double*)take(mat);
   w.P = (double*)take(mat);
-  w.GM = (int8_t*)take((size_t)np * np);
-  w.dL = (double*)take(np * sizeof(double));
-  w.dLt = (double*)take(np * sizeof(double));
-  w.Dinv = (double*)take((size_t)np * TILE * sizeof(double));
-  w.Dinvt = (double*)take((size_t)np * TILE * sizeof(double));
-  w.part = (double*)take((size_t)pass_tiles(np) * 8 * sizeof(double));
-  w.scal = (double*)take(SC_COUNT * sizeof(double));
-  w.flags = (int*)take(NFLAGS * sizeof(int));
+  w.GM = (int8_t*)take((size_t)count * np * np);
+  w.dL = (double*)take((size_t)count * np * sizeof(double));
+  w.dLt = (double*)take((size_t)count * np * sizeof(double));
+  w.Dinv = (double*)take((size_t)count * np * TILE * sizeof(double));
+  w.Dinvt = (double*)take((size_t)count * np * TILE * sizeof(double));
+  w.part = (double*)take((size_t)count * pass_tiles(np) * 8 * sizeof(double));
+  w.scal = (double*)take((size_t)count * SC_COUNT * sizeof(double));
+  w.info = (int*)take(count * sizeof(int));
+  w.skip = (int*)take(count * sizeof(int));
+  w.lsskip = (int*)take(count * sizeof(int));
+  w.accept = (int*)take(count * sizeof(int));
+  w.lam = (double*)take(count * sizeof(double));
+  w.t = (double*)take(count * sizeof(double));
   w.bad = (int64_t*)take(sizeof(int64_t));
   w.vec = (double*)take(2 * np * sizeof(double));
   return off;
 }
+
+// pinned host mirrors of the per-problem device arrays
+struct HostMirror {
+  int cap = 0;
+  double* scal = nullptr;
+  int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
+  double *lam = nullptr, *t = nullptr;
+  int64_t* bad = nullptr;
+};
 
 }  // namespace
 
@@ -77,7 +95,7 @@ struct glasso_handle_s {
   glasso_options opt;
   int device = 0;
   Workspace ws;
-  double* host = nullptr;  // pinned: scalars + flags
+  HostMirror hm;
   hipEvent_t ev[6] = {};
 };
 
@@ -94,18 +112,51 @@ namespace {
     if (_rc) return GLASSO_ERR_HIP;                    \
   } while (0)
 
-glasso_err ensure_workspace(glasso_handle h, int64_t np) {
+void free_host(HostMirror& m) {
+  if (m.scal) (void)hipHostFree(m.scal);
+  m = HostMirror();
+}
+
+glasso_err ensure_host(glasso_handle h, int count) {
+  HostMirror& m = h->hm;
+  if (m.scal && m.cap >= count) return GLASSO_OK;
+  free_host(m);
+  const size_t bytes = (size_t)count * (SC_COUNT + 2) * sizeof(double) + (size_t)count * 4 * sizeof(int) + 64;
+  char* p = nullptr;
+  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) return GLASSO_ERR_HIP;
+  m.cap = count;
+  m.scal = (double*)p;
+  m.lam = m.scal + (size_t)count * SC_COUNT;
+  m.t = m.lam + count;
+  m.info = (int*)(m.t + count);
+  m.skip = m.info + count;
+  m.lsskip = m.skip + count;
+  m.accept = m.lsskip + count;
+  m.bad = (int64_t*)(((uintptr_t)(m.accept + count) + 7) & ~uintptr_t(7));
+  return GLASSO_OK;
+}
+
+glasso_err ensure_workspace(glasso_handle h, int count, int64_t np) {
   Workspace& w = h->ws;
-  if (w.base && w.cap >= np) {
-    w.np = np;
-    return GLASSO_OK;
+  glasso_err e = ensure_host(h, count);
+  if (e) return e;
+  if (w.base && w.cap_count >= count && w.cap_np >= np &&
+      (size_t)w.cap_count * w.cap_np * w.cap_np >= (size_t)count * np * np) {
+    // re-carve the same allocation for this (count, np): every buffer fits
+    Workspace probe;
+    if (layout(probe, count, np, nullptr) <= w.bytes) {
+      layout(w, count, np, (char*)w.base);
+      w.count = count;
+      w.np = np;
+      return GLASSO_OK;
+    }
   }
   if (w.base) {
     (void)hipFree(w.base);
     w = Workspace();
   }
   Workspace probe;
-  const size_t bytes = layout(probe, np, nullptr);
+  const size_t bytes = layout(probe, count, np, nullptr);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -115,22 +166,43 @@ glasso_err ensure_workspace(glasso_handle h, int64_t np) {
     (void)hipFree(base);
     return GLASSO_ERR_HIP;
   }
-  layout(w, np, (char*)base);
+  layout(w, count, np, (char*)base);
   w.base = base;
   w.bytes = bytes;
-  w.cap = np;
+  w.cap_count = count;
+  w.cap_np = np;
+  w.count = count;
   w.np = np;
   return GLASSO_OK;
 }
 
-// copy the device scalar slots and flags to pinned host memory and wait
+FactorBatch factor_batch(const Workspace& w) {
+  FactorBatch fb;
+  fb.count = w.count;
+  fb.sA = w.nn();
+  fb.sdL = w.np;
+  fb.sDinv = w.np * TILE;
+  return fb;
+}
+
+// scalar slots and factor status of every problem -> pinned host memory, then wait
 glasso_err fetch(glasso_handle h, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(h->host, h->ws.scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h->host + SC_COUNT, h->ws.flags, NFLAGS * sizeof(int), hipMemcpyDeviceToHost, st));
+  const Workspace& w = h->ws;
+  HIP_TRY(hipMemcpyAsync(h->hm.scal, w.scal, (size_t)w.count * SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->hm.info, w.info, (size_t)w.count * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return GLASSO_OK;
 }
-int host_flag(glasso_handle h, int i) { return reinterpret_cast<int*>(h->host + SC_COUNT)[i]; }
+double hscal(glasso_handle h, int b, int slot) { return h->hm.scal[(size_t)b * SC_COUNT + slot]; }
+
+glasso_err push_ints(hipStream_t st, int* dev, const int* host, int count) {
+  HIP_TRY(hipMemcpyAsync(dev, host, count * sizeof(int), hipMemcpyHostToDevice, st));
+  return GLASSO_OK;
+}
+glasso_err push_doubles(hipStream_t st, double* dev, const double* host, int count) {
+  HIP_TRY(hipMemcpyAsync(dev, host, count * sizeof(double), hipMemcpyHostToDevice, st));
+  return GLASSO_OK;
+}
 
 glasso_err check_options(const glasso_options* o) {
   if (o->precision != GLASSO_FP64 && o->precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
@@ -149,60 +221,275 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-// Factor the padded matrix in w.L (lower, in place) and wait for the pivot status.
-glasso_err factor_current(glasso_handle h, hipStream_t st, int* info_out) {
+// Factor every problem's w.L (lower, in place); info[b] = 0 on entry for all.
+glasso_err factor_all(glasso_handle h, hipStream_t st) {
   Workspace& w = h->ws;
-  HIP_TRY(hipMemsetAsync(w.flags + FLAG_FACTOR, 0, sizeof(int), st));
-  K_TRY(potrf_lower(st, w.L, w.np, (int)w.np, w.dL, w.Dinv, w.flags + FLAG_FACTOR));
-  glasso_err e = fetch(h, st);
+  for (int b = 0; b < w.count; ++b) h->hm.info[b] = 0;
+  glasso_err e = push_ints(st, w.info, h->hm.info, w.count);
   if (e) return e;
-  *info_out = host_flag(h, FLAG_FACTOR);
+  K_TRY(potrf_lower(st, w.L, w.np, (int)w.np, w.dL, w.Dinv, w.info, factor_batch(w)));
+  return fetch(h, st);
+}
+
+// W (lower) = A^{-1} from the factor in w.L for every problem with skip == 0:
+// L <- inv(L) in place, W = inv(L)^T inv(L).  tmp: the X buffer.
+glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
+  const FactorBatch fb = factor_batch(w);
+  K_TRY(trtri_lower(st, w.L, w.np, (int)w.np, w.Dinv, w.X, skip, fb, w.nn()));
+  K_TRY(lauum_lower(st, w.L, w.np, w.W, w.np, (int)w.np, skip, fb, w.nn()));
   return GLASSO_OK;
 }
 
-// W (lower) = A^{-1} from the factor in w.L: L <- inv(L) in place, W = inv(L)^T inv(L).
-glasso_err inverse_from_factor(Workspace& w, hipStream_t st) {
-  K_TRY(trtri_lower(st, w.L, w.np, (int)w.np, w.Dinv, w.X, nullptr));
-  K_TRY(lauum_lower(st, w.L, w.np, w.W, w.np, (int)w.np));
-  return GLASSO_OK;
-}
-
-// P (lower) = A Z A: X = A Z^T (Z symmetric), P = tril(X A^T) (A symmetric).
-// Mixed FP32: A and Z are rounded to FP32 (A32, Z32 in the X buffer), X32 = A32 Z32^T
-// overwrites Z (no longer needed), P = tril(X32 A32^T) is written in FP64.
-glasso_err precond_product(Workspace& w, hipStream_t st, int precision) {
+// P (lower) = A Z A for every problem with skip == 0: X = A Z^T (Z symmetric),
+// P = tril(X A^T) (A symmetric).  Mixed FP32: A and Z are rounded to FP32 (A32,
+// Z32 in the X buffer), X32 = A32 Z32^T overwrites Z (no longer needed), and
+// P = tril(X32 A32^T) is written in FP64.
+glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip) {
   const int np = (int)w.np;
+  const int64_t nn = w.nn();
+  ZBatch z;
+  z.count = w.count;
+  z.sA = z.sB = z.sC = nn;
   if (precision == GLASSO_FP64) {
-    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, nullptr, 1, 0, 0, 0, 1));
-    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, nullptr, 1, 0, 0, 0, 1));
+    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, skip, 1, 0, 0, 0, 1, z));
+    K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, skip, 1, 0, 0, 0, 1, z));
     return GLASSO_OK;
   }
   if (precision == GLASSO_MIXED_FP32) {
-    const int64_t nn = (int64_t)np * np;
-    float* A32 = reinterpret_cast<float*>(w.X);
-    float* Z32 = A32 + nn;
+    // A32 and Z32 share the X buffer: A32 of problem b at b * 2nn floats, Z32 after it
+    float* X32buf = reinterpret_cast<float*>(w.X);
     float* X32 = reinterpret_cast<float*>(w.Z);
-    K_TRY(f64_to_f32(st, w.A, A32, nn));
-    K_TRY(f64_to_f32(st, w.Z, Z32, nn));
-    K_TRY(gemm_f32_nt(st, np, np, np, A32, np, Z32, np, X32, np, 0, 0));
-    K_TRY(gemm_f32_nt(st, np, np, np, X32, np, A32, np, w.P, np, 1, 1));
+    for (int b = 0; b < w.count; ++b) {
+      K_TRY(f64_to_f32(st, w.A + b * nn, X32buf + 2 * b * nn, nn));
+      K_TRY(f64_to_f32(st, w.Z + b * nn, X32buf + 2 * b * nn + nn, nn));
+    }
+    ZBatch z1;  // X32 = A32 Z32^T
+    z1.count = w.count;
+    z1.sA = 2 * nn;
+    z1.sB = 2 * nn;
+    z1.sC = 2 * nn;  // floats: X32 of problem b inside Z's doubles at b * nn doubles
+    K_TRY(gemm_f32_nt(st, np, np, np, X32buf, np, X32buf + nn, np, X32, np, 0, 0, z1, skip));
+    ZBatch z2;  // P = tril(X32 A32^T)
+    z2.count = w.count;
+    z2.sA = 2 * nn;
+    z2.sB = 2 * nn;
+    z2.sC = nn;
+    K_TRY(gemm_f32_nt(st, np, np, np, X32, np, X32buf, np, w.P, np, 1, 1, z2, skip));
     return GLASSO_OK;
   }
   return GLASSO_ERR_INVALID_ARG;
 }
 
-// cond(A) ~ lambda_max(A) * lambda_max(A^{-1}) by power iteration; t = (0.9/cond)^2.
+// cond(A_b) ~ lambda_max(A_b) lambda_max(A_b^{-1}) by power iteration; t = (0.9/cond)^2.
 // Ritz values approach from below, so each estimate is inflated by 5%.
-glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int64_t n, double* t_out) {
+glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int b, int64_t n, double* t_out) {
   Workspace& w = h->ws;
-  K_TRY(power_iteration(st, w.A, n, w.np, w.vec, w.scal + SC_POWER_A, 60));
-  HIP_TRY(hipMemcpyAsync(w.X, w.W, (size_t)w.np * w.np * sizeof(double), hipMemcpyDeviceToDevice, st));
-  K_TRY(mirror_lower(st, w.X, w.np));
-  K_TRY(power_iteration(st, w.X, n, w.np, w.vec, w.scal + SC_POWER_W, 60));
+  const int64_t nn = w.nn();
+  double* scal = w.scal + (size_t)b * SC_COUNT;
+  double* Xb = w.X + b * nn;
+  K_TRY(power_iteration(st, w.A + b * nn, n, w.np, w.vec, scal + SC_POWER_A, 60));
+  HIP_TRY(hipMemcpyAsync(Xb, w.W + b * nn, (size_t)nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  K_TRY(mirror_lower(st, Xb, w.np));
+  K_TRY(power_iteration(st, Xb, n, w.np, w.vec, scal + SC_POWER_W, 60));
   glasso_err e = fetch(h, st);
   if (e) return e;
-  const double cond = (1.05 * h->host[SC_POWER_A]) * (1.05 * h->host[SC_POWER_W]);
+  const double cond = (1.05 * hscal(h, b, SC_POWER_A)) * (1.05 * hscal(h, b, SC_POWER_W));
   *t_out = (0.9 / cond) * (0.9 / cond);
+  return GLASSO_OK;
+}
+
+// ----------------------------------------------------------------- the engine
+//
+// Alg. 1 for `count` problems of equal size n at once (the single solve is
+// count = 1).  Every phase is one batched launch sequence over the problems
+// still iterating; per-problem flags skip the others.  The line search runs in
+// rounds: each round evaluates one trial step per searching problem, and each
+// problem backtracks on its own t, so every problem follows exactly the
+// sequential line search of the paper.
+glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, const double* const* S,
+                      const double* lam, double tol, double* const* Aout, double* const* Wout, glasso_info* info) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const glasso_options& o = h->opt;
+  const int64_t np = pad_to_tile(n);
+  glasso_err e = ensure_workspace(h, count, np);
+  if (e) return e;
+  Workspace& w = h->ws;
+  HostMirror& hm = h->hm;
+  const int64_t nn = w.nn();
+  const int tiles = (int)pass_tiles(np);
+
+  // S into the padded layout (shared when every problem passes the same pointer);
+  // reject non-finite entries and S_ii + lambda <= 0
+  bool shared = true;
+  double lam_min = lam[0];
+  for (int b = 0; b < count; ++b) {
+    if (S[b] != S[0]) shared = false;
+    lam_min = std::min(lam_min, lam[b]);
+  }
+  HIP_TRY(hipMemsetAsync(w.bad, 0, sizeof(int64_t), st));
+  for (int b = 0; b < (shared ? 1 : count); ++b)
+    K_TRY(copy_in_padded(st, S[b], n, w.S + b * nn, np, w.bad, shared ? lam_min : lam[b], 1));
+  HIP_TRY(hipMemcpyAsync(hm.bad, w.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (*hm.bad) return GLASSO_ERR_INVALID_ARG;
+  const int64_t sS = shared ? 0 : nn;
+
+  for (int b = 0; b < count; ++b) hm.lam[b] = lam[b];
+  e = push_doubles(st, w.lam, hm.lam, count);
+  if (e) return e;
+
+  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 5); its factor
+  for (int b = 0; b < count; ++b) {
+    if (o.warm_start)
+      K_TRY(pad_copy_f64(st, Aout[b], n, np, w.A + b * nn, w.L + b * nn, 1));
+    else
+      K_TRY(init_diag(st, w.S + b * sS, n, np, lam[b], w.A + b * nn, w.L + b * nn));
+  }
+  e = factor_all(h, st);
+  if (e) return e;
+  for (int b = 0; b < count; ++b)
+    if (hm.info[b]) return o.warm_start ? GLASSO_ERR_NOT_PD : GLASSO_ERR_INVALID_ARG;
+
+  std::vector<int> active(count, 1), status(count, GLASSO_MAX_ITER), it(count, 0), trials(count, 0),
+      fallbacks(count, 0), ls(count, 0), fb_used(count, 0);
+  PassBatch pb;
+  pb.count = count;
+  pb.sS = sS;
+  pb.sM = nn;
+  pb.sV = np;
+  pb.lam = w.lam;
+  double phase[8] = {0};
+  for (;;) {
+    for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
+    e = push_ints(st, w.skip, hm.skip, count);
+    if (e) return e;
+    pb.skip = w.skip;
+    pb.t = nullptr;
+    // a1: W = A^{-1} from the accepted factor
+    HIP_TRY(hipEventRecord(h->ev[0], st));
+    e = inverse_from_factor(w, st, w.skip);
+    if (e) return e;
+    HIP_TRY(hipEventRecord(h->ev[1], st));
+    // a2: gradient, free set, sign guess, Z and the KKT measure
+    K_TRY(pass_grad(st, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
+    HIP_TRY(hipEventRecord(h->ev[2], st));
+    e = fetch(h, st);
+    if (e) return e;
+    phase[1] += elapsed(h->ev[0], h->ev[1]);
+    phase[2] += elapsed(h->ev[1], h->ev[2]);
+    int nact = 0;
+    for (int b = 0; b < count; ++b) {
+      if (!active[b]) continue;
+      if (hscal(h, b, SC_KKT_REL1) <= tol) {
+        status[b] = GLASSO_CONVERGED;
+        active[b] = 0;
+      } else if (it[b] >= o.max_iter) {
+        status[b] = GLASSO_MAX_ITER;
+        active[b] = 0;
+      } else {
+        ++nact;
+      }
+    }
+    if (!nact) break;
+    for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
+    e = push_ints(st, w.skip, hm.skip, count);
+    if (e) return e;
+    // a3: P = A Z A
+    HIP_TRY(hipEventRecord(h->ev[2], st));
+    e = precond_product(w, st, o.precision, w.skip);
+    if (e) return e;
+    HIP_TRY(hipEventRecord(h->ev[3], st));
+    // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
+    for (int b = 0; b < count; ++b) {
+      ls[b] = active[b];
+      fb_used[b] = 0;
+      hm.t[b] = o.t0;
+    }
+    for (;;) {
+      int nls = 0;
+      for (int b = 0; b < count; ++b) {
+        if (!ls[b]) continue;
+        if (hm.t[b] < o.t_floor && !fb_used[b]) {
+          double tf = 0.0;
+          e = cond_fallback_step(h, st, b, n, &tf);
+          if (e) return e;
+          hm.t[b] = std::min(hm.t[b], tf);
+          fb_used[b] = 1;
+          ++fallbacks[b];
+        }
+        if (hm.t[b] < o.t_min) {
+          ls[b] = 0;
+          active[b] = 0;
+          status[b] = GLASSO_LS_FAILED;
+          continue;
+        }
+        ++nls;
+      }
+      if (!nls) break;
+      for (int b = 0; b < count; ++b) hm.lsskip[b] = !ls[b];
+      e = push_ints(st, w.lsskip, hm.lsskip, count);
+      if (e) return e;
+      e = push_doubles(st, w.t, hm.t, count);
+      if (e) return e;
+      PassBatch pt = pb;
+      pt.skip = w.lsskip;
+      pt.t = w.t;
+      K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
+      K_TRY(potrf_lower(st, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w)));
+      K_TRY(finish_trial(st, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal, pt));
+      e = fetch(h, st);
+      if (e) return e;
+      int nacc = 0;
+      for (int b = 0; b < count; ++b) {
+        hm.accept[b] = 0;
+        if (!ls[b]) continue;
+        ++trials[b];
+        if (hm.info[b] == 0 && hscal(h, b, SC_DF) < 0.0) {
+          hm.accept[b] = 1;
+          ls[b] = 0;
+          ++it[b];
+          ++nacc;
+        } else {
+          hm.t[b] *= o.shrink;
+        }
+      }
+      if (nacc) {
+        // a7: accept
+        e = push_ints(st, w.accept, hm.accept, count);
+        if (e) return e;
+        K_TRY(accept_trials(st, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, w.Dinv, w.Dinvt, np));
+      }
+    }
+    HIP_TRY(hipEventRecord(h->ev[4], st));
+    HIP_TRY(hipEventSynchronize(h->ev[4]));
+    phase[3] += elapsed(h->ev[2], h->ev[3]);
+    phase[4] += elapsed(h->ev[3], h->ev[4]);
+  }
+
+  for (int b = 0; b < count; ++b) {
+    K_TRY(sym_copy_out(st, w.A + b * nn, np, Aout[b], n, 0));
+    if (Wout && Wout[b]) K_TRY(sym_copy_out(st, w.W + b * nn, np, Wout[b], n, 1));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (info) {
+    const double total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    for (int b = 0; b < count; ++b) {
+      glasso_info& in = info[b];
+      memset(&in, 0, sizeof(in));
+      in.objective = hscal(h, b, SC_OBJECTIVE);
+      in.kkt_rel1 = hscal(h, b, SC_KKT_REL1);
+      in.kkt_fro = hscal(h, b, SC_KKT_FRO);
+      in.kkt_max = hscal(h, b, SC_MAX_ABS_Z);
+      in.nnz = (int64_t)llround(hscal(h, b, SC_NNZ_A));
+      in.iterations = it[b];
+      in.ls_trials = trials[b];
+      in.status = status[b];
+      in.fallback_steps = fallbacks[b];
+      for (int i = 1; i < 8; ++i) in.time_ms[i] = phase[i];
+      in.time_ms[0] = total;
+    }
+  }
   return GLASSO_OK;
 }
 
@@ -239,13 +526,13 @@ glasso_err glasso_create(glasso_handle* h, const glasso_options* opt) {
     delete hh;
     return GLASSO_ERR_HIP;
   }
-  if (hipHostMalloc((void**)&hh->host, (SC_COUNT + NFLAGS) * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (ensure_host(hh, 1) != GLASSO_OK) {
     delete hh;
     return GLASSO_ERR_HIP;
   }
   for (auto& e : hh->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
-      (void)hipHostFree(hh->host);
+      free_host(hh->hm);
       delete hh;
       return GLASSO_ERR_HIP;
     }
@@ -257,7 +544,7 @@ glasso_err glasso_create(glasso_handle* h, const glasso_options* opt) {
 glasso_err glasso_destroy(glasso_handle h) {
   if (!h) return GLASSO_OK;
   if (h->ws.base) (void)hipFree(h->ws.base);
-  if (h->host) (void)hipHostFree(h->host);
+  free_host(h->hm);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   delete h;
@@ -277,9 +564,9 @@ const char* glasso_error_string(glasso_err e) {
 }
 
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes) {
-  if (n < 1 || !bytes || precision < GLASSO_FP64 || precision > GLASSO_MIXED_BF16X3) return GLASSO_ERR_INVALID_ARG;
+  if (n < 1 || !bytes || (precision != GLASSO_FP64 && precision != GLASSO_MIXED_FP32)) return GLASSO_ERR_INVALID_ARG;
   Workspace probe;
-  *bytes = layout(probe, pad_to_tile(n), nullptr);
+  *bytes = layout(probe, 1, pad_to_tile(n), nullptr);
   return GLASSO_OK;
 }
 
@@ -287,121 +574,43 @@ glasso_err glasso_solve(glasso_handle h, const double* S, int64_t n, double lamb
                         double* W, glasso_info* info, void* stream) {
   if (!h || !S || !A || n < 1 || !(lambda > 0.0) || !(tol > 0.0) || !isfinite(lambda) || n > (1 << 20))
     return GLASSO_ERR_INVALID_ARG;
-  const auto t_start = std::chrono::steady_clock::now();
-  hipStream_t st = (hipStream_t)stream;
-  const glasso_options& o = h->opt;
-  const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
-  if (e) return e;
-  Workspace& w = h->ws;
+  const double* Sp[1] = {S};
+  double* Ap[1] = {A};
+  double* Wp[1] = {W};
+  return run_engine(h, (hipStream_t)stream, 1, n, Sp, &lambda, tol, Ap, Wp, info);
+}
 
-  // S into the padded layout; reject non-finite entries and S_ii + lambda <= 0
-  HIP_TRY(hipMemsetAsync(w.bad, 0, sizeof(int64_t), st));
-  K_TRY(copy_in_padded(st, S, n, w.S, np, w.bad, lambda, 1));
-  int64_t nbad = 0;
-  HIP_TRY(hipMemcpyAsync(&nbad, w.bad, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (nbad) return GLASSO_ERR_INVALID_ARG;
-
-  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 5); its factor
-  if (o.warm_start)
-    K_TRY(pad_copy_f64(st, A, n, np, w.A, w.L, 1));
-  else
-    K_TRY(init_diag(st, w.S, n, np, lambda, w.A, w.L));
-  int finfo = 0;
-  e = factor_current(h, st, &finfo);
-  if (e) return e;
-  if (finfo) return o.warm_start ? GLASSO_ERR_NOT_PD : GLASSO_ERR_INVALID_ARG;
-
-  const int tiles = (int)pass_tiles(np);
-  int it = 0, trials = 0, fallbacks = 0;
-  int status = GLASSO_MAX_ITER;
-  double phase[8] = {0};
-  for (;;) {
-    // a1: W = A^{-1} from the accepted factor
-    HIP_TRY(hipEventRecord(h->ev[0], st));
-    e = inverse_from_factor(w, st);
+glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                                const double* lambda, double tol, double* const* A, double* const* W,
+                                glasso_info* info, void* stream) {
+  if (!h || count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return GLASSO_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!S[i] || !A[i] || n[i] < 1 || n[i] > (1 << 20) || !(lambda[i] > 0.0) || !isfinite(lambda[i]))
+      return GLASSO_ERR_INVALID_ARG;
+  // problems of equal padded size run together; groups run one after another
+  std::vector<int> done(count, 0);
+  for (int i = 0; i < count; ++i) {
+    if (done[i]) continue;
+    const int64_t np = pad_to_tile(n[i]);
+    std::vector<int> idx;
+    for (int j = i; j < count; ++j)
+      if (!done[j] && pad_to_tile(n[j]) == np && n[j] == n[i]) idx.push_back(j);
+    std::vector<const double*> Sg;
+    std::vector<double> lg;
+    std::vector<double*> Ag, Wg;
+    std::vector<glasso_info> ig(idx.size());
+    for (int j : idx) {
+      Sg.push_back(S[j]);
+      lg.push_back(lambda[j]);
+      Ag.push_back(A[j]);
+      Wg.push_back(W ? W[j] : nullptr);
+      done[j] = 1;
+    }
+    glasso_err e = run_engine(h, (hipStream_t)stream, (int)idx.size(), n[i], Sg.data(), lg.data(), tol, Ag.data(),
+                              Wg.data(), ig.data());
     if (e) return e;
-    HIP_TRY(hipEventRecord(h->ev[1], st));
-    // a2: gradient, free set, sign guess, Z and the KKT measure
-    K_TRY(pass_grad(st, w.S, w.W, w.A, w.dL, n, n, np, lambda, w.Z, w.GM, w.part, w.scal));
-    HIP_TRY(hipEventRecord(h->ev[2], st));
-    e = fetch(h, st);
-    if (e) return e;
-    phase[1] += elapsed(h->ev[0], h->ev[1]);
-    phase[2] += elapsed(h->ev[1], h->ev[2]);
-    const double kkt = h->host[SC_KKT_REL1];
-    if (kkt <= tol) {
-      status = GLASSO_CONVERGED;
-      break;
-    }
-    if (it >= o.max_iter) {
-      status = GLASSO_MAX_ITER;
-      break;
-    }
-    // a3: P = A Z A
-    HIP_TRY(hipEventRecord(h->ev[2], st));
-    e = precond_product(w, st, o.precision);
-    if (e) return e;
-    HIP_TRY(hipEventRecord(h->ev[3], st));
-    // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
-    double t = o.t0;
-    bool fallback = false, accepted = false;
-    for (;;) {
-      if (t < o.t_floor && !fallback) {
-        double tf = 0.0;
-        e = cond_fallback_step(h, st, n, &tf);
-        if (e) return e;
-        t = std::min(t, tf);
-        fallback = true;
-        ++fallbacks;
-      }
-      if (t < o.t_min) break;
-      K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, lambda, t, w.At, w.Lt, w.part, w.flags + FLAG_FACTOR));
-      K_TRY(potrf_lower(st, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.flags + FLAG_FACTOR));
-      K_TRY(finish_trial(st, w.part, tiles, w.dL, w.dLt, w.flags + FLAG_FACTOR, n, lambda, w.scal));
-      e = fetch(h, st);
-      if (e) return e;
-      ++trials;
-      if (host_flag(h, FLAG_FACTOR) == 0 && h->host[SC_DF] < 0.0) {
-        accepted = true;
-        break;
-      }
-      t *= o.shrink;
-    }
-    HIP_TRY(hipEventRecord(h->ev[4], st));
-    HIP_TRY(hipEventSynchronize(h->ev[4]));
-    phase[3] += elapsed(h->ev[2], h->ev[3]);
-    phase[4] += elapsed(h->ev[3], h->ev[4]);
-    if (!accepted) {
-      status = GLASSO_LS_FAILED;
-      break;
-    }
-    // a7: accept
-    std::swap(w.A, w.At);
-    std::swap(w.L, w.Lt);
-    std::swap(w.dL, w.dLt);
-    std::swap(w.Dinv, w.Dinvt);
-    ++it;
-  }
-
-  K_TRY(sym_copy_out(st, w.A, np, A, n, 0));
-  if (W) K_TRY(sym_copy_out(st, w.W, np, W, n, 1));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (info) {
-    memset(info, 0, sizeof(*info));
-    info->objective = h->host[SC_OBJECTIVE];
-    info->kkt_rel1 = h->host[SC_KKT_REL1];
-    info->kkt_fro = h->host[SC_KKT_FRO];
-    info->kkt_max = h->host[SC_MAX_ABS_Z];
-    info->nnz = (int64_t)llround(h->host[SC_NNZ_A]);
-    info->iterations = it;
-    info->ls_trials = trials;
-    info->status = status;
-    info->fallback_steps = fallbacks;
-    for (int i = 1; i < 8; ++i) info->time_ms[i] = phase[i];
-    info->time_ms[0] =
-        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (info)
+      for (size_t k = 0; k < idx.size(); ++k) info[idx[k]] = ig[k];
   }
   return GLASSO_OK;
 }
@@ -412,20 +621,20 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
   if (!h || !A || !L || n < 1) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
+  glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.L, nullptr, 1));
-  int finfo = 0;
-  e = factor_current(h, st, &finfo);
+  e = factor_all(h, st);
   if (e) return e;
+  const int finfo = h->hm.info[0];
   if (info) *info = finfo;
   K_TRY(sym_copy_out(st, w.L, np, L, n, 2));
   if (logdet) {
     K_TRY(sum_log(st, w.dL, n, w.scal + SC_LOGDET));
     e = fetch(h, st);
     if (e) return e;
-    *logdet = finfo ? NAN : h->host[SC_LOGDET];
+    *logdet = finfo ? NAN : hscal(h, 0, SC_LOGDET);
   }
   HIP_TRY(hipStreamSynchronize(st));
   return GLASSO_OK;
@@ -435,15 +644,14 @@ glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W
   if (!h || !A || !W || n < 1) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
+  glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.L, nullptr, 1));
-  int finfo = 0;
-  e = factor_current(h, st, &finfo);
+  e = factor_all(h, st);
   if (e) return e;
-  if (finfo) return GLASSO_ERR_NOT_PD;
-  e = inverse_from_factor(w, st);
+  if (h->hm.info[0]) return GLASSO_ERR_NOT_PD;
+  e = inverse_from_factor(w, st, nullptr);
   if (e) return e;
   K_TRY(sym_copy_out(st, w.W, np, W, n, 1));
   HIP_TRY(hipStreamSynchronize(st));
@@ -455,7 +663,7 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
   if (!h || !S || !W || !A || !Z || !GM || n < 1 || !(lambda > 0.0)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
+  glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, S, n, np, w.S, nullptr, 0));
@@ -468,10 +676,10 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
   e = fetch(h, st);
   if (e) return e;
   if (kkt) {
-    kkt[0] = h->host[SC_SUM_ABS_Z];
-    kkt[1] = h->host[SC_SUM_ABS_A];
-    kkt[2] = h->host[SC_KKT_FRO];
-    kkt[3] = h->host[SC_MAX_ABS_Z];
+    kkt[0] = hscal(h, 0, SC_SUM_ABS_Z);
+    kkt[1] = hscal(h, 0, SC_SUM_ABS_A);
+    kkt[2] = hscal(h, 0, SC_KKT_FRO);
+    kkt[3] = hscal(h, 0, SC_MAX_ABS_Z);
   }
   return GLASSO_OK;
 }
@@ -482,12 +690,12 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
   if (precision != GLASSO_FP64 && precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
+  glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
   K_TRY(pad_copy_f64(st, Z, n, np, w.Z, nullptr, 0));
-  e = precond_product(w, st, precision);
+  e = precond_product(w, st, precision, nullptr);
   if (e) return e;
   K_TRY(sym_copy_out(st, w.P, np, P, n, 1));
   HIP_TRY(hipStreamSynchronize(st));
@@ -499,22 +707,22 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
   if (!h || !A || !P || !S || !GM || !At || n < 1 || !(lambda > 0.0) || !(t > 0.0)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, np);
+  glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
   K_TRY(pad_copy_f64(st, P, n, np, w.P, nullptr, 0));
   K_TRY(pad_copy_f64(st, S, n, np, w.S, nullptr, 0));
   K_TRY(pad_copy_i8(st, GM, n, np, w.GM));
-  K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, lambda, t, w.At, w.Lt, w.part, w.flags + FLAG_FACTOR));
+  K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, lambda, t, w.At, w.Lt, w.part, w.info));
   // no factor: the log-ratio term reads the same diagonal twice and vanishes
-  K_TRY(finish_trial(st, w.part, (int)pass_tiles(np), w.dL, w.dL, w.flags + FLAG_FACTOR, 0, lambda, w.scal));
+  K_TRY(finish_trial(st, w.part, (int)pass_tiles(np), w.dL, w.dL, w.info, 0, lambda, w.scal));
   K_TRY(sym_copy_out(st, w.At, np, At, n, 0));
   e = fetch(h, st);
   if (e) return e;
   if (sums) {
-    sums[0] = h->host[SC_DTR];
-    sums[1] = h->host[SC_DL1];
+    sums[0] = hscal(h, 0, SC_DTR);
+    sums[1] = hscal(h, 0, SC_DL1);
   }
   return GLASSO_OK;
 }

@@ -9,33 +9,53 @@
 
 namespace glasso {
 
+// A batch of independent problems of equal padded size: problem z uses
+// operands offset by z * stride (elements) and abort/skip flag [z].
+struct ZBatch {
+  int count = 1;
+  int64_t sA = 0, sB = 0, sC = 0;
+};
+
 // ---------------------------------------------------------------- dense kernels
 int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag,
-             int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0, int role = 0);
+             int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0, int role = 0,
+             const ZBatch& zb = ZBatch());
 
 // C = A B^T on FP32 MFMA with FP32 accumulation (A: M x K, B: N x K, row-major
 // FP32); C is float or (c_is_double) double; lower_out as in gemm_f64.
 int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda,
                 const float* B, int64_t ldb, void* C, int64_t ldc, int c_is_double,
-                int lower_out);
+                int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr);
 int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
+
+// Strides (elements) between the problems of a batched factorisation: the
+// matrix, its diagonal vector and its diagonal-block inverses.
+struct FactorBatch {
+  int count = 1;
+  int64_t sA = 0, sdL = 0, sDinv = 0;
+};
 
 // In-place lower Cholesky of the n x n (n multiple of 128) matrix A.  Writes the
 // diagonal of L to dL, the inverses of its 128x128 diagonal blocks to Dinv
 // (n/128 blocks of 128x128, zeros above the diagonal) and, on a non-positive or
-// non-finite pivot, info = global column + 1 (later kernels then skip).
+// non-finite pivot, info = global column + 1.  A problem whose info is nonzero
+// on entry (or becomes nonzero) is skipped by every later kernel.  info has one
+// entry per problem of the batch.
 int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv,
-                int* info);
+                int* info, const FactorBatch& fb = FactorBatch());
 
 // In-place inverse of the lower-triangular n x n factor L given its diagonal-block
-// inverses (from potrf_lower).  tmp needs n*n/4 doubles.
+// inverses (from potrf_lower).  tmp needs n*n/4 doubles per problem (stride sTmp).
+// abort_flag (per problem, may be null) skips problems.
 int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* Dinv, double* tmp,
-                const int* abort_flag);
+                const int* abort_flag, const FactorBatch& fb = FactorBatch(), int64_t sTmp = 0);
 
 // W (lower triangle) = V^T V for lower-triangular V (the LAUUM product).
-int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int64_t ldw, int n);
+int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int64_t ldw, int n,
+                const int* abort_flag = nullptr, const FactorBatch& fb = FactorBatch(),
+                int64_t sW = 0);
 
 // ---------------------------------------------------------------- elementwise passes
 int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst, int64_t np,
@@ -48,14 +68,34 @@ int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, in
 int unpad_copy_i8(hipStream_t stream, const int8_t* src, int64_t np, int8_t* dst, int64_t n);
 int sum_log(hipStream_t stream, const double* d, int64_t n, double* out);
 // nlog: number of diagonal entries of the factor that enter log det (n in the solver)
+// Batch of problems for the elementwise passes (problem = grid.y): element
+// strides of S (0 = one shared S) and of the other np x np buffers, of the
+// diagonal vectors, and optional per-problem lambda, step size and skip flags
+// (device arrays; null = the scalar argument / no skipping).
+struct PassBatch {
+  int count = 1;
+  int64_t sS = 0, sM = 0, sV = 0;
+  const double* lam = nullptr;
+  const double* t = nullptr;
+  const int* skip = nullptr;
+};
+
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A,
               const double* dL, int64_t n, int64_t nlog, int64_t np, double lam, double* Z,
-              int8_t* GM, double* part, double* scal);
+              int8_t* GM, double* part, double* scal, const PassBatch& pb = PassBatch());
+// info_reset[b] is set to 0 for the problems the pass handles and to -1 for the
+// skipped ones, so that the Cholesky that follows skips them too.
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S,
                const int8_t* GM, int64_t n, int64_t np, double lam, double t, double* At,
-               double* Lt, double* part, int* info_reset);
+               double* Lt, double* part, int* info_reset, const PassBatch& pb = PassBatch());
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL,
-                 const double* dLt, const int* info, int64_t n, double lam, double* scal);
+                 const double* dLt, const int* info, int64_t n, double lam, double* scal,
+                 const PassBatch& pb = PassBatch());
+// for every problem b with accept[b] != 0 copy the trial's A, factor, diagonal
+// and diagonal-block inverses over the current ones
+int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At,
+                  double* L, const double* Lt, double* dL, const double* dLt, double* Dinv,
+                  const double* Dinvt, int64_t np);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
 int mirror_lower(hipStream_t stream, double* M, int64_t np);

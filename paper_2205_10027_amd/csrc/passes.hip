@@ -64,10 +64,19 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
                                                         const double* __restrict__ A,
                                                         const double* __restrict__ dL, int64_t n,
                                                         int64_t np, double lam, double* __restrict__ Z,
-                                                        int8_t* __restrict__ GM, double* part, int T) {
+                                                        int8_t* __restrict__ GM, double* part, int T, PassBatch pb) {
   __shared__ double zt[64][65];
   __shared__ int8_t gt[64][68];
   __shared__ double sh[4];
+  const int pbi = blockIdx.y;
+  if (pb.skip && pb.skip[pbi]) return;
+  if (pb.lam) lam = pb.lam[pbi];
+  S += pbi * pb.sS;
+  W += pbi * pb.sM;
+  A += pbi * pb.sM;
+  Z += pbi * pb.sM;
+  GM += pbi * pb.sM;
+  part += (int64_t)pbi * gridDim.x * GRAD_PARTS;
   int ti, tj;
   lower_tile(xcd_remap(blockIdx.x, gridDim.x), T, ti, tj);
   const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
@@ -139,9 +148,15 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
 
 // fixed-order reduction of the gradient-pass partials, then KKT and F(A)
 __global__ __launch_bounds__(256) void finish_grad_kernel(const double* part, int nparts, const double* dL,
-                                                          int64_t nlog, double lam, double* scal) {
+                                                          int64_t nlog, double lam, double* scal, PassBatch pb) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
+  const int pbi = blockIdx.x;
+  if (pb.skip && pb.skip[pbi]) return;
+  if (pb.lam) lam = pb.lam[pbi];
+  part += (int64_t)pbi * nparts * GRAD_PARTS;
+  dL += pbi * pb.sV;
+  scal += (int64_t)pbi * SC_COUNT;
   double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
   for (int b = tid; b < nparts; b += 256) {
     const double* pp = part + (int64_t)b * GRAD_PARTS;
@@ -182,11 +197,23 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
                                                          const int8_t* __restrict__ GM, int64_t n, int64_t np,
                                                          double lam, double t, double* __restrict__ At,
                                                          double* __restrict__ Lt, double* part, int* info_reset,
-                                                         int T) {
+                                                         int T, PassBatch pb) {
   __shared__ double tt[64][65];
   __shared__ double di[64], dj[64];
   __shared__ double sh[4];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *info_reset = 0;
+  const int pbi = blockIdx.y;
+  const bool skipped = pb.skip && pb.skip[pbi];
+  if (blockIdx.x == 0 && threadIdx.x == 0) info_reset[pbi] = skipped ? -1 : 0;
+  if (skipped) return;
+  if (pb.lam) lam = pb.lam[pbi];
+  if (pb.t) t = pb.t[pbi];
+  A += pbi * pb.sM;
+  P += pbi * pb.sM;
+  S += pbi * pb.sS;
+  GM += pbi * pb.sM;
+  At += pbi * pb.sM;
+  Lt += pbi * pb.sM;
+  part += (int64_t)pbi * gridDim.x * TRIAL_PARTS;
   int ti, tj;
   lower_tile(xcd_remap(blockIdx.x, gridDim.x), T, ti, tj);
   const int tid = threadIdx.x, c = tid & 63, rw = tid >> 6;
@@ -255,10 +282,17 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
 // After the trial's Cholesky: dF = 2 sum log(L_ii / Lt_ii) + sum S(At-A) + lam sum(|At|-|A|).
 __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, int nparts, const double* dL,
                                                            const double* dLt, const int* info, int64_t n,
-                                                           double lam, double* scal) {
+                                                           double lam, double* scal, PassBatch pb) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
-  const int inf = *info;
+  const int pbi = blockIdx.x;
+  if (pb.skip && pb.skip[pbi]) return;
+  if (pb.lam) lam = pb.lam[pbi];
+  part += (int64_t)pbi * nparts * TRIAL_PARTS;
+  dL += pbi * pb.sV;
+  dLt += pbi * pb.sV;
+  scal += (int64_t)pbi * SC_COUNT;
+  const int inf = info[pbi];
   double t0 = 0.0, t1 = 0.0, t2 = 0.0, tl = 0.0;
   for (int b = tid; b < nparts; b += 256) {
     t0 += part[(int64_t)b * TRIAL_PARTS + 0];
@@ -448,7 +482,34 @@ __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict
   if (threadIdx.x == 0 && out) *out = nrm;
 }
 
+// Accept the trial of every problem b with accept[b] != 0: A_b <- At_b, L_b <- Lt_b
+// (np x np each), dL_b <- dLt_b (np), Dinv_b <- Dinvt_b (np x 128).
+__global__ void accept_kernel(const int* accept, double* A, const double* At, double* L, const double* Lt,
+                              double* dL, const double* dLt, double* Dinv, const double* Dinvt, int64_t nn,
+                              int64_t np) {
+  const int b = blockIdx.y;
+  if (!accept[b]) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t off = (int64_t)b * nn;
+  for (int64_t e = i0; e < nn; e += stride) {
+    A[off + e] = At[off + e];
+    L[off + e] = Lt[off + e];
+  }
+  for (int64_t e = i0; e < np * 128; e += stride) Dinv[(int64_t)b * np * 128 + e] = Dinvt[(int64_t)b * np * 128 + e];
+  for (int64_t e = i0; e < np; e += stride) dL[(int64_t)b * np + e] = dLt[(int64_t)b * np + e];
+}
+
 }  // namespace
+
+int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At, double* L,
+                  const double* Lt, double* dL, const double* dLt, double* Dinv, const double* Dinvt, int64_t np) {
+  const int64_t nn = np * np;
+  const int blocks = (int)std::min<int64_t>((nn + 255) / 256, 4096);
+  hipLaunchKernelGGL(accept_kernel, dim3(blocks, count), dim3(256), 0, stream, accept, A, At, L, Lt, dL, dLt, Dinv,
+                     Dinvt, nn, np);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst, int64_t np,
                    int64_t* bad_count_dev, double lam, int check) {
@@ -491,26 +552,30 @@ int sum_log(hipStream_t stream, const double* d, int64_t n, double* out) {
 }
 
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A, const double* dL, int64_t n,
-              int64_t nlog, int64_t np, double lam, double* Z, int8_t* GM, double* part, double* scal) {
+              int64_t nlog, int64_t np, double lam, double* Z, int8_t* GM, double* part, double* scal,
+              const PassBatch& pb) {
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
-  hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z, GM, part, T);
-  hipLaunchKernelGGL(finish_grad_kernel, dim3(1), dim3(256), 0, stream, part, tiles, dL, nlog, lam, scal);
+  hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z, GM,
+                     part, T, pb);
+  hipLaunchKernelGGL(finish_grad_kernel, dim3(pb.count), dim3(256), 0, stream, part, tiles, dL, nlog, lam, scal, pb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S, const int8_t* GM, int64_t n,
-               int64_t np, double lam, double t, double* At, double* Lt, double* part, int* info_reset) {
+               int64_t np, double lam, double t, double* At, double* Lt, double* part, int* info_reset,
+               const PassBatch& pb) {
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
-  hipLaunchKernelGGL(pass_trial_kernel, dim3(tiles), dim3(256), 0, stream, A, P, S, GM, n, np, lam, t, At, Lt,
-                     part, info_reset, T);
+  hipLaunchKernelGGL(pass_trial_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, A, P, S, GM, n, np, lam, t, At,
+                     Lt, part, info_reset, T, pb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL, const double* dLt,
-                 const int* info, int64_t n, double lam, double* scal) {
-  hipLaunchKernelGGL(finish_trial_kernel, dim3(1), dim3(256), 0, stream, part, nparts, dL, dLt, info, n, lam, scal);
+                 const int* info, int64_t n, double lam, double* scal, const PassBatch& pb) {
+  hipLaunchKernelGGL(finish_trial_kernel, dim3(pb.count), dim3(256), 0, stream, part, nparts, dL, dLt, info, n, lam,
+                     scal, pb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

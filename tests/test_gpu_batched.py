@@ -1,0 +1,87 @@
+"""Batched engine (glasso_solve_batched) and the regularisation path.
+
+* every problem of a batch is bitwise identical to its own glasso_solve (the
+  kernels treat the problems of a batch independently);
+* every lambda-path mode meets the FP64 acceptance bar against the oracle for
+  every lambda (the minimiser is unique, so the path mode cannot matter).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import device, support_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    device()
+    import paper_2205_10027_amd as g
+
+    return g
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_bitwise_equals_single(g, precision):
+    S, _ = synth.random_sparse_problem(300, 150, 3)
+    lm = synth.lambda_max(S)
+    lams = [0.6 * lm, 0.35 * lm, 0.2 * lm, 0.12 * lm]
+    St = to_dev(S)
+    s = g.Solver(precision=precision)
+    batch = s.solve_batched(St, lams, 1e-7)
+    for lam, rb in zip(lams, batch):
+        r1 = g.Solver(precision=precision).solve(St, lam, 1e-7)
+        assert rb.status == r1.status == g.CONVERGED
+        assert rb.iterations == r1.iterations and rb.ls_trials == r1.ls_trials
+        assert np.array_equal(to_host(rb.A), to_host(r1.A))
+        assert np.array_equal(to_host(rb.W), to_host(r1.W))
+        assert rb.objective == r1.objective
+
+
+def test_batch_of_different_sizes(g):
+    probs = [synth.chain_problem(130, 60, 0)[0], synth.random_sparse_problem(70, 40, 1)[0],
+             synth.chain_problem(130, 60, 2)[0], synth.random_sparse_problem(260, 100, 4)[0]]
+    lams = [0.2, 0.3 * synth.lambda_max(probs[1]), 0.25, 0.3 * synth.lambda_max(probs[3])]
+    Sts = [to_dev(S) for S in probs]
+    batch = g.Solver().solve_batched(Sts, lams, 1e-6)
+    for S, St, lam, rb in zip(probs, Sts, lams, batch):
+        r1 = g.Solver().solve(St, lam, 1e-6)
+        assert np.array_equal(to_host(rb.A), to_host(r1.A))
+        chk = oracle.check_solution(S, to_host(rb.A), lam)
+        assert chk["kkt_rel1"] <= 1e-6 * 1.0001
+
+
+@pytest.mark.parametrize("mode", ["independent", "sequential", "waves"])
+def test_lambda_path_modes(g, mode):
+    """A scaled-down path: one S (random sparse, n=130, m=65), 6 lambdas geometric
+    from lambda_max to lambda_max/10 (below that the oracle needs hundreds of
+    iterations per lambda on this rank-deficient S)."""
+    S, _ = synth.random_sparse_problem(130, 65, 5)
+    lams = list(synth.lambda_path(S, count=6, ratio=10.0))
+    tol = 1e-6
+    res = g.lambda_path(to_dev(S), lams, tol, mode=mode, waves=3)
+    assert len(res) == len(lams)
+    for lam, r in zip(lams, res):
+        assert r.status == g.CONVERGED
+        A = to_host(r.A)
+        ref = oracle.pista(S, lam, tol)
+        chk = oracle.check_solution(S, A, lam)
+        assert chk["kkt_rel1"] <= tol * 1.0001
+        assert abs(r.objective - ref.objective) <= 1e-8 * max(1.0, abs(ref.objective))
+        ref_chk = oracle.check_solution(S, ref.A, lam)
+        assert support_mismatch(A, ref.A, ref_chk["g"], lam) == 0
+    # the lambda_max end of the path is the diagonal solution, reached at once
+    assert res[0].iterations == 0
+    np.testing.assert_array_equal(to_host(res[0].A), np.diag(1.0 / (np.diag(S) + lams[0])))
+
+
+def test_batch_warm_start_not_pd(g):
+    S, _ = synth.chain_problem(64, 32, 1)
+    St = to_dev(S)
+    good = to_dev(np.eye(64))
+    bad = to_dev(-np.eye(64))
+    with pytest.raises(g.GlassoError) as e:
+        g.Solver(warm_start=True).solve_batched(St, [0.2, 0.3], 1e-6, A_list=[good, bad])
+    assert e.value.code == 2
