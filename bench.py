@@ -1,18 +1,24 @@
-"""Benchmark: time-to-KKT <= 1e-5 of pISTA on one MI355X.
+"""Benchmark of pISTA (graphical lasso) on one MI355X.
 
-Workload (default): chain precision (A_ii = 1.25, A_i,i+1 = -0.5), n = 10000,
-m = 5000 Gaussian samples (seed 0), S = X X^T / m already resident in HBM;
-one step = one solve at lambda = 0.1 and one at lambda = 0.2, each from the
-diagonal initialisation to ||Z||_1 <= 1e-5 ||A||_1.
+Headline (value): time-to-KKT <= 1e-5 on the chain workload n = 10000,
+m = 5000 (seed 0), lambda in {0.1, 0.2}: one step = one solve at each lambda,
+from the diagonal initialisation, with S already resident in HBM.  The form
+timed is --precision (default: the mixed FP32 form, whose factor, log det, PD
+test, W and KKT are FP64); the plain FP64 path is timed on the same workload
+and reported beside it (config.fp64_plain_s, config.speedup_vs_fp64).
 
-Prints one JSON line:
-  value          mean time-to-KKT per solve (seconds, lower is better)
-  roofline       the A Z A GEMMs (dominant kernel): algorithmic FP64 flops per
-                 launch / mean launch time from HIP events, vs the FP64 MFMA peak
-  cpu_baseline   the CPU oracle on the host cores: one pISTA iteration of the
-                 same problem, scaled by the GPU's iteration count
+Extra objects on the same line:
+  roofline      the A Z A GEMMs (dominant kernel): algorithmic flops per launch /
+                mean launch time from HIP events around the launches
+  batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
+                from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
+  serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
+                lambda = 0.3 lambda_max, mixed FP32: p50/p99 latency, solves/s
+  cpu_baseline  the CPU oracle on the host cores: one pISTA iteration of the
+                lambda = 0.2 chain problem, scaled by the GPU's iteration count
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64] [--workload chain10k|rs2000]
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+                    [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -25,37 +31,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
-FP32_PEAK_TFLOPS = 157.3
-BF16_PEAK_TFLOPS = 2500.0
-
-WORKLOADS = {
-    # name: (generator, n, m, seed, lambdas, tol)
-    "chain10k": ("chain", 10000, 5000, 0, (0.1, 0.2), 1e-5),
-    "rs2000": ("random_sparse", 2000, 1000, 0, None, 1e-5),
-}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_problem(name):
-    import synth
-
-    kind, n, m, seed, lams, tol = WORKLOADS[name]
-    if kind == "chain":
-        S, _ = synth.chain_problem(n, m, seed)
-    else:
-        S, _ = synth.random_sparse_problem(n, m, seed)
-        cfg = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))["random_sparse_n2000"]
-        lams = (cfg["lambda"],)
-    return S, n, m, seed, lams, tol
-
-
 def cpu_baseline(S, lam, gpu_iterations):
-    """Oracle on the host cores: initialisation + one full pISTA iteration (W, the
-    gradient pass, B, the line search), scaled by the GPU's iteration count."""
+    """Oracle on the host cores: one full pISTA iteration (W, gradient pass, B, line
+    search) of the same problem, scaled by the GPU's iteration count."""
     import oracle
 
     try:
@@ -67,38 +52,13 @@ def cpu_baseline(S, lam, gpu_iterations):
     t0 = time.perf_counter()
     r = oracle.pista(S, lam, 0.0, max_iter=1)
     dt = time.perf_counter() - t0
-    per_iter = dt  # init is a diagonal factor: negligible next to the dense iteration
-    est = per_iter * max(1, gpu_iterations)
-    return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 oracle iteration (lambda={lam}, {r.ls_trials} trial(s), {dt:.1f} s) "
-                      f"x {gpu_iterations} GPU iterations"}
+    return {"value": dt * max(1, gpu_iterations), "unit": "s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 oracle iteration of chain n={S.shape[0]} lambda={lam} ({r.ls_trials} trial, "
+                      f"{dt:.1f} s) x {gpu_iterations} GPU iterations"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--workload", default="chain10k", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not part of it",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_2205_10027_amd as g
-
-    dev = torch.device("cuda:0")
-    t = time.perf_counter()
-    S, n, m, seed, lams, tol = make_problem(args.workload)
-    log(f"[bench] generated S n={n} m={m} in {time.perf_counter() - t:.1f}s")
-    St = torch.from_numpy(S).to(dev)
-    solver = g.Solver(precision=args.precision)
+def time_chain(g, St, lams, tol, precision, steps, warmup, torch):
+    solver = g.Solver(precision=precision)
     A = torch.empty_like(St)
 
     def step():
@@ -106,40 +66,160 @@ def main():
         for lam in lams:
             res = solver.solve(St, lam, tol, A=A, want_W=False)
             if res.status != g.CONVERGED or not (res.kkt_rel1 <= tol):
-                raise RuntimeError(f"solve at lambda={lam} ended with {res.status_name}, kkt={res.kkt_rel1}")
+                raise RuntimeError(f"{precision} solve at lambda={lam}: {res.status_name}, kkt={res.kkt_rel1}")
             out.append(res)
         return out
 
-    for w in range(args.warmup):
+    for w in range(warmup):
         t = time.perf_counter()
         rs = step()
-        log(f"[bench] warmup {w}: {time.perf_counter() - t:.2f}s iters={[r.iterations for r in rs]}")
+        log(f"[bench] {precision} warmup {w}: {time.perf_counter() - t:.2f}s iters={[r.iterations for r in rs]}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
-    for k in range(args.steps):
+    for k in range(steps):
         rs = step()
         results.extend(rs)
-        log(f"[bench] step {k}: iters={[r.iterations for r in rs]} trials={[r.ls_trials for r in rs]} "
-            f"times={[round(r.time_ms[0] / 1000, 3) for r in rs]}s")
+        log(f"[bench] {precision} step {k}: iters={[r.iterations for r in rs]} "
+            f"trials={[r.ls_trials for r in rs]} times={[round(r.time_ms[0] / 1000, 3) for r in rs]}s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    solver.close()
+    return elapsed, results
+
+
+def bench_path(g, torch, dev):
+    """Regularisation path: independent batch (timed twice after a warmup) and
+    the sequential warm-started path (once)."""
+    import synth
+
+    S, _ = synth.random_sparse_problem(1000, 500, 0)
+    lams = list(synth.lambda_path(S, count=32, ratio=100.0))
+    St = torch.from_numpy(S).to(dev)
+    out = {"workload": "random sparse n=1000 m=500 seed 0, 32 lambdas lambda_max..lambda_max/100, tol 1e-5",
+           "precision": "fp64"}
+    modes = {}
+    for mode, reps in (("independent", 2), ("waves", 1), ("sequential", 1)):
+        if mode == "independent":
+            g.lambda_path(St, lams, 1e-5, mode=mode, max_iter=5000)  # warmup
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            if any(r.status != g.CONVERGED for r in res):
+                raise RuntimeError(f"path mode {mode}: not every lambda converged")
+            best = dt if best is None else min(best, dt)
+        modes[mode] = {"path_s": best, "solves_per_s": len(lams) / best,
+                       "iterations": sum(r.iterations for r in res)}
+        log(f"[bench] path {mode}: {best:.2f}s ({len(lams) / best:.1f} solves/s)")
+    out["modes"] = modes
+    out["solves_per_s"] = modes["independent"]["solves_per_s"]
+    out["speedup_vs_sequential"] = modes["sequential"]["path_s"] / modes["independent"]["path_s"]
+    return out
+
+
+def bench_serve(g, count, seed=0):
+    """Serving: closed-loop capacity, then Poisson replays at 0.5, 0.8, 1.0 x capacity."""
+    import numpy as np
+
+    import synth
+    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_footprint
+
+    t = time.perf_counter()
+    base = synth.serving_requests(count, seed, rate=1.0)
+    problems = []
+    for (_, n, rs) in base:
+        S, _ = synth.random_sparse_problem(n, n // 2, rs)
+        problems.append((n, S, 0.3 * synth.lambda_max(S)))
+    log(f"[bench] serving: generated {count} requests in {time.perf_counter() - t:.1f}s")
+    slots = 4
+    budget = 64 * 2**30
+    eng = GpuEngine(slots=slots, precision="fp32", tol=1e-5)
+
+    def requests(rate):
+        arr = [a / rate for (a, _, _) in base] if rate else [0.0] * count
+        return [Request(i, arr[i], n, S, lam) for i, (n, S, lam) in enumerate(problems)]
+
+    srv = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint)
+    srv.run(requests(None)[: min(8, count)], realtime=False)  # warmup
+    st = srv.run(requests(None), realtime=False)
+    capacity = st.solves_per_s
+    log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
+    out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2, lambda=0.3 lambda_max, "
+                       f"random sparse, mixed FP32, tol 1e-5, {slots} slots, HBM budget {budget >> 30} GiB",
+           "closed_loop_solves_per_s": capacity, "rates": {}}
+    for frac in (0.5, 0.8, 1.0):
+        rate = frac * capacity
+        st = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint).run(requests(rate))
+        out["rates"][f"{frac:.1f}x"] = {"arrival_rate_per_s": rate, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+                                        "solves_per_s": st.solves_per_s, "mean_in_flight": st.mean_active,
+                                        "peak_hbm_gib": st.peak_bytes / 2**30}
+        log(f"[bench] serving {frac:.1f}x: p50 {st.p50_ms:.1f} ms p99 {st.p99_ms:.1f} ms, {st.solves_per_s:.2f}/s")
+    eng.close()
+    r08 = out["rates"]["0.8x"]
+    out.update({"p50_ms": r08["p50_ms"], "p99_ms": r08["p99_ms"], "solves_per_s": r08["solves_per_s"]})
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--no-path", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-fp64-ref", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=120)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; runs on several GPUs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2205_10027_amd as g
+    import synth
+
+    dev = torch.device("cuda:0")
+    n, m, seed, lams, tol = 10000, 5000, 0, (0.1, 0.2), 1e-5
+    t = time.perf_counter()
+    S, _ = synth.chain_problem(n, m, seed)
+    log(f"[bench] generated S n={n} m={m} in {time.perf_counter() - t:.1f}s")
+    St = torch.from_numpy(S).to(dev)
+
+    elapsed, results = time_chain(g, St, lams, tol, args.precision, args.steps, args.warmup, torch)
     solves = args.steps * len(lams)
     value = elapsed / solves
 
     # roofline of the A Z A GEMMs: 2 launches per iteration, 3 n^3 algorithmic flops
-    # (A Z: 2n^3; lower triangle of (A Z) A: n^3)
+    # (A Z: 2n^3; lower triangle of (A Z) A: n^3), event-timed around the launches
     iters = sum(r.iterations for r in results)
     aza_ms = sum(r.time_ms[3] for r in results)
     launches = 2 * iters
-    avg_launch_s = aza_ms / 1000.0 / launches if launches else float("nan")
-    flops_per_launch = 1.5 * float(n) ** 3
-    achieved = flops_per_launch / avg_launch_s / 1e12 if launches else 0.0
-    peak = {"fp64": FP64_PEAK_TFLOPS, "fp32": FP32_PEAK_TFLOPS, "bf16x3": BF16_PEAK_TFLOPS}[args.precision]
-
+    avg_launch_s = aza_ms / 1000.0 / launches
+    achieved = 1.5 * float(n) ** 3 / avg_launch_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    kernel = ("gemm_f32_nt_kernel (X = A Z and tril(X A), FP32 MFMA; the event window also holds the "
+              "two FP64->FP32 conversions)" if args.precision == "fp32"
+              else "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A), FP64 MFMA)")
+    config = {"workload": f"chain n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
+              "precision": args.precision,
+              "iterations": [r.iterations for r in results[:len(lams)]],
+              "ls_trials": [r.ls_trials for r in results[:len(lams)]],
+              "solves_per_s": solves / elapsed}
+    if not args.no_fp64_ref and args.precision != "fp64":
+        e64, r64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
+        config["fp64_plain_s"] = e64 / len(lams)
+        config["fp64_plain_iterations"] = [r.iterations for r in r64]
+        config["speedup_vs_fp64"] = (e64 / len(lams)) / value
     line = {
-        "metric": "time-to-KKT<=1e-5 at n=10k (FP64 plain)" if args.workload == "chain10k"
-        else f"time-to-KKT<=1e-5, {args.workload}",
+        "metric": "time-to-KKT<=1e-5 at n=10k (vs FP64 plain); batched solves/s; serving p50/p99",
         "value": value,
         "unit": "s",
         "n_gpus": 1,
@@ -149,25 +229,22 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else f"{args.precision}+f64",
+        "dtype": "f64" if args.precision == "fp64" else "fp32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
-                   "precision": args.precision,
-                   "iterations": [r.iterations for r in results[:len(lams)]],
-                   "ls_trials": [r.ls_trials for r in results[:len(lams)]],
-                   "solves_per_s": solves / elapsed},
+        "config": config,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "gemm_f64_kernel<0,0,1> (A Z and tril((A Z) A))",
+                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
                      "avg_launch_ms": avg_launch_s * 1000.0, "launches": launches},
     }
+    if not args.no_path:
+        line["batched"] = bench_path(g, torch, dev)
+    if not args.no_serve:
+        line["serving"] = bench_serve(g, args.serve_requests)
     if not args.no_cpu_baseline:
         lam = lams[-1]
-        gpu_it = results[len(lams) - 1].iterations
         t = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(S, lam, gpu_it)
+        line["cpu_baseline"] = cpu_baseline(S, lam, results[len(lams) - 1].iterations)
         log(f"[bench] cpu baseline sample took {time.perf_counter() - t:.1f}s")
-    solver.close()
     print(json.dumps(line), flush=True)
 
 
