@@ -32,6 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# HBM bytes per A Z A launch (mean of the two launches), from FETCH_SIZE and WRITE_SIZE
+# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_gemm_f32_chain10k.md).
+# Valid for the FP32 GEMM kernel as profiled; None where no counters were taken.
+TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None}
 
 
 def log(*a):
@@ -175,6 +179,8 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run 3 plain device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; runs on several GPUs are not part of it",
@@ -187,6 +193,13 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(args.copy_calibration * 2**20 // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     n, m, seed, lams, tol = 10000, 5000, 0, (0.1, 0.2), 1e-5
     t = time.perf_counter()
     S, _ = synth.chain_problem(n, m, seed)
@@ -198,16 +211,16 @@ def main():
     value = elapsed / solves
 
     # roofline of the A Z A GEMMs: 2 launches per iteration, 3 n^3 algorithmic flops
-    # (A Z: 2n^3; lower triangle of (A Z) A: n^3), event-timed around the launches
+    # (A Z: 2n^3; lower triangle of (A Z) A: n^3), HIP events on the solve's stream
+    # around the two GEMM launches alone
     iters = sum(r.iterations for r in results)
-    aza_ms = sum(r.time_ms[3] for r in results)
+    aza_ms = sum(r.time_ms[5] for r in results)
     launches = 2 * iters
     avg_launch_s = aza_ms / 1000.0 / launches
     achieved = 1.5 * float(n) ** 3 / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    kernel = ("gemm_f32_nt_kernel (X = A Z and tril(X A), FP32 MFMA; the event window also holds the "
-              "two FP64->FP32 conversions)" if args.precision == "fp32"
-              else "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A), FP64 MFMA)")
+    kernel = ("gemm_f32_nt_kernel<float> (X = A Z) and <double> (tril(X A)), FP32 MFMA"
+              if args.precision == "fp32" else "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A)), FP64 MFMA")
     config = {"workload": f"chain n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
               "precision": args.precision,
               "iterations": [r.iterations for r in results[:len(lams)]],
@@ -233,7 +246,7 @@ def main():
         "data": "synthetic",
         "config": config,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "frac": achieved / peak, "traffic": TRAFFIC_BYTES[args.precision], "traffic_unit": "B", "kernel": kernel,
                      "avg_launch_ms": avg_launch_s * 1000.0, "launches": launches},
     }
     if not args.no_path:

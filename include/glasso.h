@@ -73,7 +73,8 @@ typedef struct {
   int ls_trials;    /* trial points factored by the line search, over all iterations */
   int status;       /* glasso_status */
   int fallback_steps; /* line searches that reached t_floor and used the cond-based step */
-  double time_ms[8];  /* [0] total, [1] W = A^-1, [2] gradient pass, [3] A Z A, [4] line search */
+  double time_ms[8];  /* [0] total, [1] W = A^-1, [2] gradient pass, [3] A Z A,
+                        [4] line search, [5] the two A Z A GEMM launches alone */
 } glasso_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -96,7 +96,7 @@ struct glasso_handle_s {
   int device = 0;
   Workspace ws;
   HostMirror hm;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[8] = {};
 };
 
 namespace {
@@ -244,15 +244,19 @@ glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
 // P = tril(X A^T) (A symmetric).  Mixed FP32: A and Z are rounded to FP32 (A32,
 // Z32 in the X buffer), X32 = A32 Z32^T overwrites Z (no longer needed), and
 // P = tril(X32 A32^T) is written in FP64.
-glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip) {
+// gev (optional): two events recorded around the two GEMM launches only
+glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip,
+                           hipEvent_t* gev = nullptr) {
   const int np = (int)w.np;
   const int64_t nn = w.nn();
   ZBatch z;
   z.count = w.count;
   z.sA = z.sB = z.sC = nn;
   if (precision == GLASSO_FP64) {
+    if (gev) HIP_TRY(hipEventRecord(gev[0], st));
     K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.A, np, w.Z, np, 0.0, w.X, np, 0, 0, 0, skip, 1, 0, 0, 0, 1, z));
     K_TRY(gemm_f64(st, 0, 0, np, np, np, 1.0, w.X, np, w.A, np, 0.0, w.P, np, 1, 0, 0, skip, 1, 0, 0, 0, 1, z));
+    if (gev) HIP_TRY(hipEventRecord(gev[1], st));
     return GLASSO_OK;
   }
   if (precision == GLASSO_MIXED_FP32) {
@@ -268,6 +272,7 @@ glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const in
     z1.sA = 2 * nn;
     z1.sB = 2 * nn;
     z1.sC = 2 * nn;  // floats: X32 of problem b inside Z's doubles at b * nn doubles
+    if (gev) HIP_TRY(hipEventRecord(gev[0], st));
     K_TRY(gemm_f32_nt(st, np, np, np, X32buf, np, X32buf + nn, np, X32, np, 0, 0, z1, skip));
     ZBatch z2;  // P = tril(X32 A32^T)
     z2.count = w.count;
@@ -275,6 +280,7 @@ glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const in
     z2.sB = 2 * nn;
     z2.sC = nn;
     K_TRY(gemm_f32_nt(st, np, np, np, X32, np, X32buf, np, w.P, np, 1, 1, z2, skip));
+    if (gev) HIP_TRY(hipEventRecord(gev[1], st));
     return GLASSO_OK;
   }
   return GLASSO_ERR_INVALID_ARG;
@@ -396,7 +402,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (e) return e;
     // a3: P = A Z A
     HIP_TRY(hipEventRecord(h->ev[2], st));
-    e = precond_product(w, st, o.precision, w.skip);
+    e = precond_product(w, st, o.precision, w.skip, h->ev + 5);
     if (e) return e;
     HIP_TRY(hipEventRecord(h->ev[3], st));
     // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
@@ -464,6 +470,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     HIP_TRY(hipEventSynchronize(h->ev[4]));
     phase[3] += elapsed(h->ev[2], h->ev[3]);
     phase[4] += elapsed(h->ev[3], h->ev[4]);
+    phase[5] += elapsed(h->ev[5], h->ev[6]);
   }
 
   for (int b = 0; b < count; ++b) {
