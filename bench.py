@@ -3,9 +3,10 @@
 Headline (value): time-to-KKT <= 1e-5 on the chain workload n = 10000,
 m = 5000 (seed 0), lambda in {0.1, 0.2}: one step = one solve at each lambda,
 from the diagonal initialisation, with S already resident in HBM.  The form
-timed is --precision (default: the mixed FP32 form, whose factor, log det, PD
-test, W and KKT are FP64); the plain FP64 path is timed on the same workload
-and reported beside it (config.fp64_plain_s, config.speedup_vs_fp64).
+timed is --precision (default: the BF16x3 mixed form, A Z A as three BF16
+products; its factor, log det, PD test, W and KKT are FP64); the plain FP64 path
+is timed on the same workload and reported beside it (config.fp64_plain_s,
+config.speedup_vs_fp64).
 
 Extra objects on the same line:
   roofline      the A Z A GEMMs (dominant kernel): algorithmic flops per launch /
@@ -17,7 +18,7 @@ Extra objects on the same line:
   cpu_baseline  the CPU oracle on the host cores: one pISTA iteration of the
                 lambda = 0.2 chain problem, scaled by the GPU's iteration count
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+    python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
                     [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -31,11 +32,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# dense MFMA peaks; BF16x3 spends three BF16 products per algorithmic product, so its
+# peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 # HBM bytes per A Z A launch (mean of the two launches), from FETCH_SIZE and WRITE_SIZE
 # counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_gemm_f32_chain10k.md).
 # Valid for the FP32 GEMM kernel as profiled; None where no counters were taken.
-TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None}
+TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None, "bf16x3": None}
 
 
 def log(*a):
@@ -173,7 +176,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-path", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-fp64-ref", action="store_true")
@@ -219,8 +222,10 @@ def main():
     avg_launch_s = aza_ms / 1000.0 / launches
     achieved = 1.5 * float(n) ** 3 / avg_launch_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    kernel = ("gemm_f32_nt_kernel<float> (X = A Z) and <double> (tril(X A)), FP32 MFMA"
-              if args.precision == "fp32" else "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A)), FP64 MFMA")
+    kernel = {"fp32": "gemm_f32_nt_kernel<float> (X = A Z) and <double> (tril(X A)), FP32 MFMA",
+              "fp64": "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A)), FP64 MFMA",
+              "bf16x3": "gemm_bf16x3_nt_kernel<0> (X = A Z) and <1> (tril(X A)), three BF16 MFMA products"
+              }[args.precision]
     config = {"workload": f"chain n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
               "precision": args.precision,
               "iterations": [r.iterations for r in results[:len(lams)]],
@@ -242,7 +247,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "fp32+f64",
+        "dtype": {"fp64": "f64", "fp32": "fp32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
         "data": "synthetic",
         "config": config,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

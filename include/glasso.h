@@ -49,7 +49,10 @@ typedef enum {
 typedef enum {
   GLASSO_FP64 = 0,        /* every step in FP64 */
   GLASSO_MIXED_FP32 = 1,  /* A Z A products in FP32 MFMA; factor, log det, PD test, W, KKT in FP64 */
-  GLASSO_MIXED_BF16X3 = 2 /* reserved: A Z A as three BF16 split products (not accepted yet) */
+  GLASSO_MIXED_BF16X3 = 2 /* A Z A with each operand split into two BF16 parts, x = hi + lo, and each
+                             product formed as hi hi + hi lo + lo hi on BF16 MFMA with FP32
+                             accumulation (about 2^-16 relative); factor, log det, PD test, W,
+                             KKT in FP64 */
 } glasso_precision;
 
 typedef struct {

@@ -204,8 +204,10 @@ glasso_err push_doubles(hipStream_t st, double* dev, const double* host, int cou
   return GLASSO_OK;
 }
 
+bool valid_precision(int p) { return p == GLASSO_FP64 || p == GLASSO_MIXED_FP32 || p == GLASSO_MIXED_BF16X3; }
+
 glasso_err check_options(const glasso_options* o) {
-  if (o->precision != GLASSO_FP64 && o->precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
+  if (!valid_precision(o->precision)) return GLASSO_ERR_INVALID_ARG;
   if (o->max_iter < 0) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
@@ -280,6 +282,28 @@ glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const in
     z2.sB = 2 * nn;
     z2.sC = nn;
     K_TRY(gemm_f32_nt(st, np, np, np, X32, np, X32buf, np, w.P, np, 1, 1, z2, skip));
+    if (gev) HIP_TRY(hipEventRecord(gev[1], st));
+    return GLASSO_OK;
+  }
+  if (precision == GLASSO_MIXED_BF16X3) {
+    // split A and Z (4 bytes per element) share the X buffer: A of problem b at
+    // b * 2nn elements, Z after it; the split X = A Z is written over Z
+    uint8_t* As = reinterpret_cast<uint8_t*>(w.X);
+    uint8_t* Xs = reinterpret_cast<uint8_t*>(w.Z);
+    for (int b = 0; b < w.count; ++b) {
+      K_TRY(split_bf16x2(st, w.A + b * nn, As + 2 * b * nn * 4, nn));
+      K_TRY(split_bf16x2(st, w.Z + b * nn, As + (2 * b + 1) * nn * 4, nn));
+    }
+    ZBatch z1;  // Xs = A Z^T (Z symmetric)
+    z1.count = w.count;
+    z1.sA = z1.sB = z1.sC = 2 * nn;
+    if (gev) HIP_TRY(hipEventRecord(gev[0], st));
+    K_TRY(gemm_bf16x3_nt(st, np, np, np, As, np, As + nn * 4, np, Xs, np, 0, 0, z1, skip));
+    ZBatch z2;  // P = tril(X A^T)
+    z2.count = w.count;
+    z2.sA = z2.sB = 2 * nn;
+    z2.sC = nn;
+    K_TRY(gemm_bf16x3_nt(st, np, np, np, Xs, np, As, np, w.P, np, 1, 1, z2, skip));
     if (gev) HIP_TRY(hipEventRecord(gev[1], st));
     return GLASSO_OK;
   }
@@ -571,7 +595,7 @@ const char* glasso_error_string(glasso_err e) {
 }
 
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes) {
-  if (n < 1 || !bytes || (precision != GLASSO_FP64 && precision != GLASSO_MIXED_FP32)) return GLASSO_ERR_INVALID_ARG;
+  if (n < 1 || !bytes || !valid_precision(precision)) return GLASSO_ERR_INVALID_ARG;
   Workspace probe;
   *bytes = layout(probe, 1, pad_to_tile(n), nullptr);
   return GLASSO_OK;
@@ -694,7 +718,7 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
 glasso_err glasso_precond_product(glasso_handle h, const double* A, const double* Z, int64_t n, int precision,
                                   double* P, void* stream) {
   if (!h || !A || !Z || !P || n < 1) return GLASSO_ERR_INVALID_ARG;
-  if (precision != GLASSO_FP64 && precision != GLASSO_MIXED_FP32) return GLASSO_ERR_INVALID_ARG;
+  if (!valid_precision(precision)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);

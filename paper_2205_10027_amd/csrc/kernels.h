@@ -30,6 +30,16 @@ int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t
                 int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr);
 int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
 
+// C = A B^T as three BF16 products with FP32 accumulation; A (M x K) and B (N x K)
+// in the split layout of gemm_bf16x3.hip (4 bytes per element, row stride 4 ld
+// bytes).  C is written in split layout, or (c_is_double) as FP64; lower_out as
+// in gemm_f64 (FP64 output only).  ZBatch strides are in elements.
+int gemm_bf16x3_nt(hipStream_t stream, int M, int N, int K, const void* A, int64_t lda, const void* B,
+                   int64_t ldb, void* C, int64_t ldc, int c_is_double, int lower_out,
+                   const ZBatch& zb = ZBatch(), const int* skip = nullptr);
+// FP64 -> split layout (count a multiple of 8)
+int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count);
+
 // Strides (elements) between the problems of a batched factorisation: the
 // matrix, its diagonal vector and its diagonal-block inverses.
 struct FactorBatch {

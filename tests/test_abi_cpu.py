@@ -45,6 +45,10 @@ def test_host_only_entry_points():
     assert 9 * np_ * np_ * 8 < b < 9 * np_ * np_ * 8 + 2 * np_ * np_ + 64 * 2**20
     with pytest.raises(g.GlassoError):
         g.workspace_bytes(0)
+    # the mixed forms keep their reduced-precision operands inside the FP64 buffers
+    assert g.workspace_bytes(10000, "fp32") == g.workspace_bytes(10000, "bf16x3") == b
+    with pytest.raises(g.GlassoError):
+        g.workspace_bytes(100, 3)
     assert lib.glasso_create(None, None) == 1
 
 

@@ -23,7 +23,7 @@ def g():
     return g
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_batch_bitwise_equals_single(g, precision):
     S, _ = synth.random_sparse_problem(300, 150, 3)
     lm = synth.lambda_max(S)

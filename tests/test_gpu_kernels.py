@@ -61,18 +61,39 @@ def test_precond_product_fp32(solver, n):
     assert np.max(np.abs(P - ref)) > 0
 
 
-def test_precond_product_structure(solver):
-    """Identity and permutation cases pin the MFMA lane layout exactly."""
+@pytest.mark.parametrize("n", [5, 128, 300, 1024])
+def test_precond_product_bf16x3(solver, n):
+    """BF16x3 product.  Splitting x = hi + lo leaves |x - hi - lo| <= 2^-16 |x|
+    (two bf16 roundings, unit roundoff 2^-8 each); the dropped lo*lo term is
+    <= 2^-16 |a b|; so one product carries 3 * 2^-16 relative to |a||b| plus the
+    FP32 accumulation n u32.  X = A Z is split again (2^-16) before X A, so
+    |P - A Z A| <= (7 * 2^-16 + 2 (n + 2) u32) (|A||Z||A|), checked with factor 2 slack."""
+    A = sparse_sym(n, 1, density=0.3)
+    rng = np.random.default_rng(2)
+    Z = sym(rng.standard_normal((n, n)))
+    P = to_host(solver.precond_product(to_dev(A), to_dev(Z), precision="bf16x3"))
+    ref = A @ Z @ A
+    u32 = 2.0 ** -24
+    bound = 2 * (7 * 2.0 ** -16 + 2 * (n + 2) * u32) * (np.abs(A) @ np.abs(Z) @ np.abs(A)) + 1e-300
+    assert np.all(np.abs(P - ref) <= bound), np.max(np.abs(P - ref) / bound)
+    assert np.array_equal(P, P.T)
+    assert np.max(np.abs(P - ref)) > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_precond_product_structure(solver, precision):
+    """Identity and permutation cases pin the MFMA lane layout exactly (small
+    integers are exact in every form)."""
     n = 256
     rng = np.random.default_rng(3)
     Z = sym(rng.integers(-3, 4, size=(n, n)).astype(np.float64))
-    P = to_host(solver.precond_product(to_dev(np.eye(n)), to_dev(Z)))
+    P = to_host(solver.precond_product(to_dev(np.eye(n)), to_dev(Z), precision=precision))
     assert np.array_equal(P, Z)
     perm = rng.permutation(n)
     Pm = np.eye(n)[perm]
     Pm = sym(Pm + Pm.T)  # symmetric 0/1/2 matrix
-    P = to_host(solver.precond_product(to_dev(Pm), to_dev(Z)))
-    assert np.array_equal(P, Pm @ Z @ Pm)  # small integers: exact
+    P = to_host(solver.precond_product(to_dev(Pm), to_dev(Z), precision=precision))
+    assert np.array_equal(P, Pm @ Z @ Pm)
 
 
 # ------------------------------------------------------------------ Cholesky / inverse

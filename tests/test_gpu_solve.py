@@ -66,7 +66,7 @@ def test_random_sparse(g, n, seed, frac):
     check_against_oracle(g, S, lam, 1e-6)
 
 
-@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,seed,frac", [(130, 1, 0.25), (300, 2, 0.2)])
 def test_mixed_precision_meets_fp64_bar(g, precision, n, seed, frac):
     """Mixed forms: A Z A in reduced precision, everything that decides acceptance
@@ -76,9 +76,10 @@ def test_mixed_precision_meets_fp64_bar(g, precision, n, seed, frac):
     check_against_oracle(g, S, lam, 1e-6, solver=g.Solver(precision=precision))
 
 
-def test_mixed_chain(g):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_chain(g, precision):
     S, _ = synth.chain_problem(100, 50, 0)
-    res, ref = check_against_oracle(g, S, 0.2, 1e-6, solver=g.Solver(precision="fp32"))
+    res, ref = check_against_oracle(g, S, 0.2, 1e-6, solver=g.Solver(precision=precision))
 
 
 def test_n1_and_n2(g):
