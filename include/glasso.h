@@ -63,8 +63,15 @@ typedef struct {
   double t_floor;  /* below it, t = min(t, (0.9/cond A)^2) (Sec. 5); default 1e-4 */
   double t_min;    /* the line search fails below it; default 1e-12 */
   int warm_start;  /* nonzero: A holds the starting iterate (Alg. 1 takes A^(0)) */
-  int reserved;
+  int tile_policy; /* FP64 GEMM launches (Cholesky updates, triangular inverse, LAUUM,
+                      the FP64 A Z A) with fewer than this many 128x128 output tiles
+                      run 64x64 tiles; GLASSO_TILES_AUTO (the default): the value the
+                      autotuner measured for the padded size and batch count, tuned
+                      on first use and kept for the process.  Results are bitwise
+                      the same under every policy. */
 } glasso_options;
+
+#define GLASSO_TILES_AUTO (-1)
 
 typedef struct {
   double objective; /* F(A) of the returned A */
@@ -96,6 +103,16 @@ const char* glasso_error_string(glasso_err e);
 /* Device bytes of workspace a solve of size n needs with `precision` (for
  * admission by HBM footprint).  Errors: INVALID_ARG for n < 1 or bytes == NULL. */
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
+
+/* Tile autotuner: for problems of size n solved `count` at a time, time the
+ * Cholesky, triangular inverse and LAUUM (and, with opt.precision FP64, the
+ * A Z A product) of identity matrices under each candidate tile policy
+ * {0, 64, 256, 1024, never} and record the fastest for this device, padded size
+ * and count for the rest of the process (solves with GLASSO_TILES_AUTO use it).
+ * *policy (host, may be NULL) receives the choice.  Allocates the workspace for
+ * (n, count) like a solve; runs on `stream` and waits for it.
+ * Errors: INVALID_ARG (n < 1, count < 1), OOM, HIP. */
+glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, void* stream);
 
 /* Solve the graphical lasso for one S (Alg. 1 of the paper, Sec. 5 settings).
  *   S      n x n empirical covariance (device, read-only, lower triangle read)

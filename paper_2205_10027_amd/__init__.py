@@ -20,6 +20,7 @@ _lib = _native.load()
 FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
 CONVERGED, MAX_ITER, LS_FAILED = 0, 1, 2
+TILES_AUTO = -1  # tile policy chosen by the autotuner (GLASSO_TILES_AUTO)
 STATUS_NAMES = {CONVERGED: "converged", MAX_ITER: "max_iter", LS_FAILED: "ls_failed"}
 
 
@@ -82,7 +83,7 @@ class Solver:
 
     def __init__(self, precision: str | int = "fp64", max_iter: int = 500, t0: float = 1.0,
                  shrink: float = 0.5, t_floor: float = 1e-4, t_min: float = 1e-12,
-                 warm_start: bool = False):
+                 warm_start: bool = False, tile_policy: int = TILES_AUTO):
         opt = GlassoOptions()
         _check(_lib.glasso_default_options(ctypes.byref(opt)), "glasso_default_options")
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -92,6 +93,7 @@ class Solver:
         opt.t_floor = float(t_floor)
         opt.t_min = float(t_min)
         opt.warm_start = int(bool(warm_start))
+        opt.tile_policy = int(tile_policy)
         self.options = opt
         h = ctypes.c_void_p()
         _check(_lib.glasso_create(ctypes.byref(h), ctypes.byref(opt)), "glasso_create")
@@ -107,6 +109,14 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, n: int, count: int = 1, stream=None) -> int:
+        """Measure and record the GEMM tile policy for problems of size n solved
+        `count` at a time (glasso_autotune); returns the chosen threshold."""
+        pol = ctypes.c_int()
+        _check(_lib.glasso_autotune(self._h, int(n), int(count), ctypes.byref(pol), _stream(stream)),
+               "glasso_autotune")
+        return pol.value
 
     # ---------------------------------------------------------------- full solve
     def solve(self, S: torch.Tensor, lam: float, tol: float, A: torch.Tensor | None = None,

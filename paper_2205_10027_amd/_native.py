@@ -19,7 +19,7 @@ class GlassoOptions(ctypes.Structure):
         ("t_floor", ctypes.c_double),
         ("t_min", ctypes.c_double),
         ("warm_start", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("tile_policy", ctypes.c_int),
     ]
 
 
@@ -49,6 +49,7 @@ SIGNATURES = {
     "glasso_destroy": (_INT, [_VP]),
     "glasso_error_string": (ctypes.c_char_p, [_INT]),
     "glasso_workspace_size": (_INT, [_I64, _INT, ctypes.POINTER(ctypes.c_size_t)]),
+    "glasso_autotune": (_INT, [_VP, _I64, _INT, ctypes.POINTER(_INT), _VP]),
     "glasso_solve": (_INT, [_VP, _VP, _I64, _D, _D, _VP, _VP, ctypes.POINTER(GlassoInfo), _VP]),
     "glasso_solve_batched": (_INT, [_VP, _INT, ctypes.POINTER(_VP), ctypes.POINTER(_I64), ctypes.POINTER(_D), _D,
                                      ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(GlassoInfo), _VP]),

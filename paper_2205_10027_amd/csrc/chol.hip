@@ -260,7 +260,7 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
         // panel below the block: A21 <- A21 * inv(L11)^T (in place; one tile column)
         double* A21 = A + (int64_t)(k + NB) * lda + k;
         rc = gemm_f64(stream, 0, 0, rest, NB, NB, 1.0, A21, lda, Dinv + (int64_t)(k / NB) * NB * NB, NB,
-                      0.0, A21, lda, 0, 0, 2, info, 1, 0, 0, 0, 0, zT);
+                      0.0, A21, lda, 0, 0, 2, info, 1, 0, 0, 0, 0, zT, /*in_place=*/1);
         if (rc) return rc;
       }
       if (k + NB < K1) {

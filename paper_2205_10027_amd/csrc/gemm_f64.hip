@@ -20,9 +20,12 @@
 // a second one (strides zA, zB, zC), e.g. the groups of one problem and the
 // problems of a batch.
 //
-// Workgroup: 256 threads = 4 wave64s in a 2x2 arrangement, 128x128 output tile,
-// each wave owns 64x64 = 4x4 MFMA blocks (64 FP64 accumulators per lane).  BK=16
-// slices of op(A) and op(B) are double-buffered in LDS ([row][k], k contiguous).
+// Workgroup: 256 threads = 4 wave64s in a 2x2 arrangement.  Output tile 128x128
+// (each wave 64x64 = 4x4 MFMA blocks, 64 FP64 accumulators per lane) or, for
+// launches with too few tiles to fill the chip, 64x64 (each wave 2x2 blocks).
+// BK=16 slices of op(A) and op(B) are double-buffered in LDS ([row][k], k
+// contiguous).  Every output accumulates over k in the same order under both tile
+// edges, so the choice never changes a result.
 #include "common.h"
 #include "kernels.h"
 
@@ -30,8 +33,18 @@ namespace glasso {
 
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BK = 16;
 constexpr int LDK = BK + 2;  // 144-byte rows keep 16-byte alignment and spread banks
+
+// Tile edge T (128 or 64): 2x2 waves of (T/2)x(T/2); each thread stages R
+// doubles of each operand per BK slice.
+template <int T>
+struct Tile {
+  static constexpr int WT = T / 2;        // wave tile edge
+  static constexpr int NBLK = WT / 16;    // 16x16 MFMA blocks per wave edge
+  static constexpr int R = T * BK / 256;  // doubles per thread and operand slice
+  static constexpr int TPR = BK / R;      // threads per LDS row for k-contiguous loads
+};
 
 struct GemmF64Params {
   int M, N, K;
@@ -47,103 +60,61 @@ struct GemmF64Params {
   const int* abort_flag;
 };
 
-template <int TA>
-__device__ __forceinline__ void load_a(const GemmF64Params& p, const double* A, int m0, int kt,
-                                       int tid, double (&r)[8]) {
-  if (TA == 0) {
-    const int row = tid >> 1, kq = (tid & 1) * 8;
-    const double2* src = reinterpret_cast<const double2*>(A + (int64_t)(m0 + row) * p.lda + kt + kq);
+// Stage one T x BK slice of op(X) (rows r0.., k from kt) into registers.
+// TX = 0: X[row * ld + k] (k contiguous); TX = 1: X[k * ld + row] (one LDS row per
+// thread: coalesced loads along the rows, 16-byte LDS stores).  tri: 1 zeroes
+// k > row, 2 zeroes k < row; for the B operand the caller passes the mirrored code.
+template <int TX, int T>
+__device__ __forceinline__ void load_slice(const double* X, int64_t ld, int r0, int kt, int tid, int tri,
+                                           double (&r)[Tile<T>::R]) {
+  constexpr int R = Tile<T>::R, TPR = Tile<T>::TPR;
+  int row, k0;
+  if (TX == 0) {
+    row = tid / TPR;
+    k0 = (tid % TPR) * R;
+    const double2* src = reinterpret_cast<const double2*>(X + (int64_t)(r0 + row) * ld + kt + k0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = src[i];
+    for (int i = 0; i < R / 2; ++i) {
+      const double2 v = src[i];
       r[2 * i] = v.x;
       r[2 * i + 1] = v.y;
     }
-    if (p.a_tri) {
-      const int m = m0 + row;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = kt + kq + i;
-        if ((p.a_tri == 1 && k > m) || (p.a_tri == 2 && k < m)) r[i] = 0.0;
-      }
-    }
   } else {
-    // one LDS row (= one m) per thread: coalesced 8-byte loads along m, 16-byte LDS stores
-    const int mc = tid & 127, kh = (tid >> 7) * 8;
-    const double* src = A + (int64_t)(kt + kh) * p.lda + m0 + mc;
+    row = tid % T;
+    k0 = (tid / T) * R;
+    const double* src = X + (int64_t)(kt + k0) * ld + r0 + row;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = src[(int64_t)i * p.lda];
-    if (p.a_tri) {
-      const int m = m0 + mc;
+    for (int i = 0; i < R; ++i) r[i] = src[(int64_t)i * ld];
+  }
+  if (tri) {
+    const int m = r0 + row;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = kt + kh + i;
-        if ((p.a_tri == 1 && k > m) || (p.a_tri == 2 && k < m)) r[i] = 0.0;
-      }
+    for (int i = 0; i < R; ++i) {
+      const int k = kt + k0 + i;
+      if ((tri == 1 && k > m) || (tri == 2 && k < m)) r[i] = 0.0;
     }
   }
 }
 
-template <int TB>
-__device__ __forceinline__ void load_b(const GemmF64Params& p, const double* B, int n0, int kt,
-                                       int tid, double (&r)[8]) {
-  if (TB == 0) {
-    const int row = tid >> 1, kq = (tid & 1) * 8;
-    const double2* src = reinterpret_cast<const double2*>(B + (int64_t)(n0 + row) * p.ldb + kt + kq);
+template <int TX, int T>
+__device__ __forceinline__ void store_slice(double (*S)[LDK], int tid, const double (&r)[Tile<T>::R]) {
+  constexpr int R = Tile<T>::R, TPR = Tile<T>::TPR;
+  const int row = TX == 0 ? tid / TPR : tid % T;
+  const int k0 = TX == 0 ? (tid % TPR) * R : (tid / T) * R;
+  double2* dst = reinterpret_cast<double2*>(&S[row][k0]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double2 v = src[i];
-      r[2 * i] = v.x;
-      r[2 * i + 1] = v.y;
-    }
-    if (p.b_tri) {
-      const int n = n0 + row;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = kt + kq + i;
-        if ((p.b_tri == 1 && k < n) || (p.b_tri == 2 && k > n)) r[i] = 0.0;
-      }
-    }
-  } else {
-    const int nc = tid & 127, kh = (tid >> 7) * 8;
-    const double* src = B + (int64_t)(kt + kh) * p.ldb + n0 + nc;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = src[(int64_t)i * p.ldb];
-    if (p.b_tri) {
-      const int n = n0 + nc;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = kt + kh + i;
-        if ((p.b_tri == 1 && k < n) || (p.b_tri == 2 && k > n)) r[i] = 0.0;
-      }
-    }
-  }
-}
-
-// store a register slice into LDS laid out [row][k]
-template <int T>
-__device__ __forceinline__ void store_slice(double (*S)[LDK], int tid, const double (&r)[8]) {
-  if (T == 0) {
-    const int row = tid >> 1, kq = (tid & 1) * 8;
-    double2* dst = reinterpret_cast<double2*>(&S[row][kq]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[i] = make_double2(r[2 * i], r[2 * i + 1]);
-  } else {
-    const int mc = tid & 127, kh = (tid >> 7) * 8;
-    double2* dst = reinterpret_cast<double2*>(&S[mc][kh]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[i] = make_double2(r[2 * i], r[2 * i + 1]);
-  }
+  for (int i = 0; i < R / 2; ++i) dst[i] = make_double2(r[2 * i], r[2 * i + 1]);
 }
 
 // ROLE only separates instantiations in profiles: 0 = factorisation/inverse
 // updates, 1 = the preconditioned product A Z A.
-template <int TA, int TB, int ROLE>
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
+template <int TA, int TB, int ROLE, int T>
+__global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64Params p) {
   if (p.abort_flag && p.abort_flag[blockIdx.z]) return;
+  constexpr int WT = Tile<T>::WT, NBLK = Tile<T>::NBLK, R = Tile<T>::R;
 
-  __shared__ __attribute__((aligned(16))) double As[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BN][LDK];
+  __shared__ __attribute__((aligned(16))) double As[2][T][LDK];
+  __shared__ __attribute__((aligned(16))) double Bs[2][T][LDK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -151,62 +122,76 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
 
   // Contiguous tile ranges per XCD share operand panels in L2, but when the K
   // range depends on the tile (triangular operands) they would also give one XCD
-  // all the long tiles; those launches keep the hardware's round-robin order.
+  // all the long tiles; those launches keep the hardware's round-robin order and
+  // enumerate the tiles longest K range first, so the short ones fill the tail.
   const int L = (p.a_tri || p.b_tri) ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
-  if (p.lower_out)
-    lower_tile(L, p.tiles_m, ti, tj);
-  else
+  if (p.lower_out) {
+    lower_tile(L, p.tiles_m, ti, tj);  // bands from the top: longest first for LAUUM-type K >= row
+  } else if (p.a_tri) {
+    // K range grows with the tile row for a_tri = 1 (k <= m), shrinks for a_tri = 2
+    const int q = L / p.tiles_n;
+    tj = L - q * p.tiles_n;
+    ti = (p.a_tri == 1) ? p.tiles_m - 1 - q : q;
+  } else if (p.b_tri) {
+    // K range shrinks with the tile column for b_tri = 1 (k >= n), grows for b_tri = 2
+    const int q = L / p.tiles_m;
+    ti = L - q * p.tiles_m;
+    tj = (p.b_tri == 2) ? p.tiles_n - 1 - q : q;
+  } else {
     grouped_tile(L, p.tiles_m, p.tiles_n, ti, tj);
-  const int m0 = ti * BM, n0 = tj * BN;
+  }
+  const int m0 = ti * T, n0 = tj * T;
 
   const double* A = p.A + (int64_t)blockIdx.y * p.sA + (int64_t)blockIdx.z * p.zA;
   const double* B = p.B + (int64_t)blockIdx.y * p.sB + (int64_t)blockIdx.z * p.zB;
   double* C = p.C + (int64_t)blockIdx.y * p.sC + (int64_t)blockIdx.z * p.zC;
 
   int kbeg = 0, kend = p.K;
-  if (p.a_tri == 1) kend = min(kend, m0 + BM);
+  if (p.a_tri == 1) kend = min(kend, m0 + T);
   if (p.a_tri == 2) kbeg = max(kbeg, m0);
   if (p.b_tri == 1) kbeg = max(kbeg, n0);
-  if (p.b_tri == 2) kend = min(kend, n0 + BN);
+  if (p.b_tri == 2) kend = min(kend, n0 + T);
+  // op(B) is indexed [k][n]: its "lower" (zero for k < n) is the staged row's k < row
+  const int btri = p.b_tri == 1 ? 2 : (p.b_tri == 2 ? 1 : 0);
 
-  v4d acc[4][4];
+  v4d acc[NBLK][NBLK];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NBLK; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
   if (kbeg < kend) {
-    double ra[8], rb[8];
-    load_a<TA>(p, A, m0, kbeg, tid, ra);
-    load_b<TB>(p, B, n0, kbeg, tid, rb);
-    store_slice<TA>(As[0], tid, ra);
-    store_slice<TB>(Bs[0], tid, rb);
+    double ra[R], rb[R];
+    load_slice<TA, T>(A, p.lda, m0, kbeg, tid, p.a_tri, ra);
+    load_slice<TB, T>(B, p.ldb, n0, kbeg, tid, btri, rb);
+    store_slice<TA, T>(As[0], tid, ra);
+    store_slice<TB, T>(Bs[0], tid, rb);
     __syncthreads();
     int cur = 0;
     for (int kt = kbeg; kt < kend; kt += BK) {
       const bool more = kt + BK < kend;
       if (more) {
-        load_a<TA>(p, A, m0, kt + BK, tid, ra);
-        load_b<TB>(p, B, n0, kt + BK, tid, rb);
+        load_slice<TA, T>(A, p.lda, m0, kt + BK, tid, p.a_tri, ra);
+        load_slice<TB, T>(B, p.ldb, n0, kt + BK, tid, btri, rb);
       }
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
-        double af[4], bf[4];
+        double af[NBLK], bf[NBLK];
         const int kc = kk * 4 + (lane >> 4);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) af[i] = As[cur][wm * 64 + i * 16 + (lane & 15)][kc];
+        for (int i = 0; i < NBLK; ++i) af[i] = As[cur][wm * WT + i * 16 + (lane & 15)][kc];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][wn * 64 + j * 16 + (lane & 15)][kc];
+        for (int j = 0; j < NBLK; ++j) bf[j] = Bs[cur][wn * WT + j * 16 + (lane & 15)][kc];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < NBLK; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
       if (more) {
-        store_slice<TA>(As[cur ^ 1], tid, ra);
-        store_slice<TB>(Bs[cur ^ 1], tid, rb);
+        store_slice<TA, T>(As[cur ^ 1], tid, ra);
+        store_slice<TB, T>(Bs[cur ^ 1], tid, rb);
       }
       __syncthreads();
       cur ^= 1;
@@ -217,13 +202,13 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
   // (v_mfma_f64_16x16x4f64 output layout, checked on gfx950).
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NBLK; ++i) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
+    for (int j = 0; j < NBLK; ++j) {
+      const int col = n0 + wn * WT + j * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 64 + i * 16 + 4 * r + (lane >> 4);
+        const int row = m0 + wm * WT + i * 16 + 4 * r + (lane >> 4);
         double* dst = C + (int64_t)row * p.ldc + col;
         double v = alpha * acc[i][j][r];
         if (beta != 0.0) v += beta * (*dst);
@@ -233,21 +218,41 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(GemmF64Params p) {
   }
 }
 
+template <int T>
+void launch(int ta, int tb, int role, dim3 grid, hipStream_t stream, const GemmF64Params& p) {
+  dim3 block(256);
+  if (role == 1 && ta == 0 && tb == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 1, T>), grid, block, 0, stream, p);
+  else if (ta == 0 && tb == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 0, T>), grid, block, 0, stream, p);
+  else if (ta == 0 && tb == 1)
+    hipLaunchKernelGGL((gemm_f64_kernel<0, 1, 0, T>), grid, block, 0, stream, p);
+  else if (ta == 1 && tb == 0)
+    hipLaunchKernelGGL((gemm_f64_kernel<1, 0, 0, T>), grid, block, 0, stream, p);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<1, 1, 0, T>), grid, block, 0, stream, p);
+}
+
 }  // namespace
+
+namespace {
+thread_local int small_tile_below = 256;  // see set_gemm_f64_small_tile_below
+}
+
+void set_gemm_f64_small_tile_below(int tiles) { small_tile_below = tiles < 0 ? 0 : tiles; }
+int get_gemm_f64_small_tile_below() { return small_tile_below; }
 
 int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alpha,
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag, int batch,
-             int64_t sA, int64_t sB, int64_t sC, int role, const ZBatch& zb) {
+             int64_t sA, int64_t sB, int64_t sC, int role, const ZBatch& zb, int in_place) {
   if (M <= 0 || N <= 0 || batch <= 0 || zb.count <= 0) return 0;
-  if (M % BM || N % BN || K % BK || K < 0) return -1;
+  if (M % 128 || N % 128 || K % BK || K < 0) return -1;
   if (lower_out && M != N) return -1;
   GemmF64Params p;
   p.M = M;
   p.N = N;
   p.K = K;
-  p.tiles_m = M / BM;
-  p.tiles_n = N / BN;
   p.lower_out = lower_out;
   p.a_tri = a_tri;
   p.b_tri = b_tri;
@@ -266,18 +271,21 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
   p.zB = zb.sB;
   p.zC = zb.sC;
   p.abort_flag = abort_flag;
+  // 128x128 tiles unless the launch has too few of them to fill the chip; both
+  // tile edges accumulate every output in the same k order (bitwise equal results).
+  // An in-place product (C aliases A, N = 128) keeps 128-wide tiles: one workgroup
+  // must read a whole row block of A before it overwrites it.
+  const int64_t t128 = (int64_t)(lower_out ? (M / 128) * (M / 128 + 1) / 2 : (M / 128) * (N / 128)) * batch * zb.count;
+  if (in_place && N != 128) return -1;
+  const int T = (!in_place && t128 < small_tile_below) ? 64 : 128;
+  p.tiles_m = M / T;
+  p.tiles_n = N / T;
   const int tiles = lower_out ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
-  dim3 grid(tiles, batch, zb.count), block(256);
-  if (role == 1 && ta == 0 && tb == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 1>), grid, block, 0, stream, p);
-  else if (ta == 0 && tb == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<0, 0, 0>), grid, block, 0, stream, p);
-  else if (ta == 0 && tb == 1)
-    hipLaunchKernelGGL((gemm_f64_kernel<0, 1, 0>), grid, block, 0, stream, p);
-  else if (ta == 1 && tb == 0)
-    hipLaunchKernelGGL((gemm_f64_kernel<1, 0, 0>), grid, block, 0, stream, p);
+  dim3 grid(tiles, batch, zb.count);
+  if (T == 64)
+    launch<64>(ta, tb, role, grid, stream, p);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<1, 1, 0>), grid, block, 0, stream, p);
+    launch<128>(ta, tb, role, grid, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

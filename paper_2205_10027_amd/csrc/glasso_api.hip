@@ -8,7 +8,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "../../include/glasso.h"
@@ -208,7 +211,7 @@ bool valid_precision(int p) { return p == GLASSO_FP64 || p == GLASSO_MIXED_FP32 
 
 glasso_err check_options(const glasso_options* o) {
   if (!valid_precision(o->precision)) return GLASSO_ERR_INVALID_ARG;
-  if (o->max_iter < 0) return GLASSO_ERR_INVALID_ARG;
+  if (o->max_iter < 0 || o->tile_policy < GLASSO_TILES_AUTO) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -336,12 +339,96 @@ glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int b, int64_t n,
 // rounds: each round evaluates one trial step per searching problem, and each
 // problem backtracks on its own t, so every problem follows exactly the
 // sequential line search of the paper.
+// ------------------------------------------------------------------ tile autotuner
+// The FP64 GEMMs run 64x64 tiles for launches with fewer than `threshold`
+// 128x128 tiles.  The best threshold depends on the padded size and batch count
+// (how many tiles the skinny launches of the factorisation have); it is measured
+// once per (device, np, count) and kept for the process.  Results do not depend
+// on it (both tile edges accumulate every output in the same order).
+constexpr int TUNE_CANDIDATES[] = {0, 64, 256, 1024, 1 << 30};
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int>, int> g_tune;
+
+// Times factor + inverse (+ the FP64 A Z A) of identity matrices in the handle's
+// workspace under each candidate; the workspace contents are overwritten.
+glasso_err tune_tiles(glasso_handle h, hipStream_t st, int precision, int* chosen) {
+  Workspace& w = h->ws;
+  float best = 0.f;
+  int best_thr = TUNE_CANDIDATES[0];
+  bool have = false;
+  for (int thr : TUNE_CANDIDATES) {
+    set_gemm_f64_small_tile_below(thr);
+    float t_min = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+      K_TRY(fill_identity(st, w.L, w.np, w.count));
+      if (precision == GLASSO_FP64) {
+        K_TRY(fill_identity(st, w.A, w.np, w.count));
+        K_TRY(fill_identity(st, w.Z, w.np, w.count));
+      }
+      for (int b = 0; b < w.count; ++b) h->hm.info[b] = 0;
+      glasso_err e = push_ints(st, w.info, h->hm.info, w.count);
+      if (e) return e;
+      HIP_TRY(hipEventRecord(h->ev[0], st));
+      K_TRY(potrf_lower(st, w.L, w.np, (int)w.np, w.dL, w.Dinv, w.info, factor_batch(w)));
+      e = inverse_from_factor(w, st, nullptr);
+      if (e) return e;
+      if (precision == GLASSO_FP64) {
+        e = precond_product(w, st, precision, nullptr);
+        if (e) return e;
+      }
+      HIP_TRY(hipEventRecord(h->ev[1], st));
+      HIP_TRY(hipEventSynchronize(h->ev[1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+      if (rep == 0 || ms < t_min) t_min = ms;
+    }
+    if (!have || t_min < best) {
+      best = t_min;
+      best_thr = thr;
+      have = true;
+    }
+  }
+  *chosen = best_thr;
+  return GLASSO_OK;
+}
+
+// Set this thread's GEMM tile threshold for the handle's workspace shape: the
+// fixed policy of the options, else the tuned one (tuning now if unseen).
+// Call right after ensure_workspace and before the workspace is filled.
+glasso_err apply_tile_policy(glasso_handle h, hipStream_t st, int precision) {
+  if (h->opt.tile_policy >= 0) {
+    set_gemm_f64_small_tile_below(h->opt.tile_policy);
+    return GLASSO_OK;
+  }
+  const auto key = std::make_tuple(h->device, h->ws.np, h->ws.count);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      set_gemm_f64_small_tile_below(it->second);
+      return GLASSO_OK;
+    }
+  }
+  int thr = 0;
+  glasso_err e = tune_tiles(h, st, precision, &thr);
+  if (e) return e;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = thr;
+  }
+  set_gemm_f64_small_tile_below(thr);
+  return GLASSO_OK;
+}
+
 glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, const double* const* S,
                       const double* lam, double tol, double* const* Aout, double* const* Wout, glasso_info* info) {
   const auto t_start = std::chrono::steady_clock::now();
   const glasso_options& o = h->opt;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, count, np);
+  if (e) return e;
+  e = apply_tile_policy(h, st, o.precision);
   if (e) return e;
   Workspace& w = h->ws;
   HostMirror& hm = h->hm;
@@ -532,6 +619,7 @@ glasso_err glasso_default_options(glasso_options* opt) {
   if (!opt) return GLASSO_ERR_INVALID_ARG;
   memset(opt, 0, sizeof(*opt));
   opt->precision = GLASSO_FP64;
+  opt->tile_policy = GLASSO_TILES_AUTO;
   opt->max_iter = 500;
   opt->t0 = 1.0;
   opt->shrink = 0.5;
@@ -646,6 +734,22 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
   return GLASSO_OK;
 }
 
+glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, void* stream) {
+  if (!h || n < 1 || n > (1 << 20) || count < 1) return GLASSO_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  glasso_err e = ensure_workspace(h, count, pad_to_tile(n));
+  if (e) return e;
+  int thr = 0;
+  e = tune_tiles(h, st, h->opt.precision, &thr);
+  if (e) return e;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[std::make_tuple(h->device, h->ws.np, h->ws.count)] = thr;
+  }
+  if (policy) *policy = thr;
+  return GLASSO_OK;
+}
+
 // ------------------------------------------------------------------ step-level entry points
 glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* L, int64_t* info, double* logdet,
                            void* stream) {
@@ -653,6 +757,8 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);
+  if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.L, nullptr, 1));
@@ -677,6 +783,8 @@ glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
+  if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.L, nullptr, 1));
   e = factor_all(h, st);
@@ -695,6 +803,8 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);
+  if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, S, n, np, w.S, nullptr, 0));
@@ -723,6 +833,8 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);
   if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
+  if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
   K_TRY(pad_copy_f64(st, Z, n, np, w.Z, nullptr, 0));
@@ -739,6 +851,8 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
   glasso_err e = ensure_workspace(h, 1, np);
+  if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));

@@ -21,7 +21,13 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
              int64_t ldc, int lower_out, int a_tri, int b_tri, const int* abort_flag,
              int batch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0, int role = 0,
-             const ZBatch& zb = ZBatch());
+             const ZBatch& zb = ZBatch(), int in_place = 0);
+
+// Launches of gemm_f64 with fewer than `tiles` 128x128 output tiles (over the
+// whole grid, batch included) use 64x64 tiles instead.  Per calling thread (each
+// handle sets its own before its launches); results do not depend on it.
+void set_gemm_f64_small_tile_below(int tiles);
+int get_gemm_f64_small_tile_below();
 
 // C = A B^T on FP32 MFMA with FP32 accumulation (A: M x K, B: N x K, row-major
 // FP32); C is float or (c_is_double) double; lower_out as in gemm_f64.
@@ -108,6 +114,8 @@ int accept_trials(hipStream_t stream, const int* accept, int count, double* A, c
                   const double* Dinvt, int64_t np);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
+// X_b = identity for count consecutive np x np matrices
+int fill_identity(hipStream_t stream, double* X, int64_t np, int count);
 int mirror_lower(hipStream_t stream, double* M, int64_t np);
 int power_iteration(hipStream_t stream, const double* M, int64_t n, int64_t np, double* vec,
                     double* out, int iters);

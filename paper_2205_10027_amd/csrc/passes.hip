@@ -381,6 +381,15 @@ __global__ void unpad_copy_i8_kernel(const int8_t* __restrict__ src, int64_t np,
 }
 
 // out = 2 sum_{i<n} log d_i
+// X_b = I (np x np) for count problems at stride nn
+__global__ __launch_bounds__(256) void fill_identity_kernel(double* X, int64_t np, int64_t nn, int count) {
+  const int64_t total = nn * count;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = e % nn;
+    X[e] = (o / np == o % np) ? 1.0 : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void sum_log_kernel(const double* d, int64_t n, double* out) {
   __shared__ double sh[4];
   double s = 0.0;
@@ -543,6 +552,13 @@ int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, in
 
 int unpad_copy_i8(hipStream_t stream, const int8_t* src, int64_t np, int8_t* dst, int64_t n) {
   hipLaunchKernelGGL(unpad_copy_i8_kernel, dim3(grid_for(n * n)), dim3(256), 0, stream, src, np, dst, n);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int fill_identity(hipStream_t stream, double* X, int64_t np, int count) {
+  const int64_t total = np * np * count;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(fill_identity_kernel, dim3(blocks), dim3(256), 0, stream, X, np, np * np, count);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

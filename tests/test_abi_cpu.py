@@ -50,6 +50,17 @@ def test_host_only_entry_points():
     with pytest.raises(g.GlassoError):
         g.workspace_bytes(100, 3)
     assert lib.glasso_create(None, None) == 1
+    # option checks run before any device call
+    assert opt.tile_policy == g.TILES_AUTO == -1
+    h = ctypes.c_void_p()
+    bad = g.GlassoOptions()
+    lib.glasso_default_options(ctypes.byref(bad))
+    bad.tile_policy = -2
+    assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
+    lib.glasso_default_options(ctypes.byref(bad))
+    bad.precision = 3
+    assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
+    assert lib.glasso_autotune(None, 100, 1, None, None) == 1
 
 
 def test_struct_layout_matches_c():
@@ -61,7 +72,8 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+         offsetof(glasso_options, tile_policy),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
          offsetof(glasso_info, time_ms));
   return 0;
@@ -72,6 +84,7 @@ int main(void) {
         open(c, "w").write(src)
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, ctypes.sizeof(g.GlassoInfo),
+    want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, g.GlassoOptions.tile_policy.offset,
+            ctypes.sizeof(g.GlassoInfo),
             g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset]
     assert [int(x) for x in out] == want
