@@ -69,6 +69,11 @@ typedef struct {
                       autotuner measured for the padded size and batch count, tuned
                       on first use and kept for the process.  Results are bitwise
                       the same under every policy. */
+  int graphs;      /* nonzero: each launch sequence of an iteration (inverse + gradient
+                      pass, A Z A, trial point + Cholesky, accept) is captured once as
+                      a HIP graph per workspace shape and replayed; results are bitwise
+                      the same as eager launches.  time_ms[1] then holds [1] + [2], and
+                      time_ms[5] the whole A Z A sequence.  Default 0. */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)

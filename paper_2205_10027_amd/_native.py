@@ -20,6 +20,7 @@ class GlassoOptions(ctypes.Structure):
         ("t_min", ctypes.c_double),
         ("warm_start", ctypes.c_int),
         ("tile_policy", ctypes.c_int),
+        ("graphs", ctypes.c_int),
     ]
 
 

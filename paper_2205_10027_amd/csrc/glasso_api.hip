@@ -92,6 +92,23 @@ struct HostMirror {
   int64_t* bad = nullptr;
 };
 
+// Captured launch sequences of one engine iteration, valid for one workspace
+// shape (the kernels' pointer, size and launch arguments are baked in).
+struct GraphKey {
+  const void* base = nullptr;
+  const void* host = nullptr;
+  int64_t np = 0, n = 0, sS = 0;
+  int count = 0, precision = -1, tiles = -1;
+  bool operator==(const GraphKey& o) const {
+    return base == o.base && host == o.host && np == o.np && n == o.n && sS == o.sS && count == o.count &&
+           precision == o.precision && tiles == o.tiles;
+  }
+};
+struct Graphs {
+  GraphKey key;
+  hipGraphExec_t head = nullptr, prod = nullptr, trial = nullptr, acc = nullptr;
+};
+
 }  // namespace
 
 struct glasso_handle_s {
@@ -100,6 +117,8 @@ struct glasso_handle_s {
   Workspace ws;
   HostMirror hm;
   hipEvent_t ev[8] = {};
+  hipStream_t cap = nullptr;  // capture stream (graphs option)
+  Graphs graphs;
 };
 
 namespace {
@@ -188,12 +207,44 @@ FactorBatch factor_batch(const Workspace& w) {
   return fb;
 }
 
-// scalar slots and factor status of every problem -> pinned host memory, then wait
-glasso_err fetch(glasso_handle h, hipStream_t st) {
+// scalar slots and factor status of every problem -> pinned host memory
+glasso_err fetch_async(glasso_handle h, hipStream_t st) {
   const Workspace& w = h->ws;
   HIP_TRY(hipMemcpyAsync(h->hm.scal, w.scal, (size_t)w.count * SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(h->hm.info, w.info, (size_t)w.count * sizeof(int), hipMemcpyDeviceToHost, st));
+  return GLASSO_OK;
+}
+// ... and wait for it
+glasso_err fetch(glasso_handle h, hipStream_t st) {
+  glasso_err e = fetch_async(h, st);
+  if (e) return e;
   HIP_TRY(hipStreamSynchronize(st));
+  return GLASSO_OK;
+}
+
+void drop_graphs(Graphs& g) {
+  for (hipGraphExec_t* x : {&g.head, &g.prod, &g.trial, &g.acc})
+    if (*x) (void)hipGraphExecDestroy(*x);
+  g = Graphs();
+}
+
+// Record what body(stream) enqueues on the handle's capture stream as a graph.
+template <class F>
+glasso_err capture_graph(glasso_handle h, hipGraphExec_t* out, F&& body) {
+  HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  const glasso_err e = body(h->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(h->cap, &g);
+  if (e || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return e ? e : GLASSO_ERR_HIP;
+  }
+  const hipError_t ie = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    *out = nullptr;
+    return GLASSO_ERR_HIP;
+  }
   return GLASSO_OK;
 }
 double hscal(glasso_handle h, int b, int slot) { return h->hm.scal[(size_t)b * SC_COUNT + slot]; }
@@ -475,23 +526,85 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   pb.sM = nn;
   pb.sV = np;
   pb.lam = w.lam;
+  pb.skip = w.skip;
+  pb.t = nullptr;
+  PassBatch pt = pb;  // trial passes: problems still searching, their own t
+  pt.skip = w.lsskip;
+  pt.t = w.t;
+
+  // The four launch sequences of an iteration.  Each reads its host inputs from
+  // the pinned mirrors when it runs and ends without waiting; `timed` adds the
+  // phase events (eager runs only).
+  auto head = [&](hipStream_t s, bool timed) -> glasso_err {  // a1, a2
+    glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
+    if (e2) return e2;
+    if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
+    e2 = inverse_from_factor(w, s, w.skip);
+    if (e2) return e2;
+    if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
+    return fetch_async(h, s);
+  };
+  auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
+    glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
+    if (e2) return e2;
+    return precond_product(w, s, o.precision, w.skip, timed ? h->ev + 5 : nullptr);
+  };
+  auto trial = [&](hipStream_t s, bool) -> glasso_err {  // a4, a5
+    glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, count);
+    if (e2) return e2;
+    e2 = push_doubles(s, w.t, hm.t, count);
+    if (e2) return e2;
+    K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
+    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w)));
+    K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal, pt));
+    return fetch_async(h, s);
+  };
+  auto accept = [&](hipStream_t s, bool) -> glasso_err {  // a7
+    glasso_err e2 = push_ints(s, w.accept, hm.accept, count);
+    if (e2) return e2;
+    K_TRY(accept_trials(s, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, w.Dinv, w.Dinvt, np));
+    return GLASSO_OK;
+  };
+  const bool graphs = o.graphs != 0;
+  if (graphs) {
+    GraphKey key;
+    key.base = w.base;
+    key.host = hm.scal;
+    key.np = np;
+    key.n = n;
+    key.sS = sS;
+    key.count = count;
+    key.precision = o.precision;
+    key.tiles = get_gemm_f64_small_tile_below();
+    if (!(h->graphs.key == key)) {
+      drop_graphs(h->graphs);
+      h->graphs.key = key;
+    }
+  }
+  // eager: run the sequence on st; graphs: capture it once, then replay it on st
+  auto run = [&](hipGraphExec_t* slot, auto& body) -> glasso_err {
+    if (!graphs) return body(st, true);
+    if (!*slot) {
+      glasso_err e2 = capture_graph(h, slot, [&](hipStream_t cs) { return body(cs, false); });
+      if (e2) return e2;
+    }
+    HIP_TRY(hipGraphLaunch(*slot, st));
+    return GLASSO_OK;
+  };
+
   double phase[8] = {0};
   for (;;) {
     for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
-    e = push_ints(st, w.skip, hm.skip, count);
+    if (graphs) HIP_TRY(hipEventRecord(h->ev[0], st));
+    e = run(&h->graphs.head, head);
     if (e) return e;
-    pb.skip = w.skip;
-    pb.t = nullptr;
-    // a1: W = A^{-1} from the accepted factor
-    HIP_TRY(hipEventRecord(h->ev[0], st));
-    e = inverse_from_factor(w, st, w.skip);
-    if (e) return e;
-    HIP_TRY(hipEventRecord(h->ev[1], st));
-    // a2: gradient, free set, sign guess, Z and the KKT measure
-    K_TRY(pass_grad(st, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
-    HIP_TRY(hipEventRecord(h->ev[2], st));
-    e = fetch(h, st);
-    if (e) return e;
+    if (graphs) {
+      HIP_TRY(hipEventRecord(h->ev[1], st));
+      HIP_TRY(hipEventRecord(h->ev[2], st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
     phase[1] += elapsed(h->ev[0], h->ev[1]);
     phase[2] += elapsed(h->ev[1], h->ev[2]);
     int nact = 0;
@@ -509,12 +622,12 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     }
     if (!nact) break;
     for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
-    e = push_ints(st, w.skip, hm.skip, count);
-    if (e) return e;
     // a3: P = A Z A
     HIP_TRY(hipEventRecord(h->ev[2], st));
-    e = precond_product(w, st, o.precision, w.skip, h->ev + 5);
+    if (graphs) HIP_TRY(hipEventRecord(h->ev[5], st));
+    e = run(&h->graphs.prod, prod);
     if (e) return e;
+    if (graphs) HIP_TRY(hipEventRecord(h->ev[6], st));
     HIP_TRY(hipEventRecord(h->ev[3], st));
     // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
     for (int b = 0; b < count; ++b) {
@@ -544,18 +657,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       }
       if (!nls) break;
       for (int b = 0; b < count; ++b) hm.lsskip[b] = !ls[b];
-      e = push_ints(st, w.lsskip, hm.lsskip, count);
+      e = run(&h->graphs.trial, trial);
       if (e) return e;
-      e = push_doubles(st, w.t, hm.t, count);
-      if (e) return e;
-      PassBatch pt = pb;
-      pt.skip = w.lsskip;
-      pt.t = w.t;
-      K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
-      K_TRY(potrf_lower(st, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w)));
-      K_TRY(finish_trial(st, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal, pt));
-      e = fetch(h, st);
-      if (e) return e;
+      HIP_TRY(hipStreamSynchronize(st));
       int nacc = 0;
       for (int b = 0; b < count; ++b) {
         hm.accept[b] = 0;
@@ -572,9 +676,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       }
       if (nacc) {
         // a7: accept
-        e = push_ints(st, w.accept, hm.accept, count);
+        e = run(&h->graphs.acc, accept);
         if (e) return e;
-        K_TRY(accept_trials(st, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, w.Dinv, w.Dinvt, np));
       }
     }
     HIP_TRY(hipEventRecord(h->ev[4], st));
@@ -620,6 +723,7 @@ glasso_err glasso_default_options(glasso_options* opt) {
   memset(opt, 0, sizeof(*opt));
   opt->precision = GLASSO_FP64;
   opt->tile_policy = GLASSO_TILES_AUTO;
+  opt->graphs = 0;
   opt->max_iter = 500;
   opt->t0 = 1.0;
   opt->shrink = 0.5;
@@ -651,10 +755,13 @@ glasso_err glasso_create(glasso_handle* h, const glasso_options* opt) {
   }
   for (auto& e : hh->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
-      free_host(hh->hm);
-      delete hh;
+      glasso_destroy(hh);
       return GLASSO_ERR_HIP;
     }
+  }
+  if (hipStreamCreateWithFlags(&hh->cap, hipStreamNonBlocking) != hipSuccess) {
+    glasso_destroy(hh);
+    return GLASSO_ERR_HIP;
   }
   *h = hh;
   return GLASSO_OK;
@@ -662,6 +769,8 @@ glasso_err glasso_create(glasso_handle* h, const glasso_options* opt) {
 
 glasso_err glasso_destroy(glasso_handle h) {
   if (!h) return GLASSO_OK;
+  drop_graphs(h->graphs);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->ws.base) (void)hipFree(h->ws.base);
   free_host(h->hm);
   for (auto& e : h->ev)
