@@ -109,6 +109,20 @@ const char* glasso_error_string(glasso_err e);
  * admission by HBM footprint).  Errors: INVALID_ARG for n < 1 or bytes == NULL. */
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
 
+/* Many small problems (n <= GLASSO_SMALL_MAX_N each, sizes may differ) in ONE
+ * persistent launch: each workgroup takes problems i, i + G, i + 2G, ... (G =
+ * min(count, 512) workgroups) and runs the whole of Alg. 1 (Sec. 5 settings,
+ * FP64 for every step whatever opt.precision says) for each on the device, with no
+ * host round trip between iterations or trials.  Arguments, outputs and errors as
+ * for glasso_solve_batched (A[i] is also the starting iterate with warm_start);
+ * info[i].time_ms[0] is the wall time of the whole call.  Results meet the same
+ * bar against the definition as glasso_solve but are not bitwise equal to it (the
+ * reductions run in another order).  INVALID_ARG also for n[i] > GLASSO_SMALL_MAX_N. */
+#define GLASSO_SMALL_MAX_N 64
+glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                              const double* lambda, double tol, double* const* A, double* const* W,
+                              glasso_info* info, void* stream);
+
 /* Tile autotuner: for problems of size n solved `count` at a time, time the
  * Cholesky, triangular inverse and LAUUM (and, with opt.precision FP64, the
  * A Z A product) of identity matrices under each candidate tile policy

@@ -21,6 +21,7 @@ FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
 CONVERGED, MAX_ITER, LS_FAILED = 0, 1, 2
 TILES_AUTO = -1  # tile policy chosen by the autotuner (GLASSO_TILES_AUTO)
+SMALL_MAX_N = 64  # largest n of glasso_solve_small (GLASSO_SMALL_MAX_N)
 STATUS_NAMES = {CONVERGED: "converged", MAX_ITER: "max_iter", LS_FAILED: "ls_failed"}
 
 
@@ -146,6 +147,15 @@ class Solver:
         S_list: one tensor per problem (the same tensor may repeat) or a single
         tensor shared by all.  With a warm_start solver, A_list holds the starting
         iterates.  Returns one Result per problem."""
+        return self._multi("glasso_solve_batched", S_list, lams, tol, A_list, want_W, stream)
+
+    def solve_small(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
+        """Solve many problems of n <= SMALL_MAX_N in one persistent launch
+        (glasso_solve_small; every step FP64, no host round trip).  Arguments and
+        results as for solve_batched."""
+        return self._multi("glasso_solve_small", S_list, lams, tol, A_list, want_W, stream)
+
+    def _multi(self, entry, S_list, lams, tol, A_list, want_W, stream):
         lams = [float(x) for x in lams]
         count = len(lams)
         if isinstance(S_list, torch.Tensor):
@@ -171,8 +181,7 @@ class Solver:
         nn = (ctypes.c_int64 * count)(*ns)
         ll = (ctypes.c_double * count)(*lams)
         infos = (GlassoInfo * count)()
-        _check(_lib.glasso_solve_batched(self._h, count, Sp, nn, ll, float(tol), Ap, Wp, infos,
-                                         _stream(stream)), "glasso_solve_batched")
+        _check(getattr(_lib, entry)(self._h, count, Sp, nn, ll, float(tol), Ap, Wp, infos, _stream(stream)), entry)
         out = []
         for i in range(count):
             inf = infos[i]

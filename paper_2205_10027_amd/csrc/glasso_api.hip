@@ -119,6 +119,8 @@ struct glasso_handle_s {
   hipEvent_t ev[8] = {};
   hipStream_t cap = nullptr;  // capture stream (graphs option)
   Graphs graphs;
+  void* small_base = nullptr;  // workspace of the persistent small-problem solver
+  size_t small_bytes = 0;
 };
 
 namespace {
@@ -771,6 +773,7 @@ glasso_err glasso_destroy(glasso_handle h) {
   if (!h) return GLASSO_OK;
   drop_graphs(h->graphs);
   if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->small_base) (void)hipFree(h->small_base);
   if (h->ws.base) (void)hipFree(h->ws.base);
   free_host(h->hm);
   for (auto& e : h->ev)
@@ -857,6 +860,85 @@ glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, v
   }
   if (policy) *policy = thr;
   return GLASSO_OK;
+}
+
+glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                              const double* lambda, double tol, double* const* A, double* const* W,
+                              glasso_info* info, void* stream) {
+  if (!h || count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return GLASSO_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!S[i] || !A[i] || n[i] < 1 || n[i] > GLASSO_SMALL_MAX_N || !(lambda[i] > 0.0) || !isfinite(lambda[i]))
+      return GLASSO_ERR_INVALID_ARG;
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t st = (hipStream_t)stream;
+  const int grid = std::min(count, 512);
+  const size_t ws_bytes = (size_t)grid * SMALL_WS_DOUBLES * sizeof(double);
+  const size_t gm_bytes = (size_t)grid * SMALL_GM_BYTES;
+  const size_t pr_bytes = ((size_t)count * sizeof(SmallProblem) + 255) / 256 * 256;
+  const size_t out_bytes = (size_t)count * sizeof(SmallOut);
+  const size_t bytes = ws_bytes + gm_bytes + pr_bytes + out_bytes;
+  if (bytes > h->small_bytes) {
+    if (h->small_base) (void)hipFree(h->small_base);
+    h->small_base = nullptr;
+    h->small_bytes = 0;
+    if (hipMalloc(&h->small_base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return GLASSO_ERR_OOM;
+    }
+    h->small_bytes = bytes;
+  }
+  char* base = static_cast<char*>(h->small_base);
+  std::vector<SmallProblem> pr(count);
+  for (int i = 0; i < count; ++i) {
+    pr[i].S = S[i];
+    pr[i].A = A[i];
+    pr[i].W = W ? W[i] : nullptr;
+    pr[i].n = n[i];
+    pr[i].lam = lambda[i];
+  }
+  SmallParams p;
+  p.ws = reinterpret_cast<double*>(base);
+  p.gm = reinterpret_cast<int8_t*>(base + ws_bytes);
+  SmallProblem* dpr = reinterpret_cast<SmallProblem*>(base + ws_bytes + gm_bytes);
+  SmallOut* dout = reinterpret_cast<SmallOut*>(base + ws_bytes + gm_bytes + pr_bytes);
+  p.prob = dpr;
+  p.out = dout;
+  p.count = count;
+  const glasso_options& o = h->opt;
+  p.tol = tol;
+  p.t0 = o.t0;
+  p.shrink = o.shrink;
+  p.t_floor = o.t_floor;
+  p.t_min = o.t_min;
+  p.max_iter = o.max_iter;
+  p.warm_start = o.warm_start;
+  HIP_TRY(hipMemcpyAsync(dpr, pr.data(), (size_t)count * sizeof(SmallProblem), hipMemcpyHostToDevice, st));
+  K_TRY(solve_small(st, p, grid));
+  std::vector<SmallOut> out(count);
+  HIP_TRY(hipMemcpyAsync(out.data(), dout, out_bytes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  glasso_err err = GLASSO_OK;
+  for (int i = 0; i < count; ++i) {
+    if (out[i].error == 2 && !err) err = GLASSO_ERR_INVALID_ARG;
+    if (out[i].error == 1 && !err) err = GLASSO_ERR_NOT_PD;
+    if (out[i].error == 3 && !err) err = GLASSO_ERR_INTERNAL;
+    if (info) {
+      glasso_info& in = info[i];
+      memset(&in, 0, sizeof(in));
+      in.objective = out[i].objective;
+      in.kkt_rel1 = out[i].kkt_rel1;
+      in.kkt_fro = out[i].kkt_fro;
+      in.kkt_max = out[i].kkt_max;
+      in.nnz = (int64_t)llround(out[i].nnz);
+      in.iterations = out[i].iterations;
+      in.ls_trials = out[i].ls_trials;
+      in.status = (glasso_status)out[i].status;
+      in.fallback_steps = out[i].fallback_steps;
+      in.time_ms[0] = total;
+    }
+  }
+  return err;
 }
 
 // ------------------------------------------------------------------ step-level entry points

@@ -114,6 +114,35 @@ int accept_trials(hipStream_t stream, const int* accept, int count, double* A, c
                   const double* Dinvt, int64_t np);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
+// ---- persistent small-problem solver (n <= SMALL_MAX_N, one workgroup per problem)
+constexpr int SMALL_MAX_N = 64;
+constexpr int GLASSO_CONVERGED_DEV = 0, GLASSO_MAX_ITER_DEV = 1, GLASSO_LS_FAILED_DEV = 2;  // glasso_status
+struct SmallProblem {
+  const double* S;  // n x n (device), lower triangle read
+  double* A;        // n x n out (in: the starting iterate with warm_start)
+  double* W;        // n x n out, may be null
+  int64_t n;
+  double lam;
+};
+struct SmallOut {
+  double objective, kkt_rel1, kkt_fro, kkt_max, nnz;
+  int iterations, ls_trials, status, fallback_steps;
+  int error;  // 0 ok, 1 warm start not PD, 2 invalid S, 3 initial iterate not PD
+  int pad;
+};
+struct SmallParams {
+  const SmallProblem* prob;
+  SmallOut* out;
+  int count;
+  double* ws;  // per workgroup: 6 x 64 x 64 doubles (S, A, At, W, Z, P)
+  int8_t* gm;  // per workgroup: 64 x 64
+  double tol, t0, shrink, t_floor, t_min;
+  int max_iter, warm_start;
+};
+constexpr int64_t SMALL_WS_DOUBLES = 6 * 64 * 64;
+constexpr int64_t SMALL_GM_BYTES = 64 * 64;
+int solve_small(hipStream_t stream, const SmallParams& p, int grid);
+
 // X_b = identity for count consecutive np x np matrices
 int fill_identity(hipStream_t stream, double* X, int64_t np, int count);
 int mirror_lower(hipStream_t stream, double* M, int64_t np);

@@ -1,0 +1,183 @@
+// Factorisation and inversion of one diagonal block held in LDS by one
+// workgroup of 256 threads (4 wave64s), for block edges NB = 64 and 128.  Used by
+// the blocked Cholesky (NB = 128 leaf blocks) and the persistent small-problem
+// solver (NB = 64: the whole matrix).
+#pragma once
+
+#include <float.h>
+
+#include "common.h"
+
+namespace glasso {
+
+namespace {
+
+constexpr int PW = 32;  // panel width inside the block
+
+// broadcast a double from a wave-uniform lane
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// ---- small FP64 MFMA products on LDS-resident operands
+//
+// One 16x16 output block per call: acc += A B over k in [0, K), A element (m, k)
+// at a[ar + m][ac + k]; B element (k, n) at a[br + n][bc + k] (NT: rows of B^T)
+// or at a[br + k][bc + n] (NN).  Lane l supplies A[l%16][k + l/16] and
+// B[k + l/16][l%16]; D[i][j] lands in lane j + 16 (i%4), register i/4.
+// Optional masks zero A where k > m (A lower) and B where k < n (B lower), in
+// operand-local indices (mask_a/mask_b give the offsets of the block in the
+// triangular operand).
+template <bool NN, bool LOWA, bool LOWB, int LD>
+__device__ __forceinline__ v4d mfma_block(const double (*a)[LD], int ar, int ac, int br, int bc, int K, v4d acc,
+                                          int lane, int ma = 0, int mb = 0) {
+  const int i = lane & 15, kk = lane >> 4;
+#pragma unroll 4
+  for (int k = 0; k < K; k += 4) {
+    double x = a[ar + i][ac + k + kk];
+    double y = NN ? a[br + k + kk][bc + i] : a[br + i][bc + k + kk];
+    if (LOWA && (k + kk > ma + i)) x = 0.0;
+    if (LOWB && (k + kk < mb + i)) y = 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// element (4r + lane/16, lane%16) of a 16x16 MFMA block is acc[r]
+template <typename F>
+__device__ __forceinline__ void for_block(v4d acc, int lane, F f) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) f(4 * r + (lane >> 4), lane & 15, acc[r]);
+}
+
+// ---- in-LDS inverse of a lower-triangular NB x NB block (upper triangle = scratch)
+//
+// Stage 1: wave w inverts the 32x32 diagonal block w (lane c computes column c by
+// forward substitution).  Stage 2 doubles the inverted block size: for each group
+// [T11 0; T21 T22] of size 2S with T11, T22 already inverted,
+//   tmp = T21 inv(T11)  (stored transposed in the free upper triangle),
+//   X21 = -inv(T22) tmp (written over T21),
+// as 16x16 MFMA blocks spread over the four waves.
+template <int S, int NB>
+__device__ __forceinline__ void trtri_level(double (*a)[NB + 1], int tid) {
+  constexpr int NBS = S / 16;                 // 16-blocks per edge
+  constexpr int GROUPS = NB / (2 * S);
+  constexpr int JOBS = GROUPS * NBS * NBS;    // output blocks per product
+  const int lane = tid & 63, wave = tid >> 6;
+  // tmp = T21 inv(T11): block (bi, bj) sums k from 16 bj (inv(T11) is lower)
+  for (int job = wave; job < JOBS; job += 4) {
+    const int g = job / (NBS * NBS), bi = (job / NBS) % NBS, bj = job % NBS;
+    const int o = g * 2 * S;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int k0 = 16 * bj;
+    acc = mfma_block<true, false, true>(a, o + S + 16 * bi, o + k0, o + k0, o + 16 * bj, S - k0, acc, lane, 0, 0);
+    for_block(acc, lane, [&](int r, int c, double v) { a[o + 16 * bj + c][o + S + 16 * bi + r] = v; });
+  }
+  __syncthreads();
+  // X21 = -inv(T22) tmp: block (bi, bj) sums k up to 16 bi + 15 (inv(T22) is lower)
+  for (int job = wave; job < JOBS; job += 4) {
+    const int g = job / (NBS * NBS), bi = (job / NBS) % NBS, bj = job % NBS;
+    const int o = g * 2 * S;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    acc = mfma_block<false, true, false>(a, o + S + 16 * bi, o + S, o + 16 * bj, o + S, 16 * (bi + 1), acc, lane,
+                                         16 * bi, 0);
+    for_block(acc, lane, [&](int r, int c, double v) { a[o + S + 16 * bi + r][o + 16 * bj + c] = -v; });
+  }
+  __syncthreads();
+}
+
+template <int NB>
+__device__ void lds_trtri(double (*a)[NB + 1], int tid) {
+  static_assert(NB == 64 || NB == 128, "block edge");
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane < PW && PW * wave < NB) {
+    const int o = PW * wave;
+    double x[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) {
+      double s = (i == lane) ? 1.0 : 0.0;
+      // Row i's loads may not start before x[i-2] exists: without this ordering the
+      // compiler hoists all 528 loads of the block and spills.
+      int rb = (o + i) * (NB + 1) + o;
+      if (i >= 2) asm volatile("" : "+v"(rb) : "v"(x[i - 2]));
+      const double* arow = &a[0][0] + rb;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= arow[k] * x[k];
+      x[i] = s / arow[i];
+    }
+    // x[i] = 0 for i < lane: only the lower part of column `lane` is written
+#pragma unroll
+    for (int i = 0; i < PW; ++i)
+      if (i >= lane) a[o + i][o + lane] = x[i];
+  }
+  __syncthreads();
+  trtri_level<32, NB>(a, tid);
+  if (NB == 128) trtri_level<64, NB>(a, tid);
+}
+
+// Cholesky of the NB x NB lower triangle in LDS, in place.  Returns the first
+// failing pivot (non-positive or NaN) or -1; the value is identical in every
+// thread, and on failure the block is left partially factored.
+//
+// Panels of 32 columns.  For a panel starting at c0, every wave holds the 32x32
+// diagonal block in lanes 0..31 (row c0+lane, one register per column) and factors
+// it redundantly: the pivot comes from readlane and the multipliers of the block
+// rows are broadcast with readlane.  Lanes 32..63 of the waves hold the rows below
+// the block and are eliminated in the same steps (the triangular solve of the
+// panel).  All 4 waves then apply the rank-32 update to the trailing lower
+// triangle.  Elements above the diagonal are never read as data.
+template <int NB>
+__device__ int lds_potrf(double (*a)[NB + 1], int tid) {
+  const int lane = tid & 63, wave = tid >> 6;
+  int fail = -1;
+#pragma unroll 1
+  for (int p = 0; p < NB / PW; ++p) {
+    const int c0 = PW * p;
+    const int row = (lane < PW) ? c0 + lane : c0 + PW + wave * PW + (lane - PW);
+    const bool valid = row < NB;
+    double v[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      const double piv = lane_bcast(v[j], j);
+      const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
+      if (!ok && fail < 0) fail = c0 + j;
+      const double r = rsqrt(ok ? piv : 1.0);
+      const double m = v[j] * r;  // lane j: sqrt(piv); rows below: multipliers
+      v[j] = m;
+      // the multipliers of the block rows are uniform values: broadcast each one
+      // from its lane with readlane and update every later column
+#pragma unroll
+      for (int c = j + 1; c < PW; ++c) v[c] -= m * lane_bcast(m, c);
+    }
+    if (fail >= 0) break;
+    if (valid && (lane >= PW || wave == 0)) {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) a[row][c0 + q] = v[q];
+    }
+    __syncthreads();
+    // rank-32 update of the trailing lower triangle in 16x16 MFMA blocks
+    const int base = c0 + PW, R = NB - base;
+    if (R > 0) {
+      const int nb16 = R / 16;
+      const int nblk = nb16 * (nb16 + 1) / 2;
+      for (int job = wave; job < nblk; job += 4) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
+        const int bj = job - bi * (bi + 1) / 2;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_block<false, false, false>(a, base + 16 * bi, c0, base + 16 * bj, c0, PW, acc, lane);
+        for_block(acc, lane, [&](int r, int c, double v) { a[base + 16 * bi + r][base + 16 * bj + c] -= v; });
+      }
+      __syncthreads();
+    }
+  }
+  return fail;
+}
+
+}  // namespace
+
+}  // namespace glasso

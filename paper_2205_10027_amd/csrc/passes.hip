@@ -21,42 +21,12 @@
 #include <float.h>
 
 #include "common.h"
+#include "elementwise.h"
 #include "kernels.h"
 
 namespace glasso {
 
 namespace {
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-
-// Sum (or max) over a 256-thread block in a fixed order; result valid in every thread.
-__device__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
-}
-__device__ double block_max(double v, double* sh) {
-  v = wave_max(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
-}
-
-__device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
 // ------------------------------------------------------------------ gradient pass
 __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict__ S,
@@ -94,14 +64,8 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
     if (!diag || c <= r) {
       if (i < n && j < n) {
         const double a = A[off], s = S[off], w = W[off];
-        const double g = s - w;
+        grad_element(a, s, w, lam, z, gm);
         const bool nz = (a != 0.0);
-        const double G = nz ? sign_of(a) : -sign_of(g);
-        const bool M = nz || (fabs(g) > lam);
-        if (M) {
-          z = g + lam * G;
-          gm = (int8_t)G;
-        }
         const double wgt = (i == j) ? 1.0 : 2.0;
         s_absz += wgt * fabs(z);
         s_z2 += wgt * (z * z);
@@ -239,12 +203,8 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
         if (gm != 0) {
           const double a = A[off];
           const double p = P[off];
-          const double Cij = (i == j) ? lam * (di[r] * di[r]) : lam * ((di[r] * dj[c]) + (a * a));
-          const double B = p - Cij * (double)gm;
-          const double x = a - t * B;
-          const double tau = t * Cij;
-          const double m = fmax(fabs(x) - tau, 0.0);
-          at = sign_of(x) * m;
+          const double Cij = c_element(i == j, di[r], dj[c], a, lam);
+          at = trial_element(a, p, Cij, (double)gm, t);
           const double s = S[off];
           const double wgt = (i == j) ? 1.0 : 2.0;
           s_tr += wgt * (s * (at - a));

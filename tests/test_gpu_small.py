@@ -1,0 +1,118 @@
+"""Persistent small-problem solver (glasso_solve_small): many problems of
+n <= 64 in one launch, each solved entirely on the device.
+
+Acceptance per problem is the FP64 bar of glasso_solve against the oracle
+(F to 1e-8 relative, KKT recomputed by the oracle <= tol, identical support up to
+the threshold exemptions, W A = I); in addition a problem gives bitwise the same
+result alone and inside a launch with many others, and the closed forms (n = 1,
+n = 2, the diagonal case in 0 iterations) and every status and error path hold.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import pins
+from tests.gpu_util import device, support_mismatch, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    device()
+    import paper_2205_10027_amd as g
+
+    return g
+
+
+def problems():
+    out = []
+    for i, (n, seed, frac) in enumerate([(5, 0, 0.3), (17, 1, 0.25), (33, 2, 0.2), (48, 3, 0.3), (64, 4, 0.25),
+                                         (64, 5, 0.15), (40, 6, 0.4), (9, 7, 0.2)]):
+        S, _ = synth.random_sparse_problem(n, max(2, n // 2), seed)
+        out.append((S, frac * synth.lambda_max(S)))
+    for n, seed, lam in [(60, 8, 0.2), (24, 9, 0.3)]:
+        out.append((synth.chain_problem(n, n // 2, seed)[0], lam))
+    return out
+
+
+def test_small_batch_meets_oracle_bar(g):
+    probs = problems()
+    tol = 1e-7
+    res = g.Solver().solve_small([to_dev(S) for S, _ in probs], [lam for _, lam in probs], tol)
+    for (S, lam), r in zip(probs, res):
+        assert r.status == g.CONVERGED, (len(S), r.status_name)
+        A, W = to_host(r.A), to_host(r.W)
+        ref = oracle.pista(S, lam, tol)
+        chk = oracle.check_solution(S, A, lam)
+        assert chk["pd"] and chk["kkt_rel1"] <= tol * 1.0001
+        assert abs(r.objective - ref.objective) <= 1e-8 * max(1.0, abs(ref.objective))
+        assert abs(r.objective - chk["objective"]) <= 1e-10 * max(1.0, abs(chk["objective"]))
+        ref_chk = oracle.check_solution(S, ref.A, lam)
+        assert support_mismatch(A, ref.A, ref_chk["g"], lam) == 0
+        assert np.array_equal(A, A.T)
+        assert np.max(np.abs(W @ A - np.eye(len(S)))) <= 1e-10 * np.linalg.cond(A)
+
+
+def test_same_alone_and_in_the_mix(g):
+    probs = problems() * 5  # 50 problems: more than one per workgroup slot is fine too
+    Sd = [to_dev(S) for S, _ in probs]
+    lams = [lam for _, lam in probs]
+    mix = g.Solver().solve_small(Sd, lams, 1e-7)
+    for i in (0, 4, 9, 23, 49):
+        alone = g.Solver().solve_small([Sd[i]], [lams[i]], 1e-7)[0]
+        assert np.array_equal(to_host(alone.A), to_host(mix[i].A))
+        assert np.array_equal(to_host(alone.W), to_host(mix[i].W))
+        assert alone.iterations == mix[i].iterations and alone.objective == mix[i].objective
+
+
+def test_small_closed_forms(g):
+    s = g.Solver()
+    r = s.solve_small([to_dev(np.array([[0.7]]))], [0.1], 1e-10)[0]
+    assert r.iterations == 0 and to_host(r.A)[0, 0] == 1.0 / 0.8
+    for seed in range(3):
+        S = pins.random_psd(2, 3, seed)
+        for lam in (0.05, 0.3):
+            r = s.solve_small([to_dev(S)], [lam], 1e-9)[0]
+            np.testing.assert_allclose(to_host(r.A), pins.n2_closed_form(S, lam), rtol=1e-7, atol=1e-9)
+    S, _ = synth.chain_problem(50, 100, 4)
+    lam = synth.lambda_max(S)
+    r = s.solve_small([to_dev(S)], [lam], 1e-10)[0]
+    assert r.iterations == 0 and r.status == g.CONVERGED
+    np.testing.assert_array_equal(to_host(r.A), np.diag(1.0 / (np.diag(S) + lam)))
+
+
+def test_small_agrees_with_blocked_engine(g):
+    S, _ = synth.random_sparse_problem(64, 32, 11)
+    lam = 0.25 * synth.lambda_max(S)
+    a = g.Solver().solve(to_dev(S), lam, 1e-8)
+    b = g.Solver().solve_small([to_dev(S)], [lam], 1e-8)[0]
+    assert a.status == b.status == g.CONVERGED
+    assert abs(a.objective - b.objective) <= 1e-10 * abs(a.objective)
+
+
+def test_small_status_and_errors(g):
+    S, _ = synth.chain_problem(40, 20, 2)
+    Sd = to_dev(S)
+    r = g.Solver(max_iter=1).solve_small([Sd], [0.2], 1e-12)[0]
+    assert r.status == g.MAX_ITER and r.iterations == 1
+    r = g.Solver(t0=1e-13, t_min=1e-12, t_floor=0.0).solve_small([Sd], [0.2], 1e-9)[0]
+    assert r.status == g.LS_FAILED and r.iterations == 0
+    # warm start from a neighbouring solution
+    first = g.Solver().solve_small([Sd], [0.25], 1e-8)[0]
+    warm = g.Solver(warm_start=True).solve_small([Sd], [0.2], 1e-8, A_list=[first.A.clone()])[0]
+    cold = g.Solver().solve_small([Sd], [0.2], 1e-8)[0]
+    assert warm.status == g.CONVERGED and abs(warm.objective - cold.objective) <= 1e-9 * abs(cold.objective)
+    with pytest.raises(g.GlassoError) as e:
+        g.Solver(warm_start=True).solve_small([Sd], [0.2], 1e-6, A_list=[to_dev(-np.eye(40))])
+    assert e.value.code == 2
+    Sbad = S.copy()
+    Sbad[5, 3] = np.nan
+    with pytest.raises(g.GlassoError) as e:
+        g.Solver().solve_small([to_dev(Sbad)], [0.2], 1e-6)
+    assert e.value.code == 1
+    big, _ = synth.chain_problem(65, 30, 0)
+    with pytest.raises(g.GlassoError) as e:
+        g.Solver().solve_small([to_dev(big)], [0.2], 1e-6)
+    assert e.value.code == 1
