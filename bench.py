@@ -125,7 +125,41 @@ def bench_path(g, torch, dev):
     out["modes"] = modes
     out["solves_per_s"] = modes["independent"]["solves_per_s"]
     out["speedup_vs_sequential"] = modes["sequential"]["path_s"] / modes["independent"]["path_s"]
+    out["small_persistent"] = bench_small(g, torch, dev)
     return out
+
+
+def bench_small(g, torch, dev, count=1024):
+    """Many uneven-n small problems in one persistent launch (glasso_solve_small)."""
+    import numpy as np
+
+    import synth
+
+    rng = np.random.default_rng(0)
+    ns = [int(x) for x in rng.integers(16, 65, size=count)]
+    Ss, lams = [], []
+    for i, n in enumerate(ns):
+        S, _ = synth.random_sparse_problem(n, n // 2, i)
+        Ss.append(torch.from_numpy(S).to(dev))
+        lams.append(0.3 * synth.lambda_max(S))
+    s = g.Solver()
+    s.solve_small(Ss[:8], lams[:8], 1e-5)  # warmup
+    best = None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = s.solve_small(Ss, lams, 1e-5)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        best = dt if best is None else min(best, dt)
+    if any(r.status != g.CONVERGED for r in res):
+        raise RuntimeError("persistent small solves: not every problem converged")
+    s.close()
+    log(f"[bench] persistent small: {count} problems in {best * 1e3:.1f} ms ({count / best:.0f} solves/s)")
+    return {"workload": f"{count} random sparse problems, n uniform in [16, 64], m = n/2, lambda = 0.3 lambda_max, "
+                        "tol 1e-5, FP64, one persistent launch",
+            "launch_ms": best * 1e3, "solves_per_s": count / best,
+            "iterations": sum(r.iterations for r in res)}
 
 
 def bench_serve(g, count, seed=0):
