@@ -160,7 +160,10 @@ glasso_err ensure_host(glasso_handle h, int count) {
   return GLASSO_OK;
 }
 
-glasso_err ensure_workspace(glasso_handle h, int count, int64_t np) {
+// The zero fill of a new allocation is ordered on `st`, the stream of the call
+// that uses the workspace: a plain hipMemset runs on the null stream, which is not
+// ordered with non-blocking caller streams and could land after the first kernels.
+glasso_err ensure_workspace(glasso_handle h, int count, int64_t np, hipStream_t st) {
   Workspace& w = h->ws;
   glasso_err e = ensure_host(h, count);
   if (e) return e;
@@ -186,7 +189,7 @@ glasso_err ensure_workspace(glasso_handle h, int count, int64_t np) {
     (void)hipGetLastError();
     return GLASSO_ERR_OOM;
   }
-  if (hipMemset(base, 0, bytes) != hipSuccess) {
+  if (hipMemsetAsync(base, 0, bytes, st) != hipSuccess) {
     (void)hipFree(base);
     return GLASSO_ERR_HIP;
   }
@@ -479,7 +482,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   const auto t_start = std::chrono::steady_clock::now();
   const glasso_options& o = h->opt;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, count, np);
+  glasso_err e = ensure_workspace(h, count, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, o.precision);
   if (e) return e;
@@ -849,7 +852,7 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
 glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, void* stream) {
   if (!h || n < 1 || n > (1 << 20) || count < 1) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  glasso_err e = ensure_workspace(h, count, pad_to_tile(n));
+  glasso_err e = ensure_workspace(h, count, pad_to_tile(n), st);
   if (e) return e;
   int thr = 0;
   e = tune_tiles(h, st, h->opt.precision, &thr);
@@ -947,7 +950,7 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
   if (!h || !A || !L || n < 1) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, 1, np);
+  glasso_err e = ensure_workspace(h, 1, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
@@ -972,7 +975,7 @@ glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W
   if (!h || !A || !W || n < 1) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, 1, np);
+  glasso_err e = ensure_workspace(h, 1, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
@@ -993,7 +996,7 @@ glasso_err glasso_gradient_pass(glasso_handle h, const double* S, const double* 
   if (!h || !S || !W || !A || !Z || !GM || n < 1 || !(lambda > 0.0)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, 1, np);
+  glasso_err e = ensure_workspace(h, 1, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
@@ -1022,7 +1025,7 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
   if (!valid_precision(precision)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, 1, np);
+  glasso_err e = ensure_workspace(h, 1, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;
@@ -1041,7 +1044,7 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
   if (!h || !A || !P || !S || !GM || !At || n < 1 || !(lambda > 0.0) || !(t > 0.0)) return GLASSO_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, 1, np);
+  glasso_err e = ensure_workspace(h, 1, np, st);
   if (e) return e;
   e = apply_tile_policy(h, st, h->opt.precision);
   if (e) return e;

@@ -36,3 +36,34 @@ def test_mix_equals_alone():
         chk = oracle.check_solution(r.S, to_host(mix.A), r.lam)
         assert chk["kkt_rel1"] <= 1e-5 * 1.0001
     eng.close()
+
+
+def test_fresh_handle_on_nonblocking_stream_while_null_stream_busy():
+    """A new handle zero-fills its workspace on the stream of its first call.  A
+    fill on the null stream would queue behind the null stream's work and land in
+    the middle of a solve running on a non-blocking stream (as torch streams are):
+    the solve must equal the same solve run alone."""
+    device()
+    import torch
+
+    import paper_2205_10027_amd as g
+
+    S, _ = synth.random_sparse_problem(600, 300, 21)
+    lam = 0.25 * synth.lambda_max(S)
+    ref = g.Solver().solve(to_dev(S), lam, 1e-7)
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    a = torch.randn(6144, 6144, device="cuda", dtype=torch.float32)
+    for _ in range(3):
+        for _ in range(4):
+            c = a @ a  # several ms of work on the null stream
+        s = g.Solver()
+        with torch.cuda.stream(st):
+            Sd = torch.from_numpy(S).to("cuda")
+            r = s.solve(Sd, lam, 1e-7, stream=st)
+        st.synchronize()
+        torch.cuda.synchronize()
+        assert r.status == ref.status and r.iterations == ref.iterations
+        assert np.array_equal(to_host(r.A), to_host(ref.A))
+        s.close()
+    del c
