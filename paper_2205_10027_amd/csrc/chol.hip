@@ -20,11 +20,18 @@ constexpr int NB = 128;        // leaf block (= GEMM tile)
 constexpr int LDL = NB + 1;    // LDS row stride of the leaf
 constexpr int OUTER = 1024;    // outer panel width of the two-level Cholesky
 
-// Factor the 128x128 diagonal block at A (lower, in place; lds_potrf), write
-// diag(L) to dL and inv(L) (lds_trtri; zeros above the diagonal) to Dinv (ld 128).
-// k0 is the block's global column, used to report the first failing pivot through
-// info.
-__global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t lda, int k0,
+// One step of the blocked Cholesky: the 128-column block whose diagonal block is at
+// A, with `rest` rows of the panel below it (a multiple of 64).
+//
+// Every workgroup factors (lds_potrf) and inverts (lds_trtri) the diagonal block in
+// LDS; all of them compute identical values.  Workgroup 0 writes diag(L) to dL,
+// inv(L11) to Dinv (ld 128, zeros above the diagonal) and the strict lower part of
+// L11 transposed into the strict upper triangle of the block: the lower triangle is
+// still being read by the other workgroups, so place_diag_factor moves L11 into
+// place after the whole factorisation.  Workgroup 1 + q solves rows 64q .. 64q + 63
+// of the panel below, L21 = A21 inv(L11)^T, in place: it owns those rows entirely.
+// k0 is the block's global column, used to report the first failing pivot.
+__global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t lda, int k0, int rest,
                                                              double* dL, double* Dinv, int* info,
                                                              FactorBatch fb) {
   // problem blockIdx.y of the batch
@@ -34,7 +41,7 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
   info += blockIdx.y;
   if (*info) return;
   __shared__ double a[NB][LDL];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
 #pragma unroll 8
@@ -49,24 +56,69 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
 
   const int fail = lds_potrf<NB>(a, tid);
   if (fail >= 0) {
-    if (tid == 0) *info = k0 + fail + 1;
+    if (blockIdx.x == 0 && tid == 0) *info = k0 + fail + 1;
     return;
   }
-
+  if (blockIdx.x == 0) {
 #pragma unroll 8
-  for (int i = 0; i < NB * NB / 256; ++i) {
-    const int e = tid + 256 * i;
-    const int r = e >> 7, c = e & 127;
-    if (c <= r) A[(int64_t)r * lda + c] = a[r][c];
+    for (int i = 0; i < NB * NB / 256; ++i) {
+      const int e = tid + 256 * i;
+      const int r = e >> 7, c = e & 127;
+      if (c < r) A[(int64_t)c * lda + r] = a[r][c];
+    }
+    if (tid < NB) dL[tid] = a[tid][tid];
   }
-  if (tid < NB) dL[tid] = a[tid][tid];
   __syncthreads();
   lds_trtri<NB>(a, tid);
+  if (blockIdx.x == 0) {
 #pragma unroll 8
-  for (int i = 0; i < NB * NB / 256; ++i) {
-    const int e = tid + 256 * i;
+    for (int i = 0; i < NB * NB / 256; ++i) {
+      const int e = tid + 256 * i;
+      const int r = e >> 7, c = e & 127;
+      Dinv[e] = (c <= r) ? a[r][c] : 0.0;
+    }
+    return;
+  }
+  if (rest <= 0) return;
+  // rows 64q .. 64q + 63 below the block; wave w takes 16 of them.  A operand of
+  // k-step s: R[16w + lane%16][4s + lane/16] (v_mfma_f64_16x16x4f64 A layout);
+  // B operand inv(L11)^T (k, c) = inv(L11)[c][k], zero for k > c (the upper
+  // triangle of a is scratch).
+  double* R = A + (int64_t)(NB + 64 * (blockIdx.x - 1)) * lda;
+  const double* Rw = R + (int64_t)(16 * wave + (lane & 15)) * lda + (lane >> 4);
+  double af[NB / 4];
+#pragma unroll
+  for (int s = 0; s < NB / 4; ++s) af[s] = Rw[4 * s];
+  v4d acc[8];
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < NB / 4; ++s) {
+#pragma unroll
+    for (int cb = s / 4; cb < 8; ++cb) {
+      const int c = 16 * cb + (lane & 15), k = 4 * s + (lane >> 4);
+      const double y = (k <= c) ? a[c][k] : 0.0;
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], y, acc[cb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < 8; ++cb)
+    for_block(acc[cb], lane, [&](int r, int c, double v) { R[(int64_t)(16 * wave + r) * lda + 16 * cb + c] = v; });
+}
+
+// After the factorisation: the strict lower part of every 128x128 diagonal block
+// from its transposed copy in the strict upper triangle, the diagonal from dL.
+__global__ __launch_bounds__(256) void place_diag_factor_kernel(double* A, int64_t lda, const double* dL,
+                                                                const int* info, FactorBatch fb) {
+  if (info[blockIdx.y]) return;
+  double* D = A + blockIdx.y * fb.sA + (int64_t)blockIdx.x * NB * (lda + 1);
+  const double* d = dL + blockIdx.y * fb.sdL + (int64_t)blockIdx.x * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
     const int r = e >> 7, c = e & 127;
-    Dinv[e] = (c <= r) ? a[r][c] : 0.0;
+    if (c < r)
+      D[(int64_t)r * lda + c] = D[(int64_t)c * lda + r];
+    else if (c == r)
+      D[(int64_t)r * lda + r] = d[r];
   }
 }
 
@@ -92,24 +144,16 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
   ZBatch zA;  // operands and output inside the factored matrix
   zA.count = fb.count;
   zA.sA = zA.sB = zA.sC = fb.sA;
-  ZBatch zT = zA;  // triangular solve: B operand is the diagonal-block inverse
-  zT.sB = fb.sDinv;
   int rc = 0;
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
     for (int k = K0; k < K1 && rc == 0; k += NB) {
+      // factor + invert the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
       double* Akk = A + (int64_t)k * lda + k;
-      hipLaunchKernelGGL(leaf_potrf_inv_kernel, dim3(1, fb.count), dim3(256), 0, stream, Akk, lda, k, dL + k,
-                         Dinv + (int64_t)(k / NB) * NB * NB, info, fb);
-      if (hipGetLastError() != hipSuccess) return -2;
       const int rest = n - k - NB;
-      if (rest > 0) {
-        // panel below the block: A21 <- A21 * inv(L11)^T (in place; one tile column)
-        double* A21 = A + (int64_t)(k + NB) * lda + k;
-        rc = gemm_f64(stream, 0, 0, rest, NB, NB, 1.0, A21, lda, Dinv + (int64_t)(k / NB) * NB * NB, NB,
-                      0.0, A21, lda, 0, 0, 2, info, 1, 0, 0, 0, 0, zT, /*in_place=*/1);
-        if (rc) return rc;
-      }
+      hipLaunchKernelGGL(leaf_potrf_inv_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k,
+                         rest, dL + k, Dinv + (int64_t)(k / NB) * NB * NB, info, fb);
+      if (hipGetLastError() != hipSuccess) return -2;
       if (k + NB < K1) {
         // update of the remaining columns of the outer panel
         const double* Pk = A + (int64_t)(k + NB) * lda + k;
@@ -125,7 +169,9 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
                     A + (int64_t)K1 * lda + K1, lda, 1, 0, 0, info, 1, 0, 0, 0, 0, zA);
     }
   }
-  return rc;
+  if (rc) return rc;
+  hipLaunchKernelGGL(place_diag_factor_kernel, dim3(n / NB, fb.count), dim3(256), 0, stream, A, lda, dL, info, fb);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* Dinv, double* tmp,

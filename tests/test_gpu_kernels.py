@@ -61,7 +61,7 @@ def test_precond_product_fp32(solver, n):
     assert np.max(np.abs(P - ref)) > 0
 
 
-@pytest.mark.parametrize("n", [5, 128, 300, 1024])
+@pytest.mark.parametrize("n", [5, 128, 300, 1024, 2048, 2100])
 def test_precond_product_bf16x3(solver, n):
     """BF16x3 product.  Splitting x = hi + lo leaves |x - hi - lo| <= 2^-16 |x|
     (two bf16 roundings, unit roundoff 2^-8 each); the dropped lo*lo term is
@@ -80,11 +80,11 @@ def test_precond_product_bf16x3(solver, n):
     assert np.max(np.abs(P - ref)) > 0
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
-def test_precond_product_structure(solver, precision):
+@pytest.mark.parametrize("precision,n", [("fp64", 256), ("fp32", 256), ("bf16x3", 256), ("bf16x3", 2100)])
+def test_precond_product_structure(solver, precision, n):
     """Identity and permutation cases pin the MFMA lane layout exactly (small
-    integers are exact in every form)."""
-    n = 256
+    integers are exact in every form; n = 2100 takes the wide BF16x3 tiles with a
+    partial last tile row)."""
     rng = np.random.default_rng(3)
     Z = sym(rng.integers(-3, 4, size=(n, n)).astype(np.float64))
     P = to_host(solver.precond_product(to_dev(np.eye(n)), to_dev(Z), precision=precision))
