@@ -36,9 +36,9 @@ sys.path.insert(0, ROOT)
 # peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 # HBM bytes per A Z A launch (mean of the two launches), from FETCH_SIZE and WRITE_SIZE
-# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_gemm_f32_chain10k.md).
-# Valid for the FP32 GEMM kernel as profiled; None where no counters were taken.
-TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None, "bf16x3": None}
+# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_gemm_*_chain10k.md).
+# Valid for the GEMM kernels as profiled; None where no counters were taken.
+TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None, "bf16x3": 18319328585}
 
 
 def log(*a):
