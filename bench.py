@@ -66,11 +66,11 @@ def cpu_baseline(S, lam, gpu_iterations):
 
 def time_chain(g, St, lams, tol, precision, steps, warmup, torch):
     solver = g.Solver(precision=precision)
-    A = torch.empty_like(St)
+    As = [torch.empty_like(St) for _ in lams]  # the last step's solution per lambda
 
     def step():
         out = []
-        for lam in lams:
+        for lam, A in zip(lams, As):
             res = solver.solve(St, lam, tol, A=A, want_W=False)
             if res.status != g.CONVERGED or not (res.kkt_rel1 <= tol):
                 raise RuntimeError(f"{precision} solve at lambda={lam}: {res.status_name}, kkt={res.kkt_rel1}")
@@ -92,12 +92,12 @@ def time_chain(g, St, lams, tol, precision, steps, warmup, torch):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     solver.close()
-    return elapsed, results
+    return elapsed, results, As
 
 
 def bench_path(g, torch, dev):
-    """Regularisation path: independent batch (timed twice after a warmup) and
-    the sequential warm-started path (once)."""
+    """Regularisation path, FP64: every mode of lambda_path (with and without
+    graph-captured iterations) and the plain one-solve-per-lambda path."""
     import synth
 
     S, _ = synth.random_sparse_problem(1000, 500, 0)
@@ -106,25 +106,37 @@ def bench_path(g, torch, dev):
     out = {"workload": "random sparse n=1000 m=500 seed 0, 32 lambdas lambda_max..lambda_max/100, tol 1e-5",
            "precision": "fp64"}
     modes = {}
-    for mode, reps in (("independent", 2), ("waves", 1), ("sequential", 1)):
-        if mode == "independent":
-            g.lambda_path(St, lams, 1e-5, mode=mode, max_iter=5000)  # warmup
-        best = None
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t
-            if any(r.status != g.CONVERGED for r in res):
-                raise RuntimeError(f"path mode {mode}: not every lambda converged")
-            best = dt if best is None else min(best, dt)
-        modes[mode] = {"path_s": best, "solves_per_s": len(lams) / best,
-                       "iterations": sum(r.iterations for r in res)}
-        log(f"[bench] path {mode}: {best:.2f}s ({len(lams) / best:.1f} solves/s)")
+    g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000)  # warmup (and tile tuning)
+    for name, mode, graphs in (("independent", "independent", False), ("independent_graphs", "independent", True),
+                               ("waves", "waves", False), ("waves_graphs", "waves", True),
+                               ("sequential", "sequential", False)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000, graphs=graphs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if any(r.status != g.CONVERGED for r in res):
+            raise RuntimeError(f"path mode {name}: not every lambda converged")
+        modes[name] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res)}
+        log(f"[bench] path {name}: {dt:.2f}s ({len(lams) / dt:.1f} solves/s)")
+    # the plain path: one glasso_solve per lambda from the diagonal start, no batching
+    s1 = g.Solver()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = 0
+    for lam in lams:
+        r = s1.solve(St, lam, 1e-5, want_W=False)
+        its += r.iterations
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    s1.close()
+    modes["one_by_one"] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": its}
+    log(f"[bench] path one_by_one: {dt:.2f}s ({len(lams) / dt:.1f} solves/s)")
     out["modes"] = modes
-    out["solves_per_s"] = modes["independent"]["solves_per_s"]
-    out["speedup_vs_sequential"] = modes["sequential"]["path_s"] / modes["independent"]["path_s"]
+    # config 3 asks for a warm-started, graph-captured, autotuned path
+    out["solves_per_s"] = modes["waves_graphs"]["solves_per_s"]
+    out["speedup_vs_one_by_one"] = modes["one_by_one"]["path_s"] / modes["waves_graphs"]["path_s"]
+    out["best_mode"] = min(modes, key=lambda k: modes[k]["path_s"])
     out["small_persistent"] = bench_small(g, torch, dev)
     return out
 
@@ -189,9 +201,12 @@ def bench_serve(g, count, seed=0):
     st = srv.run(requests(None), realtime=False)
     capacity = st.solves_per_s
     log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
+    serial = Server(eng, slots=1, hbm_budget=budget, footprint=gpu_footprint).run(requests(None), realtime=False)
+    log(f"[bench] serving one slot: {serial.solves_per_s:.2f} solves/s")
     out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2, lambda=0.3 lambda_max, "
                        f"random sparse, mixed FP32, tol 1e-5, {slots} slots, HBM budget {budget >> 30} GiB",
-           "closed_loop_solves_per_s": capacity, "rates": {}}
+           "closed_loop_solves_per_s": capacity, "one_slot_solves_per_s": serial.solves_per_s,
+           "speedup_vs_one_slot": capacity / serial.solves_per_s, "rates": {}}
     for frac in (0.5, 0.8, 1.0):
         rate = frac * capacity
         st = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint).run(requests(rate))
@@ -243,7 +258,7 @@ def main():
     log(f"[bench] generated S n={n} m={m} in {time.perf_counter() - t:.1f}s")
     St = torch.from_numpy(S).to(dev)
 
-    elapsed, results = time_chain(g, St, lams, tol, args.precision, args.steps, args.warmup, torch)
+    elapsed, results, A_mixed = time_chain(g, St, lams, tol, args.precision, args.steps, args.warmup, torch)
     solves = args.steps * len(lams)
     value = elapsed / solves
 
@@ -266,10 +281,19 @@ def main():
               "ls_trials": [r.ls_trials for r in results[:len(lams)]],
               "solves_per_s": solves / elapsed}
     if not args.no_fp64_ref and args.precision != "fp64":
-        e64, r64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
+        e64, r64, A64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
         config["fp64_plain_s"] = e64 / len(lams)
         config["fp64_plain_iterations"] = [r.iterations for r in r64]
         config["speedup_vs_fp64"] = (e64 / len(lams)) / value
+        # error of every mixed result against the FP64 path (which meets the oracle bar)
+        err = []
+        for lam, rm, r6, Am, A6 in zip(lams, results[-len(lams):], r64, A_mixed, A64):
+            err.append({"lambda": lam,
+                        "objective_rel_diff": abs(rm.objective - r6.objective) / abs(r6.objective),
+                        "A_max_abs_diff_rel": float((Am - A6).abs().max() / A6.abs().max()),
+                        "support_diff": int(((Am != 0) != (A6 != 0)).sum()),
+                        "kkt_rel1": rm.kkt_rel1, "kkt_rel1_fp64": r6.kkt_rel1})
+        config["error_vs_fp64"] = err
     line = {
         "metric": "time-to-KKT<=1e-5 at n=10k (vs FP64 plain); batched solves/s; serving p50/p99",
         "value": value,
