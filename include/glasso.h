@@ -74,6 +74,11 @@ typedef struct {
                       a HIP graph per workspace shape and replayed; results are bitwise
                       the same as eager launches.  time_ms[1] then holds [1] + [2], and
                       time_ms[5] the whole A Z A sequence.  Default 0. */
+  int w_mixed;     /* W = V^T V (V = inv(L), FP64) in FP32 MFMA while a problem iterates;
+                      before it stops (KKT <= tol or max_iter) W and the measures are
+                      recomputed in FP64 and only those decide, after which the problem
+                      keeps FP64 W.  Returned W and reported measures are always FP64.
+                      -1 (default): on for the mixed precisions, off for FP64; 0 off; 1 on. */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)
@@ -180,7 +185,9 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
                            double* logdet, void* stream);
 
 /* W = A^{-1} (full symmetric) from the Cholesky factor of A (eq. grad_hessian
- * needs it for g = S - W).  Errors: NOT_PD when A is not PD. */
+ * needs it for g = S - W).  With opt.w_mixed == 1 the product V^T V (V = inv(L),
+ * FP64) runs in FP32, as in the mixed-W iterations of glasso_solve.
+ * Errors: NOT_PD when A is not PD. */
 glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W, void* stream);
 
 /* One gradient pass (Sec. 3.1 eqs. grad_hessian, free_set, M; eq. G+):

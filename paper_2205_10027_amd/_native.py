@@ -21,6 +21,7 @@ class GlassoOptions(ctypes.Structure):
         ("warm_start", ctypes.c_int),
         ("tile_policy", ctypes.c_int),
         ("graphs", ctypes.c_int),
+        ("w_mixed", ctypes.c_int),
     ]
 
 

@@ -18,6 +18,7 @@ constexpr int LDK = BK + 4;  // 144-byte rows: 16-byte aligned, banks spread
 
 struct GemmF32Params {
   int M, N, K, tiles_m, tiles_n, lower_out;
+  int k_from_row;  // with lower_out: k starts at the tile's first row (A = B upper-zero, e.g. V^T)
   const float* A;
   const float* B;
   void* C;
@@ -55,7 +56,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_nt_kernel(GemmF32Params p) {
   __shared__ __attribute__((aligned(16))) float Bs[2][BN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  // with a K range that depends on the tile row, contiguous tile ranges per XCD
+  // would give one XCD all the long tiles: keep the hardware's round-robin order
+  // (lower_tile enumerates the long top bands first)
+  const int L = p.k_from_row ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
   int ti, tj;
   if (p.lower_out)
     lower_tile(L, p.tiles_m, ti, tj);
@@ -69,14 +73,15 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_nt_kernel(GemmF32Params p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
 
+  const int kbeg = p.k_from_row ? m0 : 0;
   float ra[16], rb[16];
-  load_slice(p.A, p.lda, m0, 0, tid, ra);
-  load_slice(p.B, p.ldb, n0, 0, tid, rb);
+  load_slice(p.A, p.lda, m0, kbeg, tid, ra);
+  load_slice(p.B, p.ldb, n0, kbeg, tid, rb);
   store_slice(As[0], tid, ra);
   store_slice(Bs[0], tid, rb);
   __syncthreads();
   int cur = 0;
-  for (int kt = 0; kt < p.K; kt += BK) {
+  for (int kt = kbeg; kt < p.K; kt += BK) {
     const bool more = kt + BK < p.K;
     if (more) {
       load_slice(p.A, p.lda, m0, kt + BK, tid, ra);
@@ -119,6 +124,30 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_nt_kernel(GemmF32Params p) {
     }
 }
 
+// Vt[i][k] = V[k][i] in FP32 for k >= i, 0 above (V lower triangular, np x np),
+// through 64x64 LDS tiles so both the reads and the writes are coalesced.
+__global__ __launch_bounds__(256) void lower_to_f32_transposed_kernel(const double* __restrict__ V, int64_t np,
+                                                                      float* __restrict__ Vt, int64_t sV,
+                                                                      int64_t sVt, const int* skip) {
+  if (skip && skip[blockIdx.z]) return;
+  V += blockIdx.z * sV;
+  Vt += blockIdx.z * sVt;
+  __shared__ float t[64][65];
+  const int bi = blockIdx.x, bk = blockIdx.y;  // output tile: rows i of Vt, columns k
+  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)bi * 64, k0 = (int64_t)bk * 64;
+  if (bk < bi) {  // every k < i: zeros
+    for (int r = r0; r < 64; r += 4) Vt[(i0 + r) * np + k0 + c] = 0.f;
+    return;
+  }
+  for (int r = r0; r < 64; r += 4) t[r][c] = (float)V[(k0 + r) * np + i0 + c];  // t[k][i]
+  __syncthreads();
+  for (int r = r0; r < 64; r += 4) {
+    const int64_t i = i0 + r, k = k0 + c;
+    Vt[i * np + k] = (k >= i) ? t[c][r] : 0.f;
+  }
+}
+
 __global__ void f64_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t count) {
   for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; e < count;
        e += (int64_t)gridDim.x * blockDim.x * 2) {
@@ -130,11 +159,14 @@ __global__ void f64_to_f32_kernel(const double* __restrict__ src, float* __restr
 }  // namespace
 
 int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda, const float* B, int64_t ldb,
-                void* C, int64_t ldc, int c_is_double, int lower_out, const ZBatch& zb, const int* skip) {
+                void* C, int64_t ldc, int c_is_double, int lower_out, const ZBatch& zb, const int* skip,
+                int k_from_row) {
   if (M <= 0 || N <= 0 || zb.count <= 0) return 0;
   if (M % BM || N % BN || K % BK || K <= 0) return -1;
   if (lower_out && M != N) return -1;
+  if (k_from_row && !lower_out) return -1;
   GemmF32Params p;
+  p.k_from_row = k_from_row;
   p.M = M;
   p.N = N;
   p.K = K;
@@ -156,6 +188,14 @@ int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t
     hipLaunchKernelGGL(gemm_f32_nt_kernel<double>, dim3(tiles, 1, zb.count), dim3(256), 0, stream, p);
   else
     hipLaunchKernelGGL(gemm_f32_nt_kernel<float>, dim3(tiles, 1, zb.count), dim3(256), 0, stream, p);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int lower_to_f32_transposed(hipStream_t stream, const double* V, int64_t np, float* Vt, int count, int64_t sV,
+                            int64_t sVt, const int* skip) {
+  if (np % 64 || count <= 0) return np % 64 ? -1 : 0;
+  const int T = (int)(np / 64);
+  hipLaunchKernelGGL(lower_to_f32_transposed_kernel, dim3(T, T, count), dim3(256), 0, stream, V, np, Vt, sV, sVt, skip);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

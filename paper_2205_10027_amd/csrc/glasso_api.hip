@@ -38,6 +38,7 @@ struct Workspace {
   double* part = nullptr;
   double* scal = nullptr;
   int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
+  int *skip32 = nullptr, *skip64 = nullptr;  // W products in FP32 / FP64 (the mixed-W ladder)
   double *lam = nullptr, *t = nullptr;
   int64_t* bad = nullptr;
   double* vec = nullptr;
@@ -76,6 +77,8 @@ size_t layout(Workspace& w, int count, int64_t np, char* base) {
   w.skip = (int*)take(count * sizeof(int));
   w.lsskip = (int*)take(count * sizeof(int));
   w.accept = (int*)take(count * sizeof(int));
+  w.skip32 = (int*)take(count * sizeof(int));
+  w.skip64 = (int*)take(count * sizeof(int));
   w.lam = (double*)take(count * sizeof(double));
   w.t = (double*)take(count * sizeof(double));
   w.bad = (int64_t*)take(sizeof(int64_t));
@@ -88,6 +91,7 @@ struct HostMirror {
   int cap = 0;
   double* scal = nullptr;
   int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
+  int *skip32 = nullptr, *skip64 = nullptr;
   double *lam = nullptr, *t = nullptr;
   int64_t* bad = nullptr;
 };
@@ -106,7 +110,7 @@ struct GraphKey {
 };
 struct Graphs {
   GraphKey key;
-  hipGraphExec_t head = nullptr, prod = nullptr, trial = nullptr, acc = nullptr;
+  hipGraphExec_t head = nullptr, prod = nullptr, trial = nullptr, acc = nullptr, rechk = nullptr;
 };
 
 }  // namespace
@@ -145,7 +149,7 @@ glasso_err ensure_host(glasso_handle h, int count) {
   HostMirror& m = h->hm;
   if (m.scal && m.cap >= count) return GLASSO_OK;
   free_host(m);
-  const size_t bytes = (size_t)count * (SC_COUNT + 2) * sizeof(double) + (size_t)count * 4 * sizeof(int) + 64;
+  const size_t bytes = (size_t)count * (SC_COUNT + 2) * sizeof(double) + (size_t)count * 6 * sizeof(int) + 64;
   char* p = nullptr;
   if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) return GLASSO_ERR_HIP;
   m.cap = count;
@@ -156,7 +160,9 @@ glasso_err ensure_host(glasso_handle h, int count) {
   m.skip = m.info + count;
   m.lsskip = m.skip + count;
   m.accept = m.lsskip + count;
-  m.bad = (int64_t*)(((uintptr_t)(m.accept + count) + 7) & ~uintptr_t(7));
+  m.skip32 = m.accept + count;
+  m.skip64 = m.skip32 + count;
+  m.bad = (int64_t*)(((uintptr_t)(m.skip64 + count) + 7) & ~uintptr_t(7));
   return GLASSO_OK;
 }
 
@@ -228,7 +234,7 @@ glasso_err fetch(glasso_handle h, hipStream_t st) {
 }
 
 void drop_graphs(Graphs& g) {
-  for (hipGraphExec_t* x : {&g.head, &g.prod, &g.trial, &g.acc})
+  for (hipGraphExec_t* x : {&g.head, &g.prod, &g.trial, &g.acc, &g.rechk})
     if (*x) (void)hipGraphExecDestroy(*x);
   g = Graphs();
 }
@@ -267,7 +273,8 @@ bool valid_precision(int p) { return p == GLASSO_FP64 || p == GLASSO_MIXED_FP32 
 
 glasso_err check_options(const glasso_options* o) {
   if (!valid_precision(o->precision)) return GLASSO_ERR_INVALID_ARG;
-  if (o->max_iter < 0 || o->tile_policy < GLASSO_TILES_AUTO) return GLASSO_ERR_INVALID_ARG;
+  if (o->max_iter < 0 || o->tile_policy < GLASSO_TILES_AUTO || o->w_mixed < -1 || o->w_mixed > 1)
+    return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -294,6 +301,21 @@ glasso_err factor_all(glasso_handle h, hipStream_t st) {
 
 // W (lower) = A^{-1} from the factor in w.L for every problem with skip == 0:
 // L <- inv(L) in place, W = inv(L)^T inv(L).  tmp: the X buffer.
+// W (lower) = V^T V in FP32 MFMA from V = inv(L) already in w.L, for every problem
+// with skip == 0: Vt = V^T in FP32 (the X buffer, 2 nn floats per problem), then
+// the lower triangle of Vt Vt^T written FP64 with the k loop clipped to k >= row.
+glasso_err lauum_f32(Workspace& w, hipStream_t st, const int* skip) {
+  const int64_t nn = w.nn();
+  float* Vt = reinterpret_cast<float*>(w.X);
+  K_TRY(lower_to_f32_transposed(st, w.L, w.np, Vt, w.count, nn, 2 * nn, skip));
+  ZBatch z;
+  z.count = w.count;
+  z.sA = z.sB = 2 * nn;
+  z.sC = nn;
+  K_TRY(gemm_f32_nt(st, (int)w.np, (int)w.np, (int)w.np, Vt, w.np, Vt, w.np, w.W, w.np, 1, 1, z, skip, 1));
+  return GLASSO_OK;
+}
+
 glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
   const FactorBatch fb = factor_batch(w);
   K_TRY(trtri_lower(st, w.L, w.np, (int)w.np, w.Dinv, w.X, skip, fb, w.nn()));
@@ -540,15 +562,39 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   // The four launch sequences of an iteration.  Each reads its host inputs from
   // the pinned mirrors when it runs and ends without waiting; `timed` adds the
   // phase events (eager runs only).
+  // W precision ladder (mixed forms): W = V^T V in FP32 while a problem iterates;
+  // once its KKT measure (or the iteration cap) says stop, W and the measures are
+  // recomputed in FP64 from the same V and only the FP64 values decide; from then on
+  // that problem keeps FP64 W.  Every returned W and reported measure is FP64.
+  const bool w_mixed = (o.w_mixed < 0) ? (o.precision != GLASSO_FP64) : (o.w_mixed != 0);
+  std::vector<int> wexact(count, w_mixed ? 0 : 1), wlast(count, 1);
+  PassBatch pr = pb;  // FP64 re-check of the problems in skip64 == 0
+  pr.skip = w.skip64;
+  const FactorBatch fbw = factor_batch(w);
   auto head = [&](hipStream_t s, bool timed) -> glasso_err {  // a1, a2
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
-    if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
-    e2 = inverse_from_factor(w, s, w.skip);
+    e2 = push_ints(s, w.skip32, hm.skip32, count);
     if (e2) return e2;
+    e2 = push_ints(s, w.skip64, hm.skip64, count);
+    if (e2) return e2;
+    if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
+    K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip, fbw, nn));
+    K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
+    if (w_mixed) {
+      e2 = lauum_f32(w, s, w.skip32);
+      if (e2) return e2;
+    }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
     K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
+    return fetch_async(h, s);
+  };
+  auto recheck = [&](hipStream_t s, bool) -> glasso_err {  // a1, a2 in FP64 for skip64 == 0
+    glasso_err e2 = push_ints(s, w.skip64, hm.skip64, count);
+    if (e2) return e2;
+    K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pr));
     return fetch_async(h, s);
   };
   auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
@@ -600,8 +646,24 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   };
 
   double phase[8] = {0};
+  // FP64 W and measures for the problems with mark[b] != 0 (skip64 = !mark)
+  auto run_recheck = [&](const std::vector<int>& mark) -> glasso_err {
+    for (int b = 0; b < count; ++b) hm.skip64[b] = !mark[b];
+    glasso_err e2 = run(&h->graphs.rechk, recheck);
+    if (e2) return e2;
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < count; ++b)
+      if (mark[b]) wlast[b] = 1;
+    return GLASSO_OK;
+  };
+
   for (;;) {
-    for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
+    for (int b = 0; b < count; ++b) {
+      hm.skip[b] = !active[b];
+      hm.skip32[b] = !(active[b] && !wexact[b]);
+      hm.skip64[b] = !(active[b] && wexact[b]);
+      if (active[b]) wlast[b] = wexact[b];
+    }
     if (graphs) HIP_TRY(hipEventRecord(h->ev[0], st));
     e = run(&h->graphs.head, head);
     if (e) return e;
@@ -612,6 +674,19 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     HIP_TRY(hipStreamSynchronize(st));
     phase[1] += elapsed(h->ev[0], h->ev[1]);
     phase[2] += elapsed(h->ev[1], h->ev[2]);
+    // a problem that would stop on an FP32 W is re-checked with FP64 W first
+    std::vector<int> mark(count, 0);
+    int nmark = 0;
+    for (int b = 0; b < count; ++b)
+      if (active[b] && !wexact[b] && (hscal(h, b, SC_KKT_REL1) <= tol || it[b] >= o.max_iter)) {
+        mark[b] = 1;
+        wexact[b] = 1;
+        ++nmark;
+      }
+    if (nmark) {
+      e = run_recheck(mark);
+      if (e) return e;
+    }
     int nact = 0;
     for (int b = 0; b < count; ++b) {
       if (!active[b]) continue;
@@ -692,6 +767,19 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     phase[5] += elapsed(h->ev[5], h->ev[6]);
   }
 
+  {
+    std::vector<int> mark(count, 0);
+    int nmark = 0;
+    for (int b = 0; b < count; ++b)
+      if (!wlast[b]) {
+        mark[b] = 1;
+        ++nmark;
+      }
+    if (nmark) {
+      e = run_recheck(mark);
+      if (e) return e;
+    }
+  }
   for (int b = 0; b < count; ++b) {
     K_TRY(sym_copy_out(st, w.A + b * nn, np, Aout[b], n, 0));
     if (Wout && Wout[b]) K_TRY(sym_copy_out(st, w.W + b * nn, np, Wout[b], n, 1));
@@ -729,6 +817,7 @@ glasso_err glasso_default_options(glasso_options* opt) {
   opt->precision = GLASSO_FP64;
   opt->tile_policy = GLASSO_TILES_AUTO;
   opt->graphs = 0;
+  opt->w_mixed = -1;
   opt->max_iter = 500;
   opt->t0 = 1.0;
   opt->shrink = 0.5;
@@ -984,7 +1073,13 @@ glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W
   e = factor_all(h, st);
   if (e) return e;
   if (h->hm.info[0]) return GLASSO_ERR_NOT_PD;
-  e = inverse_from_factor(w, st, nullptr);
+  if (h->opt.w_mixed == 1) {
+    // the mixed-W product of the ladder: FP64 V = inv(L), then V^T V in FP32
+    K_TRY(trtri_lower(st, w.L, np, (int)np, w.Dinv, w.X, nullptr, factor_batch(w), w.nn()));
+    e = lauum_f32(w, st, nullptr);
+  } else {
+    e = inverse_from_factor(w, st, nullptr);
+  }
   if (e) return e;
   K_TRY(sym_copy_out(st, w.W, np, W, n, 1));
   HIP_TRY(hipStreamSynchronize(st));

@@ -31,9 +31,16 @@ int get_gemm_f64_small_tile_below();
 
 // C = A B^T on FP32 MFMA with FP32 accumulation (A: M x K, B: N x K, row-major
 // FP32); C is float or (c_is_double) double; lower_out as in gemm_f64.
+// k_from_row (with lower_out): the k loop of tile row ti starts at 128 ti, for
+// A = B with A[i][k] = 0 when k < i (W = V^T V from Vt = V^T).
 int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda,
                 const float* B, int64_t ldb, void* C, int64_t ldc, int c_is_double,
-                int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr);
+                int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr,
+                int k_from_row = 0);
+// Vt = V^T in FP32 with zeros above the diagonal, for count lower-triangular V
+// (np x np, np a multiple of 64; problem strides sV doubles, sVt floats)
+int lower_to_f32_transposed(hipStream_t stream, const double* V, int64_t np, float* Vt, int count,
+                            int64_t sV, int64_t sVt, const int* skip);
 int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
 
 // C = A B^T as three BF16 products with FP32 accumulation; A (M x K) and B (N x K)

@@ -51,7 +51,7 @@ def test_host_only_entry_points():
         g.workspace_bytes(100, 3)
     assert lib.glasso_create(None, None) == 1
     # option checks run before any device call
-    assert opt.tile_policy == g.TILES_AUTO == -1 and opt.graphs == 0
+    assert opt.tile_policy == g.TILES_AUTO == -1 and opt.graphs == 0 and opt.w_mixed == -1
     h = ctypes.c_void_p()
     bad = g.GlassoOptions()
     lib.glasso_default_options(ctypes.byref(bad))
@@ -72,8 +72,8 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
-         offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+         offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
          offsetof(glasso_info, time_ms));
   return 0;
@@ -85,6 +85,6 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, g.GlassoOptions.tile_policy.offset,
-            g.GlassoOptions.graphs.offset, ctypes.sizeof(g.GlassoInfo),
+            g.GlassoOptions.graphs.offset, g.GlassoOptions.w_mixed.offset, ctypes.sizeof(g.GlassoInfo),
             g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset]
     assert [int(x) for x in out] == want
