@@ -74,7 +74,8 @@ typedef struct {
                       a HIP graph per workspace shape and replayed; results are bitwise
                       the same as eager launches.  time_ms[1] then holds [1] + [2], and
                       time_ms[5] the whole A Z A sequence.  Default 0. */
-  int w_mixed;     /* W = V^T V (V = inv(L), FP64) in FP32 MFMA while a problem iterates;
+  int w_mixed;     /* W = A^{-1} from the FP64 factor in FP32 MFMA (triangular inverse and
+                      V^T V) while a problem iterates;
                       before it stops (KKT <= tol or max_iter) W and the measures are
                       recomputed in FP64 and only those decide, after which the problem
                       keeps FP64 W.  Returned W and reported measures are always FP64.
@@ -185,8 +186,8 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
                            double* logdet, void* stream);
 
 /* W = A^{-1} (full symmetric) from the Cholesky factor of A (eq. grad_hessian
- * needs it for g = S - W).  With opt.w_mixed == 1 the product V^T V (V = inv(L),
- * FP64) runs in FP32, as in the mixed-W iterations of glasso_solve.
+ * needs it for g = S - W).  With opt.w_mixed == 1 the triangular inverse and the
+ * product V^T V run in FP32 MFMA, as in the mixed-W iterations of glasso_solve.
  * Errors: NOT_PD when A is not PD. */
 glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W, void* stream);
 

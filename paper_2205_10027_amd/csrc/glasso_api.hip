@@ -301,18 +301,21 @@ glasso_err factor_all(glasso_handle h, hipStream_t st) {
 
 // W (lower) = A^{-1} from the factor in w.L for every problem with skip == 0:
 // L <- inv(L) in place, W = inv(L)^T inv(L).  tmp: the X buffer.
-// W (lower) = V^T V in FP32 MFMA from V = inv(L) already in w.L, for every problem
-// with skip == 0: Vt = V^T in FP32 (the X buffer, 2 nn floats per problem), then
-// the lower triangle of Vt Vt^T written FP64 with the k loop clipped to k >= row.
-glasso_err lauum_f32(Workspace& w, hipStream_t st, const int* skip) {
+// W (lower) = A^{-1} in FP32 MFMA for every problem with skip == 0, from its
+// factor in w.L (left unchanged) and diagonal-block inverses: V = inv(L) and V^T
+// by FP32 doubling (T, Tt in the X buffer, scratch in the P buffer), then the
+// lower triangle of Vt Vt^T written FP64 with the k loop clipped to k >= row.
+glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
   const int64_t nn = w.nn();
-  float* Vt = reinterpret_cast<float*>(w.X);
-  K_TRY(lower_to_f32_transposed(st, w.L, w.np, Vt, w.count, nn, 2 * nn, skip));
+  float* T = reinterpret_cast<float*>(w.X);
+  float* Tt = T + nn;
+  float* tmp = reinterpret_cast<float*>(w.P);
+  K_TRY(trtri_f32(st, w.L, w.Dinv, w.np, T, Tt, tmp, w.count, nn, w.np * TILE, 2 * nn, 2 * nn, skip));
   ZBatch z;
   z.count = w.count;
   z.sA = z.sB = 2 * nn;
   z.sC = nn;
-  K_TRY(gemm_f32_nt(st, (int)w.np, (int)w.np, (int)w.np, Vt, w.np, Vt, w.np, w.W, w.np, 1, 1, z, skip, 1));
+  K_TRY(gemm_f32_nt(st, (int)w.np, (int)w.np, (int)w.np, Tt, w.np, Tt, w.np, w.W, w.np, 1, 1, z, skip, 1));
   return GLASSO_OK;
 }
 
@@ -579,10 +582,12 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     e2 = push_ints(s, w.skip64, hm.skip64, count);
     if (e2) return e2;
     if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
-    K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip, fbw, nn));
+    // FP64 problems: V = inv(L) in place, W = V^T V; FP32 problems keep L intact
+    // (their FP64 re-check starts from it)
+    K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
     if (w_mixed) {
-      e2 = lauum_f32(w, s, w.skip32);
+      e2 = inverse_f32(w, s, w.skip32);
       if (e2) return e2;
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
@@ -593,6 +598,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   auto recheck = [&](hipStream_t s, bool) -> glasso_err {  // a1, a2 in FP64 for skip64 == 0
     glasso_err e2 = push_ints(s, w.skip64, hm.skip64, count);
     if (e2) return e2;
+    K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
     K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pr));
     return fetch_async(h, s);
@@ -1074,9 +1080,7 @@ glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W
   if (e) return e;
   if (h->hm.info[0]) return GLASSO_ERR_NOT_PD;
   if (h->opt.w_mixed == 1) {
-    // the mixed-W product of the ladder: FP64 V = inv(L), then V^T V in FP32
-    K_TRY(trtri_lower(st, w.L, np, (int)np, w.Dinv, w.X, nullptr, factor_batch(w), w.nn()));
-    e = lauum_f32(w, st, nullptr);
+    e = inverse_f32(w, st, nullptr);  // the mixed-W inverse of the ladder
   } else {
     e = inverse_from_factor(w, st, nullptr);
   }

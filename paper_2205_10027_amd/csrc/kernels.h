@@ -37,10 +37,11 @@ int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t
                 const float* B, int64_t ldb, void* C, int64_t ldc, int c_is_double,
                 int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr,
                 int k_from_row = 0);
-// Vt = V^T in FP32 with zeros above the diagonal, for count lower-triangular V
-// (np x np, np a multiple of 64; problem strides sV doubles, sVt floats)
-int lower_to_f32_transposed(hipStream_t stream, const double* V, int64_t np, float* Vt, int count,
-                            int64_t sV, int64_t sVt, const int* skip);
+// V = inv(L) in FP32 into T and V^T into Tt (np x np each), from the factor L
+// (lower, FP64) and its diagonal-block inverses Dinv; L is not modified.  tmp:
+// scratch of np^2 / 2 floats.  Problem strides in elements of each buffer.
+int trtri_f32(hipStream_t stream, const double* L, const double* Dinv, int64_t np, float* T, float* Tt, float* tmp,
+              int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTmp, const int* skip);
 int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
 
 // C = A B^T as three BF16 products with FP32 accumulation; A (M x K) and B (N x K)
