@@ -280,6 +280,23 @@ def main():
               "iterations": [r.iterations for r in results[:len(lams)]],
               "ls_trials": [r.ls_trials for r in results[:len(lams)]],
               "solves_per_s": solves / elapsed}
+    # every phase of an iteration against its own roofline, from the solver's HIP
+    # events: W = A^-1 (2 n^3/3 flops per iteration: triangular inverse + V^T V),
+    # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
+    # elementwise passes sit in the same window), A Z A (above)
+    trials = sum(r.ls_trials for r in results)
+    w_ms = sum(r.time_ms[1] for r in results)
+    ls_ms = sum(r.time_ms[4] for r in results)
+    w_peak = PEAK_TFLOPS["fp64"] if args.precision == "fp64" else PEAK_TFLOPS["fp32"]
+    w_tf = (2.0 / 3.0) * float(n) ** 3 * iters / (w_ms / 1000.0) / 1e12
+    ls_tf = float(n) ** 3 / 3.0 * trials / (ls_ms / 1000.0) / 1e12
+    phases = {"inverse_W": {"ms_per_iteration": w_ms / iters, "achieved_tflops": w_tf, "peak_tflops": w_peak,
+                            "frac": w_tf / w_peak,
+                            "precision": "fp64" if args.precision == "fp64" else "fp32 while iterating, fp64 re-check"},
+              "line_search": {"ms_per_trial": ls_ms / trials, "achieved_tflops": ls_tf,
+                              "peak_tflops": PEAK_TFLOPS["fp64"], "frac": ls_tf / PEAK_TFLOPS["fp64"],
+                              "precision": "fp64 (Cholesky of each trial point)"},
+              "AZA": {"ms_per_iteration": sum(r.time_ms[3] for r in results) / iters}}
     if not args.no_fp64_ref and args.precision != "fp64":
         e64, r64, A64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
         config["fp64_plain_s"] = e64 / len(lams)
@@ -308,6 +325,7 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "fp32+f64", "bf16x3": "bf16x3+f64"}[args.precision],
         "data": "synthetic",
         "config": config,
+        "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": TRAFFIC_BYTES[args.precision], "traffic_unit": "B", "kernel": kernel,
                      "avg_launch_ms": avg_launch_s * 1000.0, "launches": launches},

@@ -23,34 +23,51 @@ constexpr int OUTER = 1024;    // outer panel width of the two-level Cholesky
 // One step of the blocked Cholesky: the 128-column block whose diagonal block is at
 // A, with `rest` rows of the panel below it (a multiple of 64).
 //
-// Every workgroup factors (lds_potrf) and inverts (lds_trtri) the diagonal block in
-// LDS; all of them compute identical values.  Workgroup 0 writes diag(L) to dL,
-// inv(L11) to Dinv (ld 128, zeros above the diagonal) and the strict lower part of
-// L11 transposed into the strict upper triangle of the block: the lower triangle is
-// still being read by the other workgroups, so place_diag_factor moves L11 into
-// place after the whole factorisation.  Workgroup 1 + q solves rows 64q .. 64q + 63
-// of the panel below, L21 = A21 inv(L11)^T, in place: it owns those rows entirely.
-// k0 is the block's global column, used to report the first failing pivot.
-__global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t lda, int k0, int rest,
-                                                             double* dL, double* Dinv, int* info,
-                                                             FactorBatch fb) {
+// Every workgroup factors the diagonal block in LDS (lds_potrf); all of them
+// compute identical values.  Workgroup 0 writes diag(L) to dL and the strict lower
+// part of L11 transposed into the strict upper triangle of the block: the lower
+// triangle is still being read by the other workgroups, so finish_diag_blocks
+// moves L11 into place after the whole factorisation (and inverts it there).
+// Workgroup 1 + q solves rows 64q .. 64q + 63 of the panel below,
+// L21 = A21 inv(L11)^T, in place: it owns those rows entirely.  k0 is the block's
+// global column, used to report the first failing pivot.
+//
+// The solve works on the transpose, X^T = inv(L11) R^T, in 16-column blocks b:
+//   Y_b^T = R_b^T - sum_{q<b} L_bq X_q^T,   X_b^T = inv(L_bb) Y_b^T,
+// with the inverses of the eight 16x16 diagonal blocks computed first.  In the
+// v_mfma_f64_16x16x4f64 layouts the output block X_q^T (element (i, j) in lane
+// j + 16 (i%4), register i/4) is exactly the B operand of the k-steps over its
+// 16 rows, so every X_q stays in registers until the store.
+__global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda, int k0, int rest, double* dL,
+                                                         int* info, FactorBatch fb) {
   // problem blockIdx.y of the batch
   A += blockIdx.y * fb.sA;
   dL += blockIdx.y * fb.sdL;
-  Dinv += blockIdx.y * fb.sDinv;
   info += blockIdx.y;
   if (*info) return;
   __shared__ double a[NB][LDL];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool solver = blockIdx.x > 0 && rest > 0;
+
+  // rows of the panel owned by this wave: R[16 wave + i][.], loaded up front in the
+  // layout of Y_b^T (register s of lane l: R[l%16][16b + 4s + l/16])
+  double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
+  v4d x[8];
+  if (solver) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
+  }
 
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
 #pragma unroll 8
   for (int i = 0; i < NB * NB / 512; ++i) {
     const int e = 2 * (tid + 256 * i);
     const int r = e >> 7, c = e & 127;
-    const double2 x = *reinterpret_cast<const double2*>(A + (int64_t)r * lda + c);
-    a[r][c] = (c <= r) ? x.x : 0.0;
-    a[r][c + 1] = (c + 1 <= r) ? x.y : 0.0;
+    const double2 v = *reinterpret_cast<const double2*>(A + (int64_t)r * lda + c);
+    a[r][c] = (c <= r) ? v.x : 0.0;
+    a[r][c + 1] = (c + 1 <= r) ? v.y : 0.0;
   }
   __syncthreads();
 
@@ -67,58 +84,93 @@ __global__ __launch_bounds__(256) void leaf_potrf_inv_kernel(double* A, int64_t 
       if (c < r) A[(int64_t)c * lda + r] = a[r][c];
     }
     if (tid < NB) dL[tid] = a[tid][tid];
-  }
-  __syncthreads();
-  lds_trtri<NB>(a, tid);
-  if (blockIdx.x == 0) {
-#pragma unroll 8
-    for (int i = 0; i < NB * NB / 256; ++i) {
-      const int e = tid + 256 * i;
-      const int r = e >> 7, c = e & 127;
-      Dinv[e] = (c <= r) ? a[r][c] : 0.0;
-    }
     return;
   }
-  if (rest <= 0) return;
-  // rows 64q .. 64q + 63 below the block; wave w takes 16 of them.  A operand of
-  // k-step s: R[16w + lane%16][4s + lane/16] (v_mfma_f64_16x16x4f64 A layout);
-  // B operand inv(L11)^T (k, c) = inv(L11)[c][k], zero for k > c (the upper
-  // triangle of a is scratch).
-  double* R = A + (int64_t)(NB + 64 * (blockIdx.x - 1)) * lda;
-  const double* Rw = R + (int64_t)(16 * wave + (lane & 15)) * lda + (lane >> 4);
-  double af[NB / 4];
+  if (!solver) return;
+
+  // inverses of the 16x16 diagonal blocks: wave w inverts block 2w in lanes 0..15
+  // and block 2w + 1 in lanes 32..47, lane c computing column c by forward
+  // substitution.  They go to the free strict upper triangle: block b < 7 at tile
+  // (b, 7), block 7 at tile (0, 6) (16x16 tiles).
+  {
+    const int c = lane & 31, b = 2 * wave + (lane >> 5), o = 16 * b;
+    if (c < 16) {
+      double rd[16], xv[16];
 #pragma unroll
-  for (int s = 0; s < NB / 4; ++s) af[s] = Rw[4 * s];
-  v4d acc[8];
+      for (int i = 0; i < 16; ++i) rd[i] = 1.0 / a[o + i][o + i];
 #pragma unroll
-  for (int cb = 0; cb < 8; ++cb) acc[cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < 16; ++i) {
+        double s = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-  for (int s = 0; s < NB / 4; ++s) {
+        for (int k = 0; k < i; ++k) s -= a[o + i][o + k] * xv[k];
+        xv[i] = s * rd[i];
+      }
+      const int r0 = (b < 7) ? o : 0, c0 = (b < 7) ? 112 : 96;
 #pragma unroll
-    for (int cb = s / 4; cb < 8; ++cb) {
-      const int c = 16 * cb + (lane & 15), k = 4 * s + (lane >> 4);
-      const double y = (k <= c) ? a[c][k] : 0.0;
-      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s], y, acc[cb], 0, 0, 0);
+      for (int i = 0; i < 16; ++i) a[r0 + i][c0 + c] = xv[i];
     }
   }
+  __syncthreads();
+
+  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int cb = 0; cb < 8; ++cb)
-    for_block(acc[cb], lane, [&](int r, int c, double v) { R[(int64_t)(16 * wave + r) * lda + 16 * cb + c] = v; });
+  for (int q = 0; q < 8; ++q) {
+    // X_q^T = inv(L_qq) Y_q^T
+    const int r0 = (q < 7) ? 16 * q : 0, c0 = (q < 7) ? 112 : 96;
+    v4d xq = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      xq = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + li][c0 + 4 * s + lk], x[q][s], xq, 0, 0, 0);
+    x[q] = xq;
+    // Y_b^T -= L_bq X_q^T for the later blocks
+#pragma unroll
+    for (int b = q + 1; b < 8; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + li][16 * q + 4 * s + lk], x[q][s], x[b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) R[16 * b + 4 * s] = x[b][s];
 }
 
-// After the factorisation: the strict lower part of every 128x128 diagonal block
-// from its transposed copy in the strict upper triangle, the diagonal from dL.
-__global__ __launch_bounds__(256) void place_diag_factor_kernel(double* A, int64_t lda, const double* dL,
-                                                                const int* info, FactorBatch fb) {
+// After the factorisation, one workgroup per 128x128 diagonal block: the strict
+// lower part of the block from its transposed copy in the strict upper triangle,
+// the diagonal from dL; then the inverse of the block (lds_trtri) to Dinv (ld 128,
+// zeros above the diagonal).
+__global__ __launch_bounds__(256) void finish_diag_blocks_kernel(double* A, int64_t lda, const double* dL,
+                                                                 double* Dinv, const int* info, FactorBatch fb) {
   if (info[blockIdx.y]) return;
   double* D = A + blockIdx.y * fb.sA + (int64_t)blockIdx.x * NB * (lda + 1);
   const double* d = dL + blockIdx.y * fb.sdL + (int64_t)blockIdx.x * NB;
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+  double* Di = Dinv + blockIdx.y * fb.sDinv + (int64_t)blockIdx.x * NB * NB;
+  __shared__ double a[NB][LDL];
+  const int tid = threadIdx.x;
+  // row r of the stored block holds L[c][r] for c > r
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 512; ++i) {
+    const int e = 2 * (tid + 256 * i);
     const int r = e >> 7, c = e & 127;
-    if (c < r)
-      D[(int64_t)r * lda + c] = D[(int64_t)c * lda + r];
-    else if (c == r)
-      D[(int64_t)r * lda + r] = d[r];
+    const double2 v = *reinterpret_cast<const double2*>(D + (int64_t)r * lda + c);
+    a[c][r] = (c > r) ? v.x : 0.0;
+    a[c + 1][r] = (c + 1 > r) ? v.y : 0.0;
+  }
+  __syncthreads();
+  if (tid < NB) a[tid][tid] = d[tid];
+  __syncthreads();
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i;
+    const int r = e >> 7, c = e & 127;
+    if (c <= r) D[(int64_t)r * lda + c] = a[r][c];
+  }
+  lds_trtri<NB>(a, tid);
+#pragma unroll 8
+  for (int i = 0; i < NB * NB / 256; ++i) {
+    const int e = tid + 256 * i;
+    const int r = e >> 7, c = e & 127;
+    Di[e] = (c <= r) ? a[r][c] : 0.0;
   }
 }
 
@@ -148,11 +200,11 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
     for (int k = K0; k < K1 && rc == 0; k += NB) {
-      // factor + invert the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
+      // factor the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
       double* Akk = A + (int64_t)k * lda + k;
       const int rest = n - k - NB;
-      hipLaunchKernelGGL(leaf_potrf_inv_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k,
-                         rest, dL + k, Dinv + (int64_t)(k / NB) * NB * NB, info, fb);
+      hipLaunchKernelGGL(leaf_potrf_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k, rest,
+                         dL + k, info, fb);
       if (hipGetLastError() != hipSuccess) return -2;
       if (k + NB < K1) {
         // update of the remaining columns of the outer panel
@@ -170,7 +222,8 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
     }
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(place_diag_factor_kernel, dim3(n / NB, fb.count), dim3(256), 0, stream, A, lda, dL, info, fb);
+  hipLaunchKernelGGL(finish_diag_blocks_kernel, dim3(n / NB, fb.count), dim3(256), 0, stream, A, lda, dL, Dinv, info,
+                     fb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

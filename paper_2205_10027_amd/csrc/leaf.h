@@ -123,11 +123,11 @@ __device__ void lds_trtri(double (*a)[NB + 1], int tid) {
 //
 // Panels of 32 columns.  For a panel starting at c0, every wave holds the 32x32
 // diagonal block in lanes 0..31 (row c0+lane, one register per column) and factors
-// it redundantly: the pivot comes from readlane and the multipliers of the block
-// rows are broadcast with readlane.  Lanes 32..63 of the waves hold the rows below
-// the block and are eliminated in the same steps (the triangular solve of the
-// panel).  All 4 waves then apply the rank-32 update to the trailing lower
-// triangle.  Elements above the diagonal are never read as data.
+// it redundantly: column j of the block rows is broadcast with readlane, its
+// first entry being the pivot.  Lanes 32..63 of the waves hold the rows below the
+// block and are eliminated in the same steps (the triangular solve of the panel).
+// All 4 waves then apply the rank-32 update to the trailing lower triangle.
+// Elements above the diagonal are never read as data.
 template <int NB>
 __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
   const int lane = tid & 63, wave = tid >> 6;
@@ -142,16 +142,20 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
     for (int q = 0; q < PW; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
-      const double piv = lane_bcast(v[j], j);
+      // column j of the block rows, unscaled, as uniform values (readlane): they do
+      // not wait for the pivot's square root
+      double u[PW];
+#pragma unroll
+      for (int c = j; c < PW; ++c) u[c] = lane_bcast(v[j], c);
+      const double piv = u[j];
       const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
       if (!ok && fail < 0) fail = c0 + j;
       const double r = rsqrt(ok ? piv : 1.0);
-      const double m = v[j] * r;  // lane j: sqrt(piv); rows below: multipliers
-      v[j] = m;
-      // the multipliers of the block rows are uniform values: broadcast each one
-      // from its lane with readlane and update every later column
+      // L[row][j] L[c][j] = v[j] u[c] / piv
+      const double y = v[j] * (r * r);
+      v[j] = v[j] * r;  // lane j: sqrt(piv); rows below: L[row][j]
 #pragma unroll
-      for (int c = j + 1; c < PW; ++c) v[c] -= m * lane_bcast(m, c);
+      for (int c = j + 1; c < PW; ++c) v[c] -= y * u[c];
     }
     if (fail >= 0) break;
     if (valid && (lane >= PW || wave == 0)) {
