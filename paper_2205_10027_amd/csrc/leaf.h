@@ -12,7 +12,7 @@ namespace glasso {
 
 namespace {
 
-constexpr int PW = 32;  // panel width inside the block
+constexpr int PW = 32;  // edge of the diagonal blocks inverted in the first stage of lds_trtri
 
 // broadcast a double from a wave-uniform lane
 __device__ __forceinline__ double lane_bcast(double v, int lane) {
@@ -121,32 +121,38 @@ __device__ void lds_trtri(double (*a)[NB + 1], int tid) {
 // failing pivot (non-positive or NaN) or -1; the value is identical in every
 // thread, and on failure the block is left partially factored.
 //
-// Panels of 32 columns.  For a panel starting at c0, every wave holds the 32x32
-// diagonal block in lanes 0..31 (row c0+lane, one register per column) and factors
-// it redundantly: column j of the block rows is broadcast with readlane, its
-// first entry being the pivot.  Lanes 32..63 of the waves hold the rows below the
-// block and are eliminated in the same steps (the triangular solve of the panel).
-// All 4 waves then apply the rank-32 update to the trailing lower triangle.
-// Elements above the diagonal are never read as data.
+// Panels of PF = 16 columns.  For a panel starting at c0, every wave holds the
+// 16x16 diagonal block in lanes 0..15 (row c0+lane, one register per column) and
+// factors it redundantly: column j of the block rows is broadcast with readlane,
+// its first entry being the pivot.  Lanes 16..63 of the waves hold the rows below
+// the block (48 per wave) and are eliminated in the same steps (the triangular
+// solve of the panel).  All 4 waves then apply the rank-16 update to the trailing
+// lower triangle, two 16x16 blocks at a time per wave.  The broadcasts grow with
+// the square of the panel width, the update rounds only linearly with the number
+// of panels, which is why the panels are narrow.  Elements above the diagonal are
+// never read as data.
+constexpr int PF = 16;
+
 template <int NB>
 __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
   const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   int fail = -1;
 #pragma unroll 1
-  for (int p = 0; p < NB / PW; ++p) {
-    const int c0 = PW * p;
-    const int row = (lane < PW) ? c0 + lane : c0 + PW + wave * PW + (lane - PW);
+  for (int p = 0; p < NB / PF; ++p) {
+    const int c0 = PF * p;
+    const int row = (lane < PF) ? c0 + lane : c0 + PF + wave * (64 - PF) + (lane - PF);
     const bool valid = row < NB;
-    double v[PW];
+    double v[PF];
 #pragma unroll
-    for (int q = 0; q < PW; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
+    for (int q = 0; q < PF; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
 #pragma unroll
-    for (int j = 0; j < PW; ++j) {
+    for (int j = 0; j < PF; ++j) {
       // column j of the block rows, unscaled, as uniform values (readlane): they do
       // not wait for the pivot's square root
-      double u[PW];
+      double u[PF];
 #pragma unroll
-      for (int c = j; c < PW; ++c) u[c] = lane_bcast(v[j], c);
+      for (int c = j; c < PF; ++c) u[c] = lane_bcast(v[j], c);
       const double piv = u[j];
       const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
       if (!ok && fail < 0) fail = c0 + j;
@@ -155,26 +161,45 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
       const double y = v[j] * (r * r);
       v[j] = v[j] * r;  // lane j: sqrt(piv); rows below: L[row][j]
 #pragma unroll
-      for (int c = j + 1; c < PW; ++c) v[c] -= y * u[c];
+      for (int c = j + 1; c < PF; ++c) v[c] -= y * u[c];
     }
     if (fail >= 0) break;
-    if (valid && (lane >= PW || wave == 0)) {
+    if (valid && (lane >= PF || wave == 0)) {
 #pragma unroll
-      for (int q = 0; q < PW; ++q) a[row][c0 + q] = v[q];
+      for (int q = 0; q < PF; ++q) a[row][c0 + q] = v[q];
     }
     __syncthreads();
-    // rank-32 update of the trailing lower triangle in 16x16 MFMA blocks
-    const int base = c0 + PW, R = NB - base;
+    // rank-16 update of the trailing lower triangle: 16x16 blocks (bi >= bj) in
+    // row-major order of the triangle, wave w taking blocks w, w + 4 together,
+    // then w + 8, w + 12, ...
+    const int base = c0 + PF, R = NB - base;
     if (R > 0) {
       const int nb16 = R / 16;
       const int nblk = nb16 * (nb16 + 1) / 2;
-      for (int job = wave; job < nblk; job += 4) {
+      for (int job = wave; job < nblk; job += 8) {
+        const int job2 = job + 4;
+        const bool two = job2 < nblk;
         int bi = 0;
         while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
         const int bj = job - bi * (bi + 1) / 2;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        acc = mfma_block<false, false, false>(a, base + 16 * bi, c0, base + 16 * bj, c0, PW, acc, lane);
+        int bi2 = bi, bj2 = bj;
+        if (two) {
+          while ((bi2 + 1) * (bi2 + 2) / 2 <= job2) ++bi2;
+          bj2 = job2 - bi2 * (bi2 + 1) / 2;
+        }
+        v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < PF; k += 4) {
+          const double x1 = a[base + 16 * bi + li][c0 + k + lk];
+          const double y1 = a[base + 16 * bj + li][c0 + k + lk];
+          const double x2 = a[base + 16 * bi2 + li][c0 + k + lk];
+          const double y2 = a[base + 16 * bj2 + li][c0 + k + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc, 0, 0, 0);
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, y2, acc2, 0, 0, 0);
+        }
         for_block(acc, lane, [&](int r, int c, double v) { a[base + 16 * bi + r][base + 16 * bj + c] -= v; });
+        if (two)
+          for_block(acc2, lane, [&](int r, int c, double v) { a[base + 16 * bi2 + r][base + 16 * bj2 + c] -= v; });
       }
       __syncthreads();
     }
