@@ -625,6 +625,25 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     return GLASSO_OK;
   };
   const bool graphs = o.graphs != 0;
+  // A single problem run with eager launches takes an accepted trial point by
+  // exchanging the current and trial buffers (A, L, diag(L), the diagonal-block
+  // inverses) instead of copying them.  The exchange is undone when the call
+  // returns, so later calls (and graphs captured by them) see the usual layout.
+  struct BufferSwap {
+    Workspace& w;
+    int parity;
+    void flip() {
+      std::swap(w.A, w.At);
+      std::swap(w.L, w.Lt);
+      std::swap(w.dL, w.dLt);
+      std::swap(w.Dinv, w.Dinvt);
+      parity ^= 1;
+    }
+    ~BufferSwap() {
+      if (parity) flip();
+    }
+  } swapped{w, 0};
+  const bool swap_accept = !graphs && count == 1;
   if (graphs) {
     GraphKey key;
     key.base = w.base;
@@ -762,8 +781,12 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       }
       if (nacc) {
         // a7: accept
-        e = run(&h->graphs.acc, accept);
-        if (e) return e;
+        if (swap_accept) {
+          swapped.flip();
+        } else {
+          e = run(&h->graphs.acc, accept);
+          if (e) return e;
+        }
       }
     }
     HIP_TRY(hipEventRecord(h->ev[4], st));
