@@ -49,17 +49,6 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool solver = blockIdx.x > 0 && rest > 0;
 
-  // rows of the panel owned by this wave: R[16 wave + i][.], loaded up front in the
-  // layout of Y_b^T (register s of lane l: R[l%16][16b + 4s + l/16])
-  double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
-  v4d x[8];
-  if (solver) {
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
-  }
-
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
 #pragma unroll 8
   for (int i = 0; i < NB * NB / 512; ++i) {
@@ -70,6 +59,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
     a[r][c + 1] = (c + 1 <= r) ? v.y : 0.0;
   }
   __syncthreads();
+
+  // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
+  // (register s of lane l: R[l%16][16b + 4s + l/16]); issued after the block is in
+  // LDS, they arrive while it is being factored
+  double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
+  v4d x[8];
+  if (solver) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
+  }
 
   const int fail = lds_potrf<NB>(a, tid);
   if (fail >= 0) {

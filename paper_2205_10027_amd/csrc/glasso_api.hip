@@ -306,16 +306,17 @@ glasso_err factor_all(glasso_handle h, hipStream_t st) {
 // by FP32 doubling (T, Tt in the X buffer, scratch in the P buffer), then the
 // lower triangle of Vt Vt^T written FP64 with the k loop clipped to k >= row.
 glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
+  // W = A^-1 with FP32 accuracy on the BF16 matrix cores: V = inv(L) by recursive
+  // doubling and W = V^T V, every operand an exact three-part bf16 split of an FP32
+  // value (6 bytes per element), six products per element pair.  V split in X,
+  // V^T split in P, the doubling's scratch (at most nn/4 elements) after it in P.
   const int64_t nn = w.nn();
-  float* T = reinterpret_cast<float*>(w.X);
-  float* Tt = T + nn;
-  float* tmp = reinterpret_cast<float*>(w.P);
-  K_TRY(trtri_f32(st, w.L, w.Dinv, w.np, T, Tt, tmp, w.count, nn, w.np * TILE, 2 * nn, 2 * nn, skip));
-  ZBatch z;
-  z.count = w.count;
-  z.sA = z.sB = 2 * nn;
-  z.sC = nn;
-  K_TRY(gemm_f32_nt(st, (int)w.np, (int)w.np, (int)w.np, Tt, w.np, Tt, w.np, w.W, w.np, 1, 1, z, skip, 1));
+  const int64_t zb = nn * (int64_t)sizeof(double);  // per-problem stride of X and P, bytes
+  uint8_t* Vs = reinterpret_cast<uint8_t*>(w.X);
+  uint8_t* Vts = reinterpret_cast<uint8_t*>(w.P);
+  uint8_t* tmp = Vts + nn * 6;
+  K_TRY(trtri_bf16x6(st, w.L, w.Dinv, w.np, Vs, Vts, tmp, w.count, nn, w.np * TILE, zb, zb, zb, skip));
+  K_TRY(gemm_bf16x6_lower(st, (int)w.np, (int)w.np, Vts, w.np, Vts, w.np, w.W, w.np, 1, w.count, zb, zb, nn, skip));
   return GLASSO_OK;
 }
 

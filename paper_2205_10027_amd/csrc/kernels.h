@@ -31,17 +31,9 @@ int get_gemm_f64_small_tile_below();
 
 // C = A B^T on FP32 MFMA with FP32 accumulation (A: M x K, B: N x K, row-major
 // FP32); C is float or (c_is_double) double; lower_out as in gemm_f64.
-// k_from_row (with lower_out): the k loop of tile row ti starts at 128 ti, for
-// A = B with A[i][k] = 0 when k < i (W = V^T V from Vt = V^T).
 int gemm_f32_nt(hipStream_t stream, int M, int N, int K, const float* A, int64_t lda,
                 const float* B, int64_t ldb, void* C, int64_t ldc, int c_is_double,
-                int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr,
-                int k_from_row = 0);
-// V = inv(L) in FP32 into T and V^T into Tt (np x np each), from the factor L
-// (lower, FP64) and its diagonal-block inverses Dinv; L is not modified.  tmp:
-// scratch of np^2 / 2 floats.  Problem strides in elements of each buffer.
-int trtri_f32(hipStream_t stream, const double* L, const double* Dinv, int64_t np, float* T, float* Tt, float* tmp,
-              int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTmp, const int* skip);
+                int lower_out, const ZBatch& zb = ZBatch(), const int* skip = nullptr);
 int f64_to_f32(hipStream_t stream, const double* src, float* dst, int64_t count);
 
 // C = A B^T as three BF16 products with FP32 accumulation; A (M x K) and B (N x K)
@@ -53,6 +45,19 @@ int gemm_bf16x3_nt(hipStream_t stream, int M, int N, int K, const void* A, int64
                    const ZBatch& zb = ZBatch(), const int* skip = nullptr);
 // FP64 -> split layout (count a multiple of 8)
 int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count);
+
+// V = inv(L) and V^T as three-part bf16 splits (6 bytes per element) by recursive
+// doubling from the factor L (FP64, lower, intact) and its diagonal-block inverses
+// Dinv; tmp needs np^2/4 split elements.  Strides: sL, sD elements; sT, sTt, sTmp
+// bytes per problem.
+int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_t np, void* T, void* Tt, void* tmp,
+                 int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTt, int64_t sTmp, const int* skip);
+// C = tril(A B^T) in FP64 from three-part splits (six BF16 products, FP32 accuracy);
+// N x N output, K inner; k_from_row starts tile row m0's K range at m0.  Strides of
+// the batch: bytes for A and B, elements for C.
+int gemm_bf16x6_lower(hipStream_t stream, int N, int K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                      double* C, int64_t ldc, int k_from_row, int count, int64_t zA_bytes, int64_t zB_bytes,
+                      int64_t zC, const int* skip);
 
 // Strides (elements) between the problems of a batched factorisation: the
 // matrix, its diagonal vector and its diagonal-block inverses.

@@ -121,26 +121,60 @@ __device__ void lds_trtri(double (*a)[NB + 1], int tid) {
 // failing pivot (non-positive or NaN) or -1; the value is identical in every
 // thread, and on failure the block is left partially factored.
 //
-// Panels of PF = 16 columns.  For a panel starting at c0, every wave holds the
-// 16x16 diagonal block in lanes 0..15 (row c0+lane, one register per column) and
-// factors it redundantly: column j of the block rows is broadcast with readlane,
-// its first entry being the pivot.  Lanes 16..63 of the waves hold the rows below
-// the block (48 per wave) and are eliminated in the same steps (the triangular
-// solve of the panel).  All 4 waves then apply the rank-16 update to the trailing
-// lower triangle, two 16x16 blocks at a time per wave.  The broadcasts grow with
-// the square of the panel width, the update rounds only linearly with the number
-// of panels, which is why the panels are narrow.  Elements above the diagonal are
-// never read as data.
+// Panels of PF = 16 columns (one column of 16x16 blocks).  The lower triangle's
+// 16x16 blocks live in the waves' MFMA accumulators between panels: block k of
+// the list "column NB/16 - 1 first, then leftwards, rows top-down inside a
+// column" belongs to wave k % 4, slot k / 4, so the blocks still to be updated
+// after any panel are a prefix of the list and spread evenly over the waves.
+// For panel p:
+//   1. the owners write block column p to LDS;
+//   2. every wave factors the panel redundantly: the 16x16 diagonal block in lanes
+//      0..15 (row c0+lane, one register per column), column j of its rows broadcast
+//      with readlane (its first entry is the pivot); lanes 16..63 hold the rows
+//      below (48 per wave) and are eliminated in the same steps.  The factored panel
+//      goes to LDS;
+//   3. each wave subtracts the panel's rank-16 product from its own blocks right of
+//      the panel, four independent MFMAs per block, operands from LDS.
+// The broadcasts grow with the square of the panel width, the update rounds only
+// linearly with the number of panels, which is why the panels are narrow.
+// Elements above the diagonal are never read as data.
 constexpr int PF = 16;
 
 template <int NB>
 __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
+  constexpr int NBB = NB / 16;               // 16x16 blocks per edge
+  constexpr int NBLK = NBB * (NBB + 1) / 2;  // blocks of the lower triangle
+  constexpr int SLOTS = (NBLK + 3) / 4;      // blocks per wave
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  int bi[SLOTS], bj[SLOTS];
+  v4d acc[SLOTS];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    const int k = 4 * s + wave;
+    int c = NBB - 1, start = 0;
+    while (c >= 0 && k >= start + (NBB - c)) {
+      start += NBB - c;
+      --c;
+    }
+    bj[s] = (k < NBLK) ? c : -1;
+    bi[s] = (k < NBLK) ? c + (k - start) : 0;
+    // element (4r + lane/16, lane%16) of a block is register r (FP64 MFMA output layout)
+    if (bj[s] >= 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[s][r] = a[16 * bi[s] + 4 * r + lk][16 * bj[s] + li];
+    }
+  }
   int fail = -1;
 #pragma unroll 1
-  for (int p = 0; p < NB / PF; ++p) {
+  for (int p = 0; p < NBB; ++p) {
     const int c0 = PF * p;
+    if (p > 0) {
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s)
+        if (bj[s] == p) for_block(acc[s], lane, [&](int r, int c, double v) { a[16 * bi[s] + r][c0 + c] = v; });
+    }
+    __syncthreads();
     const int row = (lane < PF) ? c0 + lane : c0 + PF + wave * (64 - PF) + (lane - PF);
     const bool valid = row < NB;
     double v[PF];
@@ -169,39 +203,17 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
       for (int q = 0; q < PF; ++q) a[row][c0 + q] = v[q];
     }
     __syncthreads();
-    // rank-16 update of the trailing lower triangle: 16x16 blocks (bi >= bj) in
-    // row-major order of the triangle, wave w taking blocks w, w + 4 together,
-    // then w + 8, w + 12, ...
-    const int base = c0 + PF, R = NB - base;
-    if (R > 0) {
-      const int nb16 = R / 16;
-      const int nblk = nb16 * (nb16 + 1) / 2;
-      for (int job = wave; job < nblk; job += 8) {
-        const int job2 = job + 4;
-        const bool two = job2 < nblk;
-        int bi = 0;
-        while ((bi + 1) * (bi + 2) / 2 <= job) ++bi;
-        const int bj = job - bi * (bi + 1) / 2;
-        int bi2 = bi, bj2 = bj;
-        if (two) {
-          while ((bi2 + 1) * (bi2 + 2) / 2 <= job2) ++bi2;
-          bj2 = job2 - bi2 * (bi2 + 1) / 2;
-        }
-        v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+    // blocks right of the panel: acc -= L[bi rows][panel] L[bj rows][panel]^T
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+      if (bj[s] > p) {
 #pragma unroll
         for (int k = 0; k < PF; k += 4) {
-          const double x1 = a[base + 16 * bi + li][c0 + k + lk];
-          const double y1 = a[base + 16 * bj + li][c0 + k + lk];
-          const double x2 = a[base + 16 * bi2 + li][c0 + k + lk];
-          const double y2 = a[base + 16 * bj2 + li][c0 + k + lk];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc, 0, 0, 0);
-          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, y2, acc2, 0, 0, 0);
+          const double x = a[16 * bi[s] + li][c0 + k + lk];
+          const double y = a[16 * bj[s] + li][c0 + k + lk];
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x, y, acc[s], 0, 0, 0);
         }
-        for_block(acc, lane, [&](int r, int c, double v) { a[base + 16 * bi + r][base + 16 * bj + c] -= v; });
-        if (two)
-          for_block(acc2, lane, [&](int r, int c, double v) { a[base + 16 * bi2 + r][base + 16 * bj2 + c] -= v; });
       }
-      __syncthreads();
     }
   }
   return fail;

@@ -1,12 +1,16 @@
-"""The mixed-W ladder (glasso_options.w_mixed): W = V^T V in FP32 while a problem
-iterates, FP64 W and measures before it stops.
+"""The mixed-W ladder (glasso_options.w_mixed): W = V^T V with FP32 accuracy while a
+problem iterates, FP64 W and measures before it stops.
 
-* the FP32 inverse itself: V = inv(L) by FP32 recursive doubling carries the
-  triangular-inverse bound |dV| <= c u32 |V||L||V|, where the levels' products
-  (inner dimensions s = 128, 256, ... summing to about 2n) and the rounding of L and
-  of the diagonal-block inverses to FP32 give c = 2n + 2; W32 = V^T V then differs
-  from inv(A) by at most 2 |V|^T |dV| + (n + 4) u32 |V|^T |V| (the FP32 product over
-  n terms), checked elementwise with factor 2 slack (V and L computed on the CPU);
+* the FP32-accurate inverse itself: every product is formed from exact three-part
+  bf16 splits of FP32 values, six partial products per pair, each exact in FP32,
+  accumulated in FP32 (at most 6 roundings per inner index), with three dropped
+  partial products below 2.1 u32 |x y|.  V = inv(L) by recursive doubling then
+  carries the triangular-inverse bound |dV| <= c u32 |V||L||V|: the levels' products
+  (inner dimensions s = 128, 256, ... summing to about 2n, six roundings each, plus
+  3 per level) and the rounding of L and of the diagonal-block inverses to FP32 give
+  c = 12n + 32.  W32 = V^T V differs from inv(A) by at most
+  2 |V|^T |dV| + (6n + 3) u32 |V|^T |V|, checked elementwise with factor 2 slack
+  (V and L computed on the CPU);
 * solves in both mixed forms meet the FP64 bar against the oracle, and their
   reported KKT measure is the FP64 one (recomputed on the CPU from the returned A);
 * the returned W is the FP64 inverse on every exit: converged, MAX_ITER and
@@ -39,8 +43,8 @@ def test_fp32_w_product(g, n):
     V = np.linalg.inv(L)
     ref = np.linalg.inv(A)
     aV = np.abs(V)
-    dV = (2 * n + 2) * U32 * (aV @ np.abs(L) @ aV)
-    bound = 2 * (2 * aV.T @ dV + (n + 4) * U32 * (aV.T @ aV)) + 1e-300
+    dV = (12 * n + 32) * U32 * (aV @ np.abs(L) @ aV)
+    bound = 2 * (2 * aV.T @ dV + (6 * n + 3) * U32 * (aV.T @ aV)) + 1e-300
     assert np.all(np.abs(W32 - ref) <= bound), np.max(np.abs(W32 - ref) / bound)
     assert np.max(np.abs(W32 - ref)) > 0  # really the FP32 product
     W64 = to_host(g.Solver(w_mixed=0).inverse(to_dev(A)))
