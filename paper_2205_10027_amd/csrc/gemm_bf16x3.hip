@@ -18,6 +18,7 @@
 // output tile per workgroup, 4 wave64 of 64x64, 32 k per stage in double-buffered
 // LDS (72 KB, two workgroups per CU).  C is written in split layout (the next
 // product's operand) or as the FP64 lower triangle.
+#include "bf16.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -40,14 +41,6 @@ struct GemmBf16Params {
   int64_t zA, zB, zC;     // per-problem strides, elements
   const int* skip;        // per-problem skip flags (may be null)
 };
-
-// float -> bf16 bits, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
 
 // one 128-row x 32-k stage of a split operand: thread t copies 64 bytes of row t/2
 __device__ __forceinline__ void load_stage(const uint8_t* P, int64_t ld, int r0, int kt, int tid, v4u (&r)[4]) {
@@ -158,9 +151,9 @@ __global__ void split_bf16x2_kernel(const double* __restrict__ src, uint8_t* __r
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double2 v = s[q];
-      const uint32_t h0 = bf16_bits((float)v.x), h1 = bf16_bits((float)v.y);
-      const uint32_t l0 = bf16_bits((float)(v.x - (double)bf16_value(h0)));
-      const uint32_t l1 = bf16_bits((float)(v.y - (double)bf16_value(h1)));
+      uint32_t h0, l0, h1, l1;
+      split2(v.x, h0, l0);
+      split2(v.y, h1, l1);
       hi[q] = h0 | (h1 << 16);
       lo[q] = l0 | (l1 << 16);
     }

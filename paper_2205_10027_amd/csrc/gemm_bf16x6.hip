@@ -22,6 +22,7 @@
 // registers.  k_from_row starts each tile's K range at its first row (A[m][k] = 0
 // for k < m, as for A = V^T with V lower triangular); tiles then run in launch
 // order, longest K range first.
+#include "bf16.h"
 #include "common.h"
 #include "kernels.h"
 
@@ -46,14 +47,6 @@ struct GemmBf6Params {
   int64_t zA, zB, zC;     // per-problem strides: bytes for A and B, elements for C
   const int* skip;
 };
-
-// float -> bf16 bits, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ uint32_t bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
 
 // thread t stages 96 bytes (two runs) of row t/2 of a 128-row operand slice
 __device__ __forceinline__ void load6(const uint8_t* P, int64_t ld, int r0, int kt, int tid, v4u (&r)[6]) {
@@ -159,10 +152,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_nt_kernel(GemmBf6Params p)
 
 // ---- the three-part split of single FP32 values, and stores of them
 __device__ __forceinline__ void split3(float x, uint32_t& h1, uint32_t& h2, uint32_t& h3) {
-  h1 = bf16_rne(x);
-  const float r1 = x - bf16_float(h1);  // exact
-  h2 = bf16_rne(r1);
-  h3 = bf16_rne(r1 - bf16_float(h2));  // exact
+  h1 = bf16_bits(x);
+  const float r1 = x - bf16_value(h1);  // exact
+  h2 = bf16_bits(r1);
+  h3 = bf16_bits(r1 - bf16_value(h2));  // exact
 }
 // element (row, col) of a split matrix with ld elements per row
 __device__ __forceinline__ void store_split(uint8_t* M, int64_t ld, int64_t row, int col, float x) {
@@ -257,8 +250,28 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p)
     }
 }
 
+// a run of 8 consecutive elements (row, col0 .. col0 + 7), col0 a multiple of 8:
+// three 16-byte stores
+__device__ __forceinline__ void store_run(uint8_t* M, int64_t ld, int64_t row, int64_t col0, const float (&x)[8]) {
+  uint32_t p1[4], p2[4], p3[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t a1, a2, a3, b1, b2, b3;
+    split3(x[2 * q], a1, a2, a3);
+    split3(x[2 * q + 1], b1, b2, b3);
+    p1[q] = a1 | (b1 << 16);
+    p2[q] = a2 | (b2 << 16);
+    p3[q] = a3 | (b3 << 16);
+  }
+  v4u* d = reinterpret_cast<v4u*>(M + (row * ld + col0) * 6);
+  d[0] = (v4u){p1[0], p1[1], p1[2], p1[3]};
+  d[1] = (v4u){p2[0], p2[1], p2[2], p2[3]};
+  d[2] = (v4u){p3[0], p3[1], p3[2], p3[3]};
+}
+
 // T and Tt (split) from the factor L (lower, FP64) and its diagonal-block inverses
-// Dinv (np x 128, ld 128): 64x64 tiles through LDS so both are written along rows.
+// Dinv (np x 128, ld 128): a 64x64 tile of T goes through LDS, then every thread
+// writes whole runs of T's rows and of Tt's rows.
 __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __restrict__ L,
                                                              const double* __restrict__ Dinv, int64_t np,
                                                              uint8_t* __restrict__ T, uint8_t* __restrict__ Tt,
@@ -271,26 +284,29 @@ __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __re
   Tt += blockIdx.z * sTt;
   __shared__ float t[64][65];
   const int bi = blockIdx.x, bj = blockIdx.y;  // tile rows i, columns j of T
-  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int tid = threadIdx.x, c = tid & 63, r0 = tid >> 6;
   const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
-  if (bj > bi) {  // above the diagonal: zeros in T, and in Tt below it
-    for (int r = r0; r < 64; r += 4) {
-      store_split(T, np, i0 + r, (int)(j0 + c), 0.f);
-      store_split(Tt, np, j0 + r, (int)(i0 + c), 0.f);
-    }
-    return;
-  }
   const bool same_block = (bi >> 1) == (bj >> 1);  // inside one 128x128 diagonal block
   for (int r = r0; r < 64; r += 4) {
     const int64_t i = i0 + r, j = j0 + c;
     float v = 0.f;
-    if (j <= i)
+    if (bj <= bi && j <= i)
       v = same_block ? (float)Dinv[(i >> 7) * 128 * 128 + (i & 127) * 128 + (j & 127)] : (float)L[i * np + j];
-    store_split(T, np, i, (int)j, v);
     t[r][c] = v;
   }
   __syncthreads();
-  for (int r = r0; r < 64; r += 4) store_split(Tt, np, j0 + r, (int)(i0 + c), t[c][r]);
+  // 64 rows x 8 runs of T's tile and of Tt's tile (its transpose), two of each per thread
+  for (int g = tid; g < 512; g += 256) {
+    const int r = g >> 3, q = g & 7;
+    float x[8], y[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      x[e] = t[r][8 * q + e];
+      y[e] = t[8 * q + e][r];
+    }
+    store_run(T, np, i0 + r, j0 + 8 * q, x);
+    store_run(Tt, np, j0 + r, i0 + 8 * q, y);
+  }
 }
 
 }  // namespace

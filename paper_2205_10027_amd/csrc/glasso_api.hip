@@ -333,7 +333,7 @@ glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
 // P = tril(X32 A32^T) is written in FP64.
 // gev (optional): two events recorded around the two GEMM launches only
 glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip,
-                           hipEvent_t* gev = nullptr) {
+                           hipEvent_t* gev = nullptr, bool z_split_ready = false) {
   const int np = (int)w.np;
   const int64_t nn = w.nn();
   ZBatch z;
@@ -372,12 +372,13 @@ glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const in
   }
   if (precision == GLASSO_MIXED_BF16X3) {
     // split A and Z (4 bytes per element) share the X buffer: A of problem b at
-    // b * 2nn elements, Z after it; the split X = A Z is written over Z
+    // b * 2nn elements, Z after it (written there by the gradient pass when
+    // z_split_ready); the split X = A Z is written over Z
     uint8_t* As = reinterpret_cast<uint8_t*>(w.X);
     uint8_t* Xs = reinterpret_cast<uint8_t*>(w.Z);
     for (int b = 0; b < w.count; ++b) {
       K_TRY(split_bf16x2(st, w.A + b * nn, As + 2 * b * nn * 4, nn));
-      K_TRY(split_bf16x2(st, w.Z + b * nn, As + (2 * b + 1) * nn * 4, nn));
+      if (!z_split_ready) K_TRY(split_bf16x2(st, w.Z + b * nn, As + (2 * b + 1) * nn * 4, nn));
     }
     ZBatch z1;  // Xs = A Z^T (Z symmetric)
     z1.count = w.count;
@@ -575,6 +576,11 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   PassBatch pr = pb;  // FP64 re-check of the problems in skip64 == 0
   pr.skip = w.skip64;
   const FactorBatch fbw = factor_batch(w);
+  // BF16x3 form: the gradient pass writes Z only as the split the product reads
+  // (into the second half of each problem's X region, free once W is formed)
+  double* const z_f64 = (o.precision == GLASSO_MIXED_BF16X3) ? nullptr : w.Z;
+  void* const z_split = (o.precision == GLASSO_MIXED_BF16X3) ? (void*)(reinterpret_cast<uint8_t*>(w.X) + 4 * nn)
+                                                             : nullptr;
   auto head = [&](hipStream_t s, bool timed) -> glasso_err {  // a1, a2
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
@@ -592,7 +598,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (e2) return e2;
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
-    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     return fetch_async(h, s);
   };
@@ -601,13 +607,13 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (e2) return e2;
     K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
-    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pr));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pr, z_split, 8 * nn));
     return fetch_async(h, s);
   };
   auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
-    return precond_product(w, s, o.precision, w.skip, timed ? h->ev + 5 : nullptr);
+    return precond_product(w, s, o.precision, w.skip, timed ? h->ev + 5 : nullptr, z_split != nullptr);
   };
   auto trial = [&](hipStream_t s, bool) -> glasso_err {  // a4, a5
     glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, count);

@@ -109,9 +109,12 @@ struct PassBatch {
   const int* skip = nullptr;
 };
 
+// Z (FP64, may be null) and/or Zs, its two-part bf16 split (4 bytes per element,
+// per-problem byte stride sZs; may be null).
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A,
               const double* dL, int64_t n, int64_t nlog, int64_t np, double lam, double* Z,
-              int8_t* GM, double* part, double* scal, const PassBatch& pb = PassBatch());
+              int8_t* GM, double* part, double* scal, const PassBatch& pb = PassBatch(),
+              void* Zs = nullptr, int64_t sZs = 0);
 // info_reset[b] is set to 0 for the problems the pass handles and to -1 for the
 // skipped ones, so that the Cholesky that follows skips them too.
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S,

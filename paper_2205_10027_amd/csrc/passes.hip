@@ -20,6 +20,7 @@
 
 #include <float.h>
 
+#include "bf16.h"
 #include "common.h"
 #include "elementwise.h"
 #include "kernels.h"
@@ -34,6 +35,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
                                                         const double* __restrict__ A,
                                                         const double* __restrict__ dL, int64_t n,
                                                         int64_t np, double lam, double* __restrict__ Z,
+                                                        uint8_t* __restrict__ Zs, int64_t sZs,
                                                         int8_t* __restrict__ GM, double* part, int T, PassBatch pb) {
   __shared__ double zt[64][65];
   __shared__ int8_t gt[64][68];
@@ -44,7 +46,8 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
   S += pbi * pb.sS;
   W += pbi * pb.sM;
   A += pbi * pb.sM;
-  Z += pbi * pb.sM;
+  if (Z) Z += pbi * pb.sM;
+  if (Zs) Zs += pbi * sZs;
   GM += pbi * pb.sM;
   part += (int64_t)pbi * gridDim.x * GRAD_PARTS;
   int ti, tj;
@@ -74,7 +77,8 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
         s_nnz += nz ? wgt : 0.0;
         s_sa += wgt * (s * a);
       }
-      Z[off] = z;
+      if (Z) Z[off] = z;
+      if (Zs) store_split2(Zs, np, i, j, z);
       GM[off] = gm;
     }
     zt[r][c] = z;
@@ -85,10 +89,12 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
   for (int q = 0; q < 16; ++q) {
     const int r = rw + 4 * q;
     if (!diag) {
-      Z[(j0 + r) * np + i0 + c] = zt[c][r];
+      if (Z) Z[(j0 + r) * np + i0 + c] = zt[c][r];
+      if (Zs) store_split2(Zs, np, j0 + r, i0 + c, zt[c][r]);
       GM[(j0 + r) * np + i0 + c] = gt[c][r];
     } else if (c > r) {
-      Z[(i0 + r) * np + j0 + c] = zt[c][r];
+      if (Z) Z[(i0 + r) * np + j0 + c] = zt[c][r];
+      if (Zs) store_split2(Zs, np, i0 + r, j0 + c, zt[c][r]);
       GM[(i0 + r) * np + j0 + c] = gt[c][r];
     }
   }
@@ -529,11 +535,11 @@ int sum_log(hipStream_t stream, const double* d, int64_t n, double* out) {
 
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A, const double* dL, int64_t n,
               int64_t nlog, int64_t np, double lam, double* Z, int8_t* GM, double* part, double* scal,
-              const PassBatch& pb) {
+              const PassBatch& pb, void* Zs, int64_t sZs) {
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
-  hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z, GM,
-                     part, T, pb);
+  hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z,
+                     static_cast<uint8_t*>(Zs), sZs, GM, part, T, pb);
   hipLaunchKernelGGL(finish_grad_kernel, dim3(pb.count), dim3(256), 0, stream, part, tiles, dL, nlog, lam, scal, pb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
