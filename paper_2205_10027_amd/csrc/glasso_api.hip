@@ -299,12 +299,8 @@ glasso_err factor_all(glasso_handle h, hipStream_t st) {
   return fetch(h, st);
 }
 
-// W (lower) = A^{-1} from the factor in w.L for every problem with skip == 0:
-// L <- inv(L) in place, W = inv(L)^T inv(L).  tmp: the X buffer.
-// W (lower) = A^{-1} in FP32 MFMA for every problem with skip == 0, from its
-// factor in w.L (left unchanged) and diagonal-block inverses: V = inv(L) and V^T
-// by FP32 doubling (T, Tt in the X buffer, scratch in the P buffer), then the
-// lower triangle of Vt Vt^T written FP64 with the k loop clipped to k >= row.
+// W (lower) = A^{-1} with FP32 accuracy for every problem with skip == 0, from its
+// factor in w.L (left unchanged) and diagonal-block inverses.
 glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
   // W = A^-1 with FP32 accuracy on the BF16 matrix cores: V = inv(L) by recursive
   // doubling and W = V^T V, every operand an exact three-part bf16 split of an FP32
@@ -320,6 +316,8 @@ glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
   return GLASSO_OK;
 }
 
+// W (lower) = A^{-1} in FP64 from the factor in w.L for every problem with skip ==
+// 0: L <- inv(L) in place, W = inv(L)^T inv(L).  tmp: the X buffer.
 glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
   const FactorBatch fb = factor_batch(w);
   K_TRY(trtri_lower(st, w.L, w.np, (int)w.np, w.Dinv, w.X, skip, fb, w.nn()));
@@ -538,17 +536,26 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   e = push_doubles(st, w.lam, hm.lam, count);
   if (e) return e;
 
-  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 5); its factor
+  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 5); its factor.  The
+  // diagonal start comes with its factor and W = A^-1 in closed form.
+  const bool diag_start = !o.warm_start;
   for (int b = 0; b < count; ++b) {
     if (o.warm_start)
       K_TRY(pad_copy_f64(st, Aout[b], n, np, w.A + b * nn, w.L + b * nn, 1));
     else
-      K_TRY(init_diag(st, w.S + b * sS, n, np, lam[b], w.A + b * nn, w.L + b * nn));
+      K_TRY(init_diag(st, w.S + b * sS, n, np, lam[b], w.A + b * nn, w.L + b * nn, w.dL + b * np,
+                      w.Dinv + b * np * TILE, w.W + b * nn));
   }
-  e = factor_all(h, st);
-  if (e) return e;
-  for (int b = 0; b < count; ++b)
-    if (hm.info[b]) return o.warm_start ? GLASSO_ERR_NOT_PD : GLASSO_ERR_INVALID_ARG;
+  if (diag_start) {
+    for (int b = 0; b < count; ++b) hm.info[b] = 0;
+    e = push_ints(st, w.info, hm.info, count);
+    if (e) return e;
+  } else {
+    e = factor_all(h, st);
+    if (e) return e;
+    for (int b = 0; b < count; ++b)
+      if (hm.info[b]) return GLASSO_ERR_NOT_PD;
+  }
 
   std::vector<int> active(count, 1), status(count, GLASSO_MAX_ITER), it(count, 0), trials(count, 0),
       fallbacks(count, 0), ls(count, 0), fb_used(count, 0);
@@ -598,6 +605,17 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (e2) return e2;
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
+    return fetch_async(h, s);
+  };
+  auto head_given_w = [&](hipStream_t s, bool timed) -> glasso_err {  // a2 with W already formed
+    glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
+    if (e2) return e2;
+    if (timed) {
+      HIP_TRY(hipEventRecord(h->ev[0], s));
+      HIP_TRY(hipEventRecord(h->ev[1], s));
+    }
     K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     return fetch_async(h, s);
@@ -689,20 +707,29 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     return GLASSO_OK;
   };
 
+  // the first W of a diagonal start is exact (formed with A^(0))
+  bool w_given = diag_start;
   for (;;) {
     for (int b = 0; b < count; ++b) {
       hm.skip[b] = !active[b];
       hm.skip32[b] = !(active[b] && !wexact[b]);
       hm.skip64[b] = !(active[b] && wexact[b]);
-      if (active[b]) wlast[b] = wexact[b];
+      if (active[b]) wlast[b] = w_given ? 1 : wexact[b];
     }
-    if (graphs) HIP_TRY(hipEventRecord(h->ev[0], st));
-    e = run(&h->graphs.head, head);
+    const bool exact_w = w_given;
+    if (w_given) {
+      e = head_given_w(st, true);
+      w_given = false;
+    } else {
+      if (graphs) HIP_TRY(hipEventRecord(h->ev[0], st));
+      e = run(&h->graphs.head, head);
+      if (e) return e;
+      if (graphs) {
+        HIP_TRY(hipEventRecord(h->ev[1], st));
+        HIP_TRY(hipEventRecord(h->ev[2], st));
+      }
+    }
     if (e) return e;
-    if (graphs) {
-      HIP_TRY(hipEventRecord(h->ev[1], st));
-      HIP_TRY(hipEventRecord(h->ev[2], st));
-    }
     HIP_TRY(hipStreamSynchronize(st));
     phase[1] += elapsed(h->ev[0], h->ev[1]);
     phase[2] += elapsed(h->ev[1], h->ev[2]);
@@ -710,7 +737,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     std::vector<int> mark(count, 0);
     int nmark = 0;
     for (int b = 0; b < count; ++b)
-      if (active[b] && !wexact[b] && (hscal(h, b, SC_KKT_REL1) <= tol || it[b] >= o.max_iter)) {
+      if (active[b] && !wexact[b] && !exact_w && (hscal(h, b, SC_KKT_REL1) <= tol || it[b] >= o.max_iter)) {
         mark[b] = 1;
         wexact[b] = 1;
         ++nmark;

@@ -89,8 +89,10 @@ int lauum_lower(hipStream_t stream, const double* V, int64_t ldv, double* W, int
 // ---------------------------------------------------------------- elementwise passes
 int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst, int64_t np,
                    int64_t* bad_count_dev, double lam, int check);
+// A^(0) = diag(1/(S_ii + lam)) (identity padding) with its factor L, diag(L) in dL,
+// the diagonal-block inverses of L in Dinv and W = A^-1, all in closed form.
 int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A,
-              double* L);
+              double* L, double* dL, double* Dinv, double* W);
 int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst,
                  double* dst2, int pad_diag);
 int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, int8_t* dst);

@@ -301,16 +301,29 @@ __global__ void copy_in_kernel(const double* __restrict__ src, int64_t n, double
   if (check && nbad) atomicAdd(bad, nbad);
 }
 
+// A^(0) = diag(1/(S_ii + lam)) with identity padding and, because it is diagonal,
+// its factor and inverse in closed form: L = diag(sqrt(A_ii)) (diag(L) also in dL),
+// the 128x128 diagonal-block inverses of L in Dinv (np x 128), W = diag(1/A_ii).
+__device__ __forceinline__ double initial_diag(const double* Sp, int64_t n, int64_t np, double lam, int64_t i) {
+  return (i < n) ? 1.0 / (Sp[i * np + i] + lam) : 1.0;
+}
 __global__ void init_diag_kernel(const double* __restrict__ Sp, int64_t n, int64_t np, double lam,
-                                 double* __restrict__ A, double* __restrict__ L) {
+                                 double* __restrict__ A, double* __restrict__ L, double* __restrict__ dL,
+                                 double* __restrict__ Dinv, double* __restrict__ W) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = np * np;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t e = first; e < total; e += stride) {
     const int64_t i = e / np, j = e - i * np;
-    double v = 0.0;
-    if (i == j) v = (i < n) ? 1.0 / (Sp[i * np + i] + lam) : 1.0;
-    A[e] = v;
-    L[e] = v;
+    const double a = (i == j) ? initial_diag(Sp, n, np, lam, i) : 0.0;
+    A[e] = a;
+    L[e] = (i == j) ? sqrt(a) : 0.0;
+    W[e] = (i == j) ? 1.0 / a : 0.0;
   }
+  for (int64_t e = first; e < np * 128; e += stride) {
+    const int64_t i = e >> 7;
+    Dinv[e] = ((e & 127) == (i & 127)) ? 1.0 / sqrt(initial_diag(Sp, n, np, lam, i)) : 0.0;
+  }
+  for (int64_t i = first; i < np; i += stride) dL[i] = sqrt(initial_diag(Sp, n, np, lam, i));
 }
 
 // dst (np x np) <- src (n x n, ld n); outside the n x n block: identity when
@@ -495,10 +508,11 @@ int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A, double* L) {
+int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A, double* L,
+              double* dL, double* Dinv, double* W) {
   const int64_t total = np * np;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 16384);
-  hipLaunchKernelGGL(init_diag_kernel, dim3(blocks), dim3(256), 0, stream, Sp, n, np, lam, A, L);
+  hipLaunchKernelGGL(init_diag_kernel, dim3(blocks), dim3(256), 0, stream, Sp, n, np, lam, A, L, dL, Dinv, W);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
