@@ -73,6 +73,7 @@ class Result:
     ls_trials: int
     fallback_steps: int
     time_ms: tuple
+    aza_gemm_products: int = 0
 
     @property
     def status_name(self) -> str:
@@ -142,7 +143,7 @@ class Solver:
                                  ctypes.byref(info), _stream(stream)), "glasso_solve")
         return Result(A, W, info.objective, info.iterations, info.status, info.kkt_rel1,
                       info.kkt_fro, info.kkt_max, int(info.nnz), info.ls_trials,
-                      info.fallback_steps, tuple(info.time_ms))
+                      info.fallback_steps, tuple(info.time_ms), info.aza_gemm_products)
 
     def solve_batched(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
         """Solve len(lams) problems in batched launches (glasso_solve_batched).
@@ -189,7 +190,7 @@ class Solver:
             inf = infos[i]
             out.append(Result(A_list[i], W_list[i] if want_W else None, inf.objective, inf.iterations,
                               inf.status, inf.kkt_rel1, inf.kkt_fro, inf.kkt_max, int(inf.nnz),
-                              inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms)))
+                              inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms), inf.aza_gemm_products))
         return out
 
     # ---------------------------------------------------------------- single steps

@@ -37,6 +37,7 @@ class GlassoInfo(ctypes.Structure):
         ("status", ctypes.c_int),
         ("fallback_steps", ctypes.c_int),
         ("time_ms", ctypes.c_double * 8),
+        ("aza_gemm_products", ctypes.c_int),
     ]
 
 

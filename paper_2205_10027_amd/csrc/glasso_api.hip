@@ -558,7 +558,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   }
 
   std::vector<int> active(count, 1), status(count, GLASSO_MAX_ITER), it(count, 0), trials(count, 0),
-      fallbacks(count, 0), ls(count, 0), fb_used(count, 0);
+      fallbacks(count, 0), ls(count, 0), fb_used(count, 0), gemm_products(count, 0);
   PassBatch pb;
   pb.count = count;
   pb.sS = sS;
@@ -616,7 +616,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       HIP_TRY(hipEventRecord(h->ev[0], s));
       HIP_TRY(hipEventRecord(h->ev[1], s));
     }
-    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, w.Z, w.GM, w.part, w.scal, pb));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     return fetch_async(h, s);
   };
@@ -761,12 +761,21 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     }
     if (!nact) break;
     for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
-    // a3: P = A Z A
+    // a3: P = A Z A; with A still the diagonal A^(0) it is D Z D, formed elementwise
     HIP_TRY(hipEventRecord(h->ev[2], st));
-    if (graphs) HIP_TRY(hipEventRecord(h->ev[5], st));
-    e = run(&h->graphs.prod, prod);
-    if (e) return e;
-    if (graphs) HIP_TRY(hipEventRecord(h->ev[6], st));
+    if (exact_w) {
+      HIP_TRY(hipEventRecord(h->ev[5], st));
+      e = push_ints(st, w.skip, hm.skip, count);
+      if (e) return e;
+      K_TRY(diag_product(st, w.A, w.Z, w.P, np, count, w.skip));
+      HIP_TRY(hipEventRecord(h->ev[6], st));
+    } else {
+      if (graphs) HIP_TRY(hipEventRecord(h->ev[5], st));
+      e = run(&h->graphs.prod, prod);
+      if (e) return e;
+      if (graphs) HIP_TRY(hipEventRecord(h->ev[6], st));
+      for (int b = 0; b < count; ++b) gemm_products[b] += active[b];
+    }
     HIP_TRY(hipEventRecord(h->ev[3], st));
     // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
     for (int b = 0; b < count; ++b) {
@@ -863,6 +872,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       in.ls_trials = trials[b];
       in.status = status[b];
       in.fallback_steps = fallbacks[b];
+      in.aza_gemm_products = gemm_products[b];
       for (int i = 1; i < 8; ++i) in.time_ms[i] = phase[i];
       in.time_ms[0] = total;
     }

@@ -93,6 +93,9 @@ int copy_in_padded(hipStream_t stream, const double* src, int64_t n, double* dst
 // the diagonal-block inverses of L in Dinv and W = A^-1, all in closed form.
 int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, double lam, double* A,
               double* L, double* dL, double* Dinv, double* W);
+// P = A Z A for diagonal A (elementwise, FP64), problems with skip == 0.
+int diag_product(hipStream_t stream, const double* A, const double* Z, double* P, int64_t np, int count,
+                 const int* skip);
 int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst,
                  double* dst2, int pad_diag);
 int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, int8_t* dst);

@@ -326,6 +326,22 @@ __global__ void init_diag_kernel(const double* __restrict__ Sp, int64_t n, int64
   for (int64_t i = first; i < np; i += stride) dL[i] = sqrt(initial_diag(Sp, n, np, lam, i));
 }
 
+// P = A Z A for a diagonal A: P_ij = (A_ii Z_ij) A_jj, rounded as the FP64 GEMM
+// pair rounds it (X = A Z, then X A), for the problems with skip == 0.
+__global__ void diag_product_kernel(const double* __restrict__ A, const double* __restrict__ Z,
+                                    double* __restrict__ P, int64_t np, int64_t sM, const int* skip) {
+  if (skip && skip[blockIdx.y]) return;
+  A += blockIdx.y * sM;
+  Z += blockIdx.y * sM;
+  P += blockIdx.y * sM;
+  const int64_t total = np * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    const double x = A[i * (np + 1)] * Z[e];
+    P[e] = x * A[j * (np + 1)];
+  }
+}
+
 // dst (np x np) <- src (n x n, ld n); outside the n x n block: identity when
 // pad_diag, else zero.  dst2 (may be null) receives the same values.
 __global__ void pad_copy_f64_kernel(const double* __restrict__ src, int64_t n, int64_t np, double* __restrict__ dst,
@@ -517,6 +533,14 @@ int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, doubl
 }
 
 static int grid_for(int64_t total) { return (int)std::min<int64_t>((total + 255) / 256, 16384); }
+
+int diag_product(hipStream_t stream, const double* A, const double* Z, double* P, int64_t np, int count,
+                 const int* skip) {
+  if (count <= 0) return 0;
+  const int blocks = (int)std::min<int64_t>((np * np + 255) / 256, 8192);
+  hipLaunchKernelGGL(diag_product_kernel, dim3(blocks, count), dim3(256), 0, stream, A, Z, P, np, np * np, skip);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst, double* dst2,
                  int pad_diag) {

@@ -72,10 +72,10 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
          offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
-         offsetof(glasso_info, time_ms));
+         offsetof(glasso_info, time_ms), offsetof(glasso_info, aza_gemm_products));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -86,5 +86,6 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, g.GlassoOptions.tile_policy.offset,
             g.GlassoOptions.graphs.offset, g.GlassoOptions.w_mixed.offset, ctypes.sizeof(g.GlassoInfo),
-            g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset]
+            g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset,
+            g.GlassoInfo.aza_gemm_products.offset]
     assert [int(x) for x in out] == want
