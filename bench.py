@@ -137,6 +137,34 @@ def bench_path(g, torch, dev):
     out["solves_per_s"] = modes["waves_graphs"]["solves_per_s"]
     out["speedup_vs_one_by_one"] = modes["one_by_one"]["path_s"] / modes["waves_graphs"]["path_s"]
     out["best_mode"] = min(modes, key=lambda k: modes[k]["path_s"])
+    # the same path in the default mixed form (BF16x3 products, BF16x6 W, FP64
+    # Cholesky / line search / KKT): forms F1 and F2 together, against the plain
+    # FP64 one-solve-per-lambda path above, with the error of every lambda's result
+    # against the FP64 batched result
+    g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000, precision="bf16x3")  # warmup
+    mixed = {}
+    ref = {}
+    for name, mode, graphs, prec in (("waves_graphs", "waves", True, "fp64"),
+                                     ("independent", "independent", False, "bf16x3"),
+                                     ("waves_graphs", "waves", True, "bf16x3")):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000, graphs=graphs, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if any(r.status != g.CONVERGED for r in res):
+            raise RuntimeError(f"path {prec} {name}: not every lambda converged")
+        if prec == "fp64":
+            ref = {i: r for i, r in enumerate(res)}
+            continue
+        worst = max(abs(r.objective - ref[i].objective) / abs(ref[i].objective) for i, r in enumerate(res))
+        supp = sum(int(((r.A != 0) != (ref[i].A != 0)).sum()) for i, r in enumerate(res))
+        mixed[name] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res),
+                       "speedup_vs_fp64_one_by_one": modes["one_by_one"]["path_s"] / dt,
+                       "max_objective_rel_diff_vs_fp64": worst, "support_diff_vs_fp64": supp,
+                       "max_kkt_rel1": max(r.kkt_rel1 for r in res)}
+        log(f"[bench] path bf16x3 {name}: {dt:.2f}s ({len(lams) / dt:.1f} solves/s), F rel diff {worst:.1e}")
+    out["mixed_bf16x3"] = mixed
     out["small_persistent"] = bench_small(g, torch, dev)
     return out
 
