@@ -145,6 +145,7 @@ def bench_path(g, torch, dev):
     mixed = {}
     ref = {}
     for name, mode, graphs, prec in (("waves_graphs", "waves", True, "fp64"),
+                                     ("independent", "independent", False, "fp64"),
                                      ("independent", "independent", False, "bf16x3"),
                                      ("waves_graphs", "waves", True, "bf16x3")):
         torch.cuda.synchronize()
@@ -154,11 +155,17 @@ def bench_path(g, torch, dev):
         dt = time.perf_counter() - t
         if any(r.status != g.CONVERGED for r in res):
             raise RuntimeError(f"path {prec} {name}: not every lambda converged")
-        if prec == "fp64":
+        if prec == "fp64" and not ref:
             ref = {i: r for i, r in enumerate(res)}
             continue
         worst = max(abs(r.objective - ref[i].objective) / abs(ref[i].objective) for i, r in enumerate(res))
         supp = sum(int(((r.A != 0) != (ref[i].A != 0)).sum()) for i, r in enumerate(res))
+        if prec == "fp64":
+            # two FP64 modes against each other: how far apart two solutions of the
+            # same tolerance reached along different trajectories lie
+            mixed["fp64_independent_vs_fp64_waves"] = {"max_objective_rel_diff": worst, "support_diff": supp}
+            log(f"[bench] path fp64 independent vs waves: F rel diff {worst:.1e}, support diff {supp}")
+            continue
         mixed[name] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res),
                        "speedup_vs_fp64_one_by_one": modes["one_by_one"]["path_s"] / dt,
                        "max_objective_rel_diff_vs_fp64": worst, "support_diff_vs_fp64": supp,
