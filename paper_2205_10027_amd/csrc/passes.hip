@@ -327,18 +327,27 @@ __global__ void init_diag_kernel(const double* __restrict__ Sp, int64_t n, int64
 }
 
 // P = A Z A for a diagonal A: P_ij = (A_ii Z_ij) A_jj, rounded as the FP64 GEMM
-// pair rounds it (X = A Z, then X A), for the problems with skip == 0.
-__global__ void diag_product_kernel(const double* __restrict__ A, const double* __restrict__ Z,
-                                    double* __restrict__ P, int64_t np, int64_t sM, const int* skip) {
-  if (skip && skip[blockIdx.y]) return;
-  A += blockIdx.y * sM;
-  Z += blockIdx.y * sM;
-  P += blockIdx.y * sM;
-  const int64_t total = np * np;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / np, j = e - i * np;
-    const double x = A[i * (np + 1)] * Z[e];
-    P[e] = x * A[j * (np + 1)];
+// pair rounds it (X = A Z, then X A), for the problems with skip == 0.  64x64
+// tiles; the tile's 128 diagonal entries are staged in LDS first.
+__global__ __launch_bounds__(256) void diag_product_kernel(const double* __restrict__ A,
+                                                           const double* __restrict__ Z, double* __restrict__ P,
+                                                           int64_t np, int64_t sM, const int* skip) {
+  if (skip && skip[blockIdx.z]) return;
+  A += blockIdx.z * sM;
+  Z += blockIdx.z * sM;
+  P += blockIdx.z * sM;
+  __shared__ double di[64], dj[64];
+  const int tid = threadIdx.x, c = tid & 63;
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  if (tid < 64)
+    di[tid] = A[(i0 + tid) * (np + 1)];
+  else if (tid < 128)
+    dj[tid - 64] = A[(j0 + tid - 64) * (np + 1)];
+  __syncthreads();
+  for (int r = tid >> 6; r < 64; r += 4) {
+    const int64_t e = (i0 + r) * np + j0 + c;
+    const double x = di[r] * Z[e];
+    P[e] = x * dj[c];
   }
 }
 
@@ -536,9 +545,9 @@ static int grid_for(int64_t total) { return (int)std::min<int64_t>((total + 255)
 
 int diag_product(hipStream_t stream, const double* A, const double* Z, double* P, int64_t np, int count,
                  const int* skip) {
-  if (count <= 0) return 0;
-  const int blocks = (int)std::min<int64_t>((np * np + 255) / 256, 8192);
-  hipLaunchKernelGGL(diag_product_kernel, dim3(blocks, count), dim3(256), 0, stream, A, Z, P, np, np * np, skip);
+  if (count <= 0 || np % 64) return count <= 0 ? 0 : -1;
+  const int T = (int)(np / 64);
+  hipLaunchKernelGGL(diag_product_kernel, dim3(T, T, count), dim3(256), 0, stream, A, Z, P, np, np * np, skip);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
