@@ -48,11 +48,12 @@ typedef enum {
 
 typedef enum {
   GLASSO_FP64 = 0,        /* every step in FP64 */
-  GLASSO_MIXED_FP32 = 1,  /* A Z A products in FP32 MFMA; factor, log det, PD test, W, KKT in FP64 */
+  GLASSO_MIXED_FP32 = 1,  /* A Z A products in FP32 MFMA; factor, log det, PD test and KKT in FP64;
+                             W as set by w_mixed */
   GLASSO_MIXED_BF16X3 = 2 /* A Z A with each operand split into two BF16 parts, x = hi + lo, and each
                              product formed as hi hi + hi lo + lo hi on BF16 MFMA with FP32
-                             accumulation (about 2^-16 relative); factor, log det, PD test, W,
-                             KKT in FP64 */
+                             accumulation (about 2^-16 relative); factor, log det, PD test and
+                             KKT in FP64; W as set by w_mixed */
 } glasso_precision;
 
 typedef struct {
@@ -74,8 +75,9 @@ typedef struct {
                       a HIP graph per workspace shape and replayed; results are bitwise
                       the same as eager launches.  time_ms[1] then holds [1] + [2], and
                       time_ms[5] the whole A Z A sequence.  Default 0. */
-  int w_mixed;     /* W = A^{-1} from the FP64 factor in FP32 MFMA (triangular inverse and
-                      V^T V) while a problem iterates;
+  int w_mixed;     /* W = A^{-1} from the FP64 factor with FP32 accuracy (triangular inverse
+                      and V^T V, each product formed from exact three-part BF16 splits of
+                      FP32 values, six BF16 MFMA products per pair) while a problem iterates;
                       before it stops (KKT <= tol or max_iter) W and the measures are
                       recomputed in FP64 and only those decide, after which the problem
                       keeps FP64 W.  Returned W and reported measures are always FP64.
@@ -189,7 +191,8 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
 
 /* W = A^{-1} (full symmetric) from the Cholesky factor of A (eq. grad_hessian
  * needs it for g = S - W).  With opt.w_mixed == 1 the triangular inverse and the
- * product V^T V run in FP32 MFMA, as in the mixed-W iterations of glasso_solve.
+ * product V^T V run with FP32 accuracy on BF16 MFMA, as in the mixed-W iterations
+ * of glasso_solve.
  * Errors: NOT_PD when A is not PD. */
 glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W, void* stream);
 

@@ -38,7 +38,7 @@ struct Workspace {
   double* part = nullptr;
   double* scal = nullptr;
   int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
-  int *skip32 = nullptr, *skip64 = nullptr;  // W products in FP32 / FP64 (the mixed-W ladder)
+  int *skip32 = nullptr, *skip64 = nullptr;  // W with FP32 accuracy / in FP64 (the mixed-W ladder)
   double *lam = nullptr, *t = nullptr;
   int64_t* bad = nullptr;
   double* vec = nullptr;
@@ -574,10 +574,11 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   // The four launch sequences of an iteration.  Each reads its host inputs from
   // the pinned mirrors when it runs and ends without waiting; `timed` adds the
   // phase events (eager runs only).
-  // W precision ladder (mixed forms): W = V^T V in FP32 while a problem iterates;
-  // once its KKT measure (or the iteration cap) says stop, W and the measures are
-  // recomputed in FP64 from the same V and only the FP64 values decide; from then on
-  // that problem keeps FP64 W.  Every returned W and reported measure is FP64.
+  // W precision ladder (mixed forms): W with FP32 accuracy (BF16x6) while a problem
+  // iterates; once its KKT measure (or the iteration cap) says stop, W and the
+  // measures are recomputed in FP64 from the same factor and only the FP64 values
+  // decide; from then on that problem keeps FP64 W.  Every returned W and reported
+  // measure is FP64.
   const bool w_mixed = (o.w_mixed < 0) ? (o.precision != GLASSO_FP64) : (o.w_mixed != 0);
   std::vector<int> wexact(count, w_mixed ? 0 : 1), wlast(count, 1);
   PassBatch pr = pb;  // FP64 re-check of the problems in skip64 == 0
@@ -596,7 +597,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     e2 = push_ints(s, w.skip64, hm.skip64, count);
     if (e2) return e2;
     if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
-    // FP64 problems: V = inv(L) in place, W = V^T V; FP32 problems keep L intact
+    // FP64-W problems: V = inv(L) in place, W = V^T V; the others keep L intact
     // (their FP64 re-check starts from it)
     K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
@@ -733,7 +734,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     HIP_TRY(hipStreamSynchronize(st));
     phase[1] += elapsed(h->ev[0], h->ev[1]);
     phase[2] += elapsed(h->ev[1], h->ev[2]);
-    // a problem that would stop on an FP32 W is re-checked with FP64 W first
+    // a problem that would stop on an FP32-accurate W is re-checked with FP64 W first
     std::vector<int> mark(count, 0);
     int nmark = 0;
     for (int b = 0; b < count; ++b)
