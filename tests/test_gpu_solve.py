@@ -108,11 +108,19 @@ def test_diagonal_solution_zero_iterations(g):
     np.testing.assert_array_equal(A, np.diag(1.0 / (np.diag(S) + lam)))
 
 
-def test_random_sparse_n2000_workload(g):
-    """The n=2000 random-sparse workload with its frozen lambda (nnz ~ 5n)."""
+@pytest.fixture(scope="module")
+def n2000():
     cfg = json.load(open(os.path.join(HERE, "golden", "workloads.json")))["random_sparse_n2000"]
     S, _ = synth.random_sparse_problem(cfg["n"], cfg["m"], cfg["seed"])
-    res, ref = check_against_oracle(g, S, cfg["lambda"], cfg["tol"])
+    return cfg, S, oracle.pista(S, cfg["lambda"], cfg["tol"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_random_sparse_n2000_workload(g, n2000, precision):
+    """The n=2000 random-sparse workload with its frozen lambda (nnz ~ 5n): the FP64
+    path and both mixed forms (FP64 factor, line search and KKT) against the oracle."""
+    cfg, S, ref = n2000
+    res, _ = check_against_oracle(g, S, cfg["lambda"], cfg["tol"], solver=g.Solver(precision=precision), ref=ref)
     assert abs(res.nnz - cfg["oracle_nnz"]) <= 0.01 * cfg["oracle_nnz"]
 
 
