@@ -14,7 +14,7 @@ Extra objects on the same line:
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
                 from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
   serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
-                lambda = 0.3 lambda_max, mixed FP32: p50/p99 latency, solves/s
+                lambda = 0.3 lambda_max, BF16x3 form: p50/p99 latency, solves/s
   cpu_baseline  the CPU oracle on the host cores: one pISTA iteration of the
                 lambda = 0.2 chain problem, scaled by the GPU's iteration count
 
@@ -209,7 +209,7 @@ def bench_small(g, torch, dev, count=1024):
             "iterations": sum(r.iterations for r in res)}
 
 
-def bench_serve(g, count, seed=0):
+def bench_serve(g, count, seed=0, precision="bf16x3"):
     """Serving: closed-loop capacity, then Poisson replays at 0.5, 0.8, 1.0 x capacity."""
     import numpy as np
 
@@ -225,7 +225,7 @@ def bench_serve(g, count, seed=0):
     log(f"[bench] serving: generated {count} requests in {time.perf_counter() - t:.1f}s")
     slots = 4
     budget = 64 * 2**30
-    eng = GpuEngine(slots=slots, precision="fp32", tol=1e-5)
+    eng = GpuEngine(slots=slots, precision=precision, tol=1e-5)
 
     def requests(rate):
         arr = [a / rate for (a, _, _) in base] if rate else [0.0] * count
@@ -239,7 +239,7 @@ def bench_serve(g, count, seed=0):
     serial = Server(eng, slots=1, hbm_budget=budget, footprint=gpu_footprint).run(requests(None), realtime=False)
     log(f"[bench] serving one slot: {serial.solves_per_s:.2f} solves/s")
     out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2, lambda=0.3 lambda_max, "
-                       f"random sparse, mixed FP32, tol 1e-5, {slots} slots, HBM budget {budget >> 30} GiB",
+                       f"random sparse, {precision} form, tol 1e-5, {slots} slots, HBM budget {budget >> 30} GiB",
            "closed_loop_solves_per_s": capacity, "one_slot_solves_per_s": serial.solves_per_s,
            "speedup_vs_one_slot": capacity / serial.solves_per_s, "rates": {}}
     for frac in (0.5, 0.8, 1.0):

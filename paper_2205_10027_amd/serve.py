@@ -68,7 +68,7 @@ class Stats:
         return self.count / self.makespan_s if self.makespan_s > 0 else float("nan")
 
 
-def gpu_footprint(n: int, precision: str = "fp32") -> int:
+def gpu_footprint(n: int, precision: str = "bf16x3") -> int:
     """Device bytes a request of size n holds while it runs."""
     import paper_2205_10027_amd as g
 
@@ -78,7 +78,7 @@ def gpu_footprint(n: int, precision: str = "fp32") -> int:
 class GpuEngine:
     """One libglasso handle and one HIP stream per slot."""
 
-    def __init__(self, slots: int, precision: str = "fp32", tol: float = 1e-5, device: int = 0):
+    def __init__(self, slots: int, precision: str = "bf16x3", tol: float = 1e-5, device: int = 0):
         import torch
 
         import paper_2205_10027_amd as g

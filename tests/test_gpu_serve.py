@@ -11,7 +11,8 @@ from tests.gpu_util import device, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-def test_mix_equals_alone():
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32"])
+def test_mix_equals_alone(precision):
     device()
     import paper_2205_10027_amd as g
     from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_footprint
@@ -21,12 +22,12 @@ def test_mix_equals_alone():
     for i, (n, seed) in enumerate(specs):
         S, _ = synth.random_sparse_problem(n, n // 2, seed)
         reqs.append(Request(i, 0.002 * i, n, S, 0.3 * synth.lambda_max(S)))
-    eng = GpuEngine(slots=4, precision="fp32", tol=1e-5)
-    budget = sum(gpu_footprint(n) for n, _ in specs[:5])
-    srv = Server(eng, slots=4, hbm_budget=budget, footprint=gpu_footprint)
+    eng = GpuEngine(slots=4, precision=precision, tol=1e-5)
+    budget = sum(gpu_footprint(n, precision) for n, _ in specs[:5])
+    srv = Server(eng, slots=4, hbm_budget=budget, footprint=lambda n: gpu_footprint(n, precision))
     st = srv.run(reqs)
     assert st.count == len(reqs) and st.peak_bytes <= budget
-    alone_solver = g.Solver(precision="fp32")
+    alone_solver = g.Solver(precision=precision)
     for r in reqs:
         assert r.error is None, r.error
         mix = r.result
