@@ -44,6 +44,19 @@ def test_precond_product_fp64(solver, n):
     assert np.array_equal(P, P.T)
 
 
+@pytest.mark.parametrize("n", [5, 300, 1024])
+def test_precond_product_fp64_diagonal_A(solver, n):
+    """For a diagonal A every entry of the FP64 GEMM pair is one rounded product per
+    GEMM, (A_ii Z_ij) A_jj, the other terms being exact zeros: the elementwise D Z D
+    the solver uses for the first product of a diagonal start rounds the same way."""
+    rng = np.random.default_rng(5)
+    d = rng.uniform(0.1, 3.0, n)
+    Z = sym(rng.standard_normal((n, n)))
+    P = to_host(solver.precond_product(to_dev(np.diag(d)), to_dev(Z)))
+    ref = (d[:, None] * Z) * d[None, :]
+    assert np.array_equal(np.tril(P), np.tril(ref))
+
+
 @pytest.mark.parametrize("n", [5, 128, 300, 1024])
 def test_precond_product_fp32(solver, n):
     """FP32 MFMA product: inputs rounded to FP32 (relative 2^-24) and FP32
