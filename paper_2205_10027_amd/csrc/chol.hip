@@ -141,8 +141,8 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
 // the diagonal from dL; then the inverse of the block (lds_trtri) to Dinv (ld 128,
 // zeros above the diagonal).
 __global__ __launch_bounds__(256) void finish_diag_blocks_kernel(double* A, int64_t lda, const double* dL,
-                                                                 double* Dinv, const int* info, FactorBatch fb) {
-  if (info[blockIdx.y]) return;
+                                                                 double* Dinv, const int* skip, FactorBatch fb) {
+  if (skip && skip[blockIdx.y]) return;
   double* D = A + blockIdx.y * fb.sA + (int64_t)blockIdx.x * NB * (lda + 1);
   const double* d = dL + blockIdx.y * fb.sdL + (int64_t)blockIdx.x * NB;
   double* Di = Dinv + blockIdx.y * fb.sDinv + (int64_t)blockIdx.x * NB * NB;
@@ -190,8 +190,17 @@ __global__ __launch_bounds__(256) void copy_diag_blocks_kernel(double* L, int64_
 
 }  // namespace
 
+int finish_factor(hipStream_t stream, double* A, int64_t lda, int n, const double* dL, double* Dinv,
+                  const int* skip, const FactorBatch& fb) {
+  if (n % NB) return -1;
+  if (fb.count <= 0) return 0;
+  hipLaunchKernelGGL(finish_diag_blocks_kernel, dim3(n / NB, fb.count), dim3(256), 0, stream, A, lda, dL, Dinv, skip,
+                     fb);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv, int* info,
-                const FactorBatch& fb) {
+                const FactorBatch& fb, int finish) {
   if (n % NB) return -1;
   if (fb.count <= 0) return 0;
   ZBatch zA;  // operands and output inside the factored matrix
@@ -223,9 +232,7 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
     }
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(finish_diag_blocks_kernel, dim3(n / NB, fb.count), dim3(256), 0, stream, A, lda, dL, Dinv, info,
-                     fb);
-  return hipGetLastError() == hipSuccess ? 0 : -2;
+  return finish ? finish_factor(stream, A, lda, n, dL, Dinv, info, fb) : 0;
 }
 
 int trtri_lower(hipStream_t stream, double* L, int64_t ld, int n, const double* Dinv, double* tmp,

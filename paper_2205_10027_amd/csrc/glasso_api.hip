@@ -597,6 +597,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     e2 = push_ints(s, w.skip64, hm.skip64, count);
     if (e2) return e2;
     if (timed) HIP_TRY(hipEventRecord(h->ev[0], s));
+    // the accepted trial's factor: place and invert its diagonal blocks
+    K_TRY(finish_factor(s, w.L, np, (int)np, w.dL, w.Dinv, w.skip, fbw));
     // FP64-W problems: V = inv(L) in place, W = V^T V; the others keep L intact
     // (their FP64 re-check starts from it)
     K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
@@ -640,7 +642,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     e2 = push_doubles(s, w.t, hm.t, count);
     if (e2) return e2;
     K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
-    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w)));
+    // the trial's factor is finished (diagonal blocks placed and inverted) only if
+    // it is accepted, at the next head
+    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w), 0));
     K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal, pt));
     return fetch_async(h, s);
   };

@@ -71,9 +71,17 @@ struct FactorBatch {
 // (n/128 blocks of 128x128, zeros above the diagonal) and, on a non-positive or
 // non-finite pivot, info = global column + 1.  A problem whose info is nonzero
 // on entry (or becomes nonzero) is skipped by every later kernel.  info has one
-// entry per problem of the batch.
+// entry per problem of the batch.  With finish == 0 the factor is left unfinished:
+// the strict lower part of each 128x128 diagonal block of L sits transposed in the
+// block's strict upper triangle (dL is final) until finish_factor runs; the line
+// search only needs dL of its trial points.
 int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv,
-                int* info, const FactorBatch& fb = FactorBatch());
+                int* info, const FactorBatch& fb = FactorBatch(), int finish = 1);
+// Places the diagonal blocks of a factor left by potrf_lower(finish = 0) and
+// writes their inverses to Dinv, for the problems with skip == 0.  Idempotent as
+// long as L has not been overwritten in between (trtri_lower does that).
+int finish_factor(hipStream_t stream, double* A, int64_t lda, int n, const double* dL, double* Dinv,
+                  const int* skip, const FactorBatch& fb = FactorBatch());
 
 // In-place inverse of the lower-triangular n x n factor L given its diagonal-block
 // inverses (from potrf_lower).  tmp needs n*n/4 doubles per problem (stride sTmp).
