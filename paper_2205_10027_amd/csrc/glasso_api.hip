@@ -26,17 +26,21 @@ struct Workspace {
   int cap_count = 0;   // problems the buffers were laid out for
   int64_t cap_np = 0;  // padded size the buffers were laid out for
   int count = 0;       // problems of the current call
+  int slots = 0;       // line-search trial slots of the current call (>= count)
   int64_t np = 0;      // padded size (leading dimension) of the current call
   void* base = nullptr;
   size_t bytes = 0;
   // per problem b: matrices at + b * np^2, diagonals at + b * np, block inverses at
-  // + b * np * 128, pass partials at + b * tiles * 8, scalar slots at + b * SC_COUNT
+  // + b * np * 128, pass partials at + b * tiles * 8, scalar slots at + b * SC_COUNT.
+  // The trial point and factor (At, Lt, dLt), info, lsskip and t are per trial slot
+  // j (slots of problem b: b * slots / count ...); trial scalars at scal_t + j * SC_COUNT.
   double *S = nullptr, *A = nullptr, *At = nullptr, *L = nullptr, *Lt = nullptr, *W = nullptr, *Z = nullptr,
          *X = nullptr, *P = nullptr;
   int8_t* GM = nullptr;
   double *dL = nullptr, *dLt = nullptr, *Dinv = nullptr, *Dinvt = nullptr;
   double* part = nullptr;
   double* scal = nullptr;
+  double* scal_t = nullptr;
   int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
   int *skip32 = nullptr, *skip64 = nullptr;  // W with FP32 accuracy / in FP64 (the mixed-W ladder)
   double *lam = nullptr, *t = nullptr;
@@ -49,7 +53,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Carve the workspace for `count` problems of padded size np out of one
 // allocation (base may be null to only measure).
-size_t layout(Workspace& w, int count, int64_t np, char* base) {
+size_t layout(Workspace& w, int count, int slots, int64_t np, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -57,30 +61,32 @@ size_t layout(Workspace& w, int count, int64_t np, char* base) {
     return p;
   };
   const size_t mat = (size_t)count * np * np * sizeof(double);
+  const size_t mat_t = (size_t)slots * np * np * sizeof(double);
   w.S = (double*)take(mat);
   w.A = (double*)take(mat);
-  w.At = (double*)take(mat);
+  w.At = (double*)take(mat_t);
   w.L = (double*)take(mat);
-  w.Lt = (double*)take(mat);
+  w.Lt = (double*)take(mat_t);
   w.W = (double*)take(mat);
   w.Z = (double*)take(mat);
   w.X = (double*)take(mat);
   w.P = (double*)take(mat);
   w.GM = (int8_t*)take((size_t)count * np * np);
   w.dL = (double*)take((size_t)count * np * sizeof(double));
-  w.dLt = (double*)take((size_t)count * np * sizeof(double));
+  w.dLt = (double*)take((size_t)slots * np * sizeof(double));
   w.Dinv = (double*)take((size_t)count * np * TILE * sizeof(double));
   w.Dinvt = (double*)take((size_t)count * np * TILE * sizeof(double));
-  w.part = (double*)take((size_t)count * pass_tiles(np) * 8 * sizeof(double));
-  w.scal = (double*)take((size_t)count * SC_COUNT * sizeof(double));
-  w.info = (int*)take(count * sizeof(int));
+  w.part = (double*)take((size_t)slots * pass_tiles(np) * 8 * sizeof(double));
+  w.scal = (double*)take((size_t)(count + slots) * SC_COUNT * sizeof(double));
+  w.scal_t = base ? w.scal + (size_t)count * SC_COUNT : nullptr;
+  w.info = (int*)take(slots * sizeof(int));
   w.skip = (int*)take(count * sizeof(int));
-  w.lsskip = (int*)take(count * sizeof(int));
+  w.lsskip = (int*)take(slots * sizeof(int));
   w.accept = (int*)take(count * sizeof(int));
   w.skip32 = (int*)take(count * sizeof(int));
   w.skip64 = (int*)take(count * sizeof(int));
   w.lam = (double*)take(count * sizeof(double));
-  w.t = (double*)take(count * sizeof(double));
+  w.t = (double*)take(slots * sizeof(double));
   w.bad = (int64_t*)take(sizeof(int64_t));
   w.vec = (double*)take(2 * np * sizeof(double));
   return off;
@@ -88,7 +94,9 @@ size_t layout(Workspace& w, int count, int64_t np, char* base) {
 
 // pinned host mirrors of the per-problem device arrays
 struct HostMirror {
-  int cap = 0;
+  int cap = 0;        // problems
+  int cap_slots = 0;  // trial slots
+  int count = 0;      // problems of the current call (scal_t follows their scalars)
   double* scal = nullptr;
   int *info = nullptr, *skip = nullptr, *lsskip = nullptr, *accept = nullptr;
   int *skip32 = nullptr, *skip64 = nullptr;
@@ -102,10 +110,10 @@ struct GraphKey {
   const void* base = nullptr;
   const void* host = nullptr;
   int64_t np = 0, n = 0, sS = 0;
-  int count = 0, precision = -1, tiles = -1;
+  int count = 0, slots = 0, precision = -1, tiles = -1;
   bool operator==(const GraphKey& o) const {
     return base == o.base && host == o.host && np == o.np && n == o.n && sS == o.sS && count == o.count &&
-           precision == o.precision && tiles == o.tiles;
+           slots == o.slots && precision == o.precision && tiles == o.tiles;
   }
 };
 struct Graphs {
@@ -145,41 +153,50 @@ void free_host(HostMirror& m) {
   m = HostMirror();
 }
 
-glasso_err ensure_host(glasso_handle h, int count) {
+// host arrays: per problem (skip, accept, skip32, skip64, lam) or per trial slot
+// (scalars after the problems' own, info, lsskip, t)
+glasso_err ensure_host(glasso_handle h, int count, int slots) {
   HostMirror& m = h->hm;
-  if (m.scal && m.cap >= count) return GLASSO_OK;
+  m.count = count;
+  if (m.scal && m.cap >= count && m.cap_slots >= slots) return GLASSO_OK;
+  const int c = std::max(count, m.cap), sl = std::max({slots, count, m.cap_slots});
   free_host(m);
-  const size_t bytes = (size_t)count * (SC_COUNT + 2) * sizeof(double) + (size_t)count * 6 * sizeof(int) + 64;
+  const size_t bytes = (size_t)(c + sl) * SC_COUNT * sizeof(double) + (size_t)(c + sl) * sizeof(double) +
+                       (size_t)(5 * c + 2 * sl) * sizeof(int) + 64;
   char* p = nullptr;
   if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) return GLASSO_ERR_HIP;
-  m.cap = count;
-  m.scal = (double*)p;
-  m.lam = m.scal + (size_t)count * SC_COUNT;
-  m.t = m.lam + count;
-  m.info = (int*)(m.t + count);
-  m.skip = m.info + count;
-  m.lsskip = m.skip + count;
-  m.accept = m.lsskip + count;
-  m.skip32 = m.accept + count;
-  m.skip64 = m.skip32 + count;
-  m.bad = (int64_t*)(((uintptr_t)(m.skip64 + count) + 7) & ~uintptr_t(7));
+  m.cap = c;
+  m.cap_slots = sl;
+  m.count = count;
+  m.scal = (double*)p;  // problems' scalars, then the trial slots' (placed at scal + count * SC_COUNT)
+  m.lam = m.scal + (size_t)(c + sl) * SC_COUNT;
+  m.t = m.lam + c;
+  m.info = (int*)(m.t + sl);
+  m.lsskip = m.info + sl;
+  m.skip = m.lsskip + sl;
+  m.accept = m.skip + c;
+  m.skip32 = m.accept + c;
+  m.skip64 = m.skip32 + c;
+  m.bad = (int64_t*)(((uintptr_t)(m.skip64 + c) + 7) & ~uintptr_t(7));
   return GLASSO_OK;
 }
 
 // The zero fill of a new allocation is ordered on `st`, the stream of the call
 // that uses the workspace: a plain hipMemset runs on the null stream, which is not
 // ordered with non-blocking caller streams and could land after the first kernels.
-glasso_err ensure_workspace(glasso_handle h, int count, int64_t np, hipStream_t st) {
+glasso_err ensure_workspace(glasso_handle h, int count, int64_t np, hipStream_t st, int slots = 0) {
   Workspace& w = h->ws;
-  glasso_err e = ensure_host(h, count);
+  slots = std::max(slots, count);
+  glasso_err e = ensure_host(h, count, slots);
   if (e) return e;
   if (w.base && w.cap_count >= count && w.cap_np >= np &&
       (size_t)w.cap_count * w.cap_np * w.cap_np >= (size_t)count * np * np) {
-    // re-carve the same allocation for this (count, np): every buffer fits
+    // re-carve the same allocation for this (count, slots, np): every buffer fits
     Workspace probe;
-    if (layout(probe, count, np, nullptr) <= w.bytes) {
-      layout(w, count, np, (char*)w.base);
+    if (layout(probe, count, slots, np, nullptr) <= w.bytes) {
+      layout(w, count, slots, np, (char*)w.base);
       w.count = count;
+      w.slots = slots;
       w.np = np;
       return GLASSO_OK;
     }
@@ -189,7 +206,7 @@ glasso_err ensure_workspace(glasso_handle h, int count, int64_t np, hipStream_t 
     w = Workspace();
   }
   Workspace probe;
-  const size_t bytes = layout(probe, count, np, nullptr);
+  const size_t bytes = layout(probe, count, slots, np, nullptr);
   void* base = nullptr;
   if (hipMalloc(&base, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -199,12 +216,13 @@ glasso_err ensure_workspace(glasso_handle h, int count, int64_t np, hipStream_t 
     (void)hipFree(base);
     return GLASSO_ERR_HIP;
   }
-  layout(w, count, np, (char*)base);
+  layout(w, count, slots, np, (char*)base);
   w.base = base;
   w.bytes = bytes;
   w.cap_count = count;
   w.cap_np = np;
   w.count = count;
+  w.slots = slots;
   w.np = np;
   return GLASSO_OK;
 }
@@ -221,8 +239,9 @@ FactorBatch factor_batch(const Workspace& w) {
 // scalar slots and factor status of every problem -> pinned host memory
 glasso_err fetch_async(glasso_handle h, hipStream_t st) {
   const Workspace& w = h->ws;
-  HIP_TRY(hipMemcpyAsync(h->hm.scal, w.scal, (size_t)w.count * SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h->hm.info, w.info, (size_t)w.count * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->hm.scal, w.scal, (size_t)(w.count + w.slots) * SC_COUNT * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->hm.info, w.info, (size_t)w.slots * sizeof(int), hipMemcpyDeviceToHost, st));
   return GLASSO_OK;
 }
 // ... and wait for it
@@ -259,6 +278,10 @@ glasso_err capture_graph(glasso_handle h, hipGraphExec_t* out, F&& body) {
   return GLASSO_OK;
 }
 double hscal(glasso_handle h, int b, int slot) { return h->hm.scal[(size_t)b * SC_COUNT + slot]; }
+// scalar of trial slot j
+double hscal_t(glasso_handle h, int j, int slot) {
+  return h->hm.scal[(size_t)(h->hm.count + j) * SC_COUNT + slot];
+}
 
 glasso_err push_ints(hipStream_t st, int* dev, const int* host, int count) {
   HIP_TRY(hipMemcpyAsync(dev, host, count * sizeof(int), hipMemcpyHostToDevice, st));
@@ -417,9 +440,10 @@ glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int b, int64_t n,
 // Alg. 1 for `count` problems of equal size n at once (the single solve is
 // count = 1).  Every phase is one batched launch sequence over the problems
 // still iterating; per-problem flags skip the others.  The line search runs in
-// rounds: each round evaluates one trial step per searching problem, and each
-// problem backtracks on its own t, so every problem follows exactly the
-// sequential line search of the paper.
+// rounds: each round evaluates one or more consecutive trial steps per searching
+// problem, and each problem backtracks on its own t and takes the first step
+// that succeeds, so every problem follows exactly the sequential line search of
+// the paper.
 // ------------------------------------------------------------------ tile autotuner
 // The FP64 GEMMs run 64x64 tiles for launches with fewer than `threshold`
 // 128x128 tiles.  The best threshold depends on the padded size and batch count
@@ -427,6 +451,12 @@ glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int b, int64_t n,
 // once per (device, np, count) and kept for the process.  Results do not depend
 // on it (both tile edges accumulate every output in the same order).
 constexpr int TUNE_CANDIDATES[] = {0, 64, 256, 1024, 1 << 30};
+
+// Line-search width: up to LS_WIDTH step sizes per round for padded sizes up to
+// LS_WIDE_MAX_NP, where one trial (pass + factorisation) leaves most of the chip idle.
+constexpr int LS_WIDTH = 4;
+constexpr int64_t LS_WIDE_MAX_NP = 2048;
+int ls_width(int64_t np) { return np <= LS_WIDE_MAX_NP ? LS_WIDTH : 1; }
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int>, int> g_tune;
@@ -507,7 +537,11 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   const auto t_start = std::chrono::steady_clock::now();
   const glasso_options& o = h->opt;
   const int64_t np = pad_to_tile(n);
-  glasso_err e = ensure_workspace(h, count, np, st);
+  // line-search width: trial slots per problem (several step sizes of the
+  // backtracking sequence per round while one round is launch-latency bound)
+  const int K = ls_width(np);
+  const int slots = count * K;
+  glasso_err e = ensure_workspace(h, count, np, st, slots);
   if (e) return e;
   e = apply_tile_policy(h, st, o.precision);
   if (e) return e;
@@ -558,7 +592,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   }
 
   std::vector<int> active(count, 1), status(count, GLASSO_MAX_ITER), it(count, 0), trials(count, 0),
-      fallbacks(count, 0), ls(count, 0), fb_used(count, 0), gemm_products(count, 0);
+      fallbacks(count, 0), ls(count, 0), fb_used(count, 0), gemm_products(count, 0), ncand(count, 0),
+      last_trials(count, 1), since(count, 0);
+  std::vector<double> tb(count, o.t0);  // next step size of each problem's backtracking sequence
   PassBatch pb;
   pb.count = count;
   pb.sS = sS;
@@ -567,9 +603,14 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   pb.lam = w.lam;
   pb.skip = w.skip;
   pb.t = nullptr;
-  PassBatch pt = pb;  // trial passes: problems still searching, their own t
+  PassBatch pt = pb;  // trial passes: slot y is candidate y % K of problem y / K
+  pt.count = slots;
+  pt.div = K;
   pt.skip = w.lsskip;
   pt.t = w.t;
+  FactorBatch fbt = factor_batch(w);
+  fbt.count = slots;
+  fbt.sDinv = 0;
 
   // The four launch sequences of an iteration.  Each reads its host inputs from
   // the pinned mirrors when it runs and ends without waiting; `timed` adds the
@@ -637,21 +678,21 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     return precond_product(w, s, o.precision, w.skip, timed ? h->ev + 5 : nullptr, z_split != nullptr);
   };
   auto trial = [&](hipStream_t s, bool) -> glasso_err {  // a4, a5
-    glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, count);
+    glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, slots);
     if (e2) return e2;
-    e2 = push_doubles(s, w.t, hm.t, count);
+    e2 = push_doubles(s, w.t, hm.t, slots);
     if (e2) return e2;
     K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
     // the trial's factor is finished (diagonal blocks placed and inverted) only if
     // it is accepted, at the next head
-    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, w.Dinvt, w.info, factor_batch(w), 0));
-    K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal, pt));
+    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, nullptr, w.info, fbt, 0));
+    K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal_t, pt));
     return fetch_async(h, s);
   };
   auto accept = [&](hipStream_t s, bool) -> glasso_err {  // a7
     glasso_err e2 = push_ints(s, w.accept, hm.accept, count);
     if (e2) return e2;
-    K_TRY(accept_trials(s, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, w.Dinv, w.Dinvt, np));
+    K_TRY(accept_trials(s, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, np));
     return GLASSO_OK;
   };
   const bool graphs = o.graphs != 0;
@@ -673,7 +714,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (parity) flip();
     }
   } swapped{w, 0};
-  const bool swap_accept = !graphs && count == 1;
+  const bool swap_accept = !graphs && count == 1 && K == 1;
   if (graphs) {
     GraphKey key;
     key.base = w.base;
@@ -682,6 +723,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     key.n = n;
     key.sS = sS;
     key.count = count;
+    key.slots = slots;
     key.precision = o.precision;
     key.tiles = get_gemm_f64_small_tile_below();
     if (!(h->graphs.key == key)) {
@@ -782,25 +824,31 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       for (int b = 0; b < count; ++b) gemm_products[b] += active[b];
     }
     HIP_TRY(hipEventRecord(h->ev[3], st));
-    // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease
+    // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease.
+    // A round evaluates the next ncand[b] <= K step sizes of that sequence for each
+    // searching problem (never past the point where the sequential search would
+    // take the fallback step or give up) and takes the first that succeeds, so the
+    // accepted step is the one the one-at-a-time search takes.  The first round of
+    // an iteration evaluates as many as the last accepted step needed.
     for (int b = 0; b < count; ++b) {
       ls[b] = active[b];
       fb_used[b] = 0;
-      hm.t[b] = o.t0;
+      tb[b] = o.t0;
     }
+    bool first_round = true;
     for (;;) {
       int nls = 0;
       for (int b = 0; b < count; ++b) {
         if (!ls[b]) continue;
-        if (hm.t[b] < o.t_floor && !fb_used[b]) {
+        if (tb[b] < o.t_floor && !fb_used[b]) {
           double tf = 0.0;
           e = cond_fallback_step(h, st, b, n, &tf);
           if (e) return e;
-          hm.t[b] = std::min(hm.t[b], tf);
+          tb[b] = std::min(tb[b], tf);
           fb_used[b] = 1;
           ++fallbacks[b];
         }
-        if (hm.t[b] < o.t_min) {
+        if (tb[b] < o.t_min) {
           ls[b] = 0;
           active[b] = 0;
           status[b] = GLASSO_LS_FAILED;
@@ -809,7 +857,21 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
         ++nls;
       }
       if (!nls) break;
-      for (int b = 0; b < count; ++b) hm.lsskip[b] = !ls[b];
+      for (int b = 0; b < count; ++b) {
+        for (int i = 0; i < K; ++i) hm.lsskip[b * K + i] = 1;
+        ncand[b] = 0;
+        if (!ls[b]) continue;
+        const int want = first_round ? std::min(K, std::max(1, last_trials[b])) : K;
+        double c = tb[b];
+        for (;;) {
+          hm.t[b * K + ncand[b]] = c;
+          hm.lsskip[b * K + ncand[b]] = 0;
+          if (++ncand[b] == want) break;
+          c *= o.shrink;
+          if (c < o.t_min || (c < o.t_floor && !fb_used[b])) break;
+        }
+      }
+      first_round = false;
       e = run(&h->graphs.trial, trial);
       if (e) return e;
       HIP_TRY(hipStreamSynchronize(st));
@@ -817,14 +879,22 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       for (int b = 0; b < count; ++b) {
         hm.accept[b] = 0;
         if (!ls[b]) continue;
-        ++trials[b];
-        if (hm.info[b] == 0 && hscal(h, b, SC_DF) < 0.0) {
-          hm.accept[b] = 1;
+        int got = -1;
+        for (int i = 0; i < ncand[b] && got < 0; ++i)
+          if (hm.info[b * K + i] == 0 && hscal_t(h, b * K + i, SC_DF) < 0.0) got = i;
+        if (got >= 0) {
+          trials[b] += got + 1;
+          since[b] += got + 1;
+          last_trials[b] = since[b];
+          since[b] = 0;
+          hm.accept[b] = b * K + got + 1;
           ls[b] = 0;
           ++it[b];
           ++nacc;
         } else {
-          hm.t[b] *= o.shrink;
+          trials[b] += ncand[b];
+          since[b] += ncand[b];
+          tb[b] = hm.t[b * K + ncand[b] - 1] * o.shrink;
         }
       }
       if (nacc) {
@@ -921,7 +991,7 @@ glasso_err glasso_create(glasso_handle* h, const glasso_options* opt) {
     delete hh;
     return GLASSO_ERR_HIP;
   }
-  if (ensure_host(hh, 1) != GLASSO_OK) {
+  if (ensure_host(hh, 1, 1) != GLASSO_OK) {
     delete hh;
     return GLASSO_ERR_HIP;
   }
@@ -967,7 +1037,8 @@ const char* glasso_error_string(glasso_err e) {
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes) {
   if (n < 1 || !bytes || !valid_precision(precision)) return GLASSO_ERR_INVALID_ARG;
   Workspace probe;
-  *bytes = layout(probe, 1, pad_to_tile(n), nullptr);
+  const int64_t np = pad_to_tile(n);
+  *bytes = layout(probe, 1, ls_width(np), np, nullptr);
   return GLASSO_OK;
 }
 

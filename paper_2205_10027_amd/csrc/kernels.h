@@ -120,6 +120,10 @@ struct PassBatch {
   const double* lam = nullptr;
   const double* t = nullptr;
   const int* skip = nullptr;
+  // trial passes: batch entry y is a trial slot of problem y / div; the problem's
+  // inputs (A, P, S, GM, diag(L), lambda) are read at that index, the slot's own
+  // step size, skip flag and outputs at y
+  int div = 1;
 };
 
 // Z (FP64, may be null) and/or Zs, its two-part bf16 split (4 bytes per element,
@@ -136,11 +140,11 @@ int pass_trial(hipStream_t stream, const double* A, const double* P, const doubl
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL,
                  const double* dLt, const int* info, int64_t n, double lam, double* scal,
                  const PassBatch& pb = PassBatch());
-// for every problem b with accept[b] != 0 copy the trial's A, factor, diagonal
-// and diagonal-block inverses over the current ones
+// for every problem b with accept[b] = j + 1 != 0 copy trial slot j's point, its
+// (unfinished) factor and diagonal over problem b's current ones; the diagonal-block
+// inverses are formed when the factor is finished
 int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At,
-                  double* L, const double* Lt, double* dL, const double* dLt, double* Dinv,
-                  const double* Dinvt, int64_t np);
+                  double* L, const double* Lt, double* dL, const double* dLt, int64_t np);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
 // ---- persistent small-problem solver (n <= SMALL_MAX_N, one workgroup per problem)

@@ -171,16 +171,16 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
   __shared__ double tt[64][65];
   __shared__ double di[64], dj[64];
   __shared__ double sh[4];
-  const int pbi = blockIdx.y;
+  const int pbi = blockIdx.y, prob = pbi / pb.div;  // trial slot, its problem
   const bool skipped = pb.skip && pb.skip[pbi];
   if (blockIdx.x == 0 && threadIdx.x == 0) info_reset[pbi] = skipped ? -1 : 0;
   if (skipped) return;
-  if (pb.lam) lam = pb.lam[pbi];
+  if (pb.lam) lam = pb.lam[prob];
   if (pb.t) t = pb.t[pbi];
-  A += pbi * pb.sM;
-  P += pbi * pb.sM;
-  S += pbi * pb.sS;
-  GM += pbi * pb.sM;
+  A += prob * pb.sM;
+  P += prob * pb.sM;
+  S += prob * pb.sS;
+  GM += prob * pb.sM;
   At += pbi * pb.sM;
   Lt += pbi * pb.sM;
   part += (int64_t)pbi * gridDim.x * TRIAL_PARTS;
@@ -251,11 +251,11 @@ __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, i
                                                            double lam, double* scal, PassBatch pb) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
-  const int pbi = blockIdx.x;
+  const int pbi = blockIdx.x, prob = pbi / pb.div;  // trial slot, its problem
   if (pb.skip && pb.skip[pbi]) return;
-  if (pb.lam) lam = pb.lam[pbi];
+  if (pb.lam) lam = pb.lam[prob];
   part += (int64_t)pbi * nparts * TRIAL_PARTS;
-  dL += pbi * pb.sV;
+  dL += prob * pb.sV;
   dLt += pbi * pb.sV;
   scal += (int64_t)pbi * SC_COUNT;
   const int inf = info[pbi];
@@ -495,32 +495,30 @@ __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict
   if (threadIdx.x == 0 && out) *out = nrm;
 }
 
-// Accept the trial of every problem b with accept[b] != 0: A_b <- At_b, L_b <- Lt_b
-// (np x np each), dL_b <- dLt_b (np), Dinv_b <- Dinvt_b (np x 128).
+// Accept trial slot j = accept[b] - 1 of every problem b with accept[b] != 0:
+// A_b <- At_j, L_b <- Lt_j (np x np each), dL_b <- dLt_j (np).
 __global__ void accept_kernel(const int* accept, double* A, const double* At, double* L, const double* Lt,
-                              double* dL, const double* dLt, double* Dinv, const double* Dinvt, int64_t nn,
-                              int64_t np) {
+                              double* dL, const double* dLt, int64_t nn, int64_t np) {
   const int b = blockIdx.y;
-  if (!accept[b]) return;
+  const int j = accept[b] - 1;  // trial slot to take, or none
+  if (j < 0) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t off = (int64_t)b * nn;
+  const int64_t dst = (int64_t)b * nn, src = (int64_t)j * nn;
   for (int64_t e = i0; e < nn; e += stride) {
-    A[off + e] = At[off + e];
-    L[off + e] = Lt[off + e];
+    A[dst + e] = At[src + e];
+    L[dst + e] = Lt[src + e];
   }
-  for (int64_t e = i0; e < np * 128; e += stride) Dinv[(int64_t)b * np * 128 + e] = Dinvt[(int64_t)b * np * 128 + e];
-  for (int64_t e = i0; e < np; e += stride) dL[(int64_t)b * np + e] = dLt[(int64_t)b * np + e];
+  for (int64_t e = i0; e < np; e += stride) dL[(int64_t)b * np + e] = dLt[(int64_t)j * np + e];
 }
 
 }  // namespace
 
 int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At, double* L,
-                  const double* Lt, double* dL, const double* dLt, double* Dinv, const double* Dinvt, int64_t np) {
+                  const double* Lt, double* dL, const double* dLt, int64_t np) {
   const int64_t nn = np * np;
   const int blocks = (int)std::min<int64_t>((nn + 255) / 256, 4096);
-  hipLaunchKernelGGL(accept_kernel, dim3(blocks, count), dim3(256), 0, stream, accept, A, At, L, Lt, dL, dLt, Dinv,
-                     Dinvt, nn, np);
+  hipLaunchKernelGGL(accept_kernel, dim3(blocks, count), dim3(256), 0, stream, accept, A, At, L, Lt, dL, dLt, nn, np);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
