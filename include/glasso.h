@@ -82,6 +82,12 @@ typedef struct {
                       recomputed in FP64 and only those decide, after which the problem
                       keeps FP64 W.  Returned W and reported measures are always FP64.
                       -1 (default): on for the mixed precisions, off for FP64; 0 off; 1 on. */
+  int ls_width;    /* step sizes of the backtracking sequence (t, t*shrink, ...) that one
+                      line-search round factors per problem, at once; the first that
+                      succeeds is taken, so the accepted steps, iterations and ls_trials
+                      are the same for every width.  Each unit of width holds one more
+                      trial point and factor (2 n^2 doubles) per problem.  0 (default):
+                      4 for n <= 2048, 1 above; else 1 .. 16. */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)
@@ -115,8 +121,8 @@ glasso_err glasso_destroy(glasso_handle h);
 /* Static description of an error code. */
 const char* glasso_error_string(glasso_err e);
 
-/* Device bytes of workspace a solve of size n needs with `precision` (for
- * admission by HBM footprint).  Errors: INVALID_ARG for n < 1 or bytes == NULL. */
+/* Device bytes of workspace a solve of size n needs with `precision` and the
+ * default ls_width (for admission by HBM footprint).  Errors: INVALID_ARG for n < 1 or bytes == NULL. */
 glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
 
 /* Many small problems (n <= GLASSO_SMALL_MAX_N each, sizes may differ) in ONE

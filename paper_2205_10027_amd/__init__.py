@@ -86,7 +86,7 @@ class Solver:
     def __init__(self, precision: str | int = "fp64", max_iter: int = 500, t0: float = 1.0,
                  shrink: float = 0.5, t_floor: float = 1e-4, t_min: float = 1e-12,
                  warm_start: bool = False, tile_policy: int = TILES_AUTO, graphs: bool = False,
-                 w_mixed: int = -1):
+                 w_mixed: int = -1, ls_width: int = 0):
         opt = GlassoOptions()
         _check(_lib.glasso_default_options(ctypes.byref(opt)), "glasso_default_options")
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -99,6 +99,7 @@ class Solver:
         opt.tile_policy = int(tile_policy)
         opt.graphs = int(bool(graphs))
         opt.w_mixed = int(w_mixed)
+        opt.ls_width = int(ls_width)
         self.options = opt
         h = ctypes.c_void_p()
         _check(_lib.glasso_create(ctypes.byref(h), ctypes.byref(opt)), "glasso_create")

@@ -22,6 +22,7 @@ class GlassoOptions(ctypes.Structure):
         ("tile_policy", ctypes.c_int),
         ("graphs", ctypes.c_int),
         ("w_mixed", ctypes.c_int),
+        ("ls_width", ctypes.c_int),
     ]
 
 

@@ -294,10 +294,18 @@ glasso_err push_doubles(hipStream_t st, double* dev, const double* host, int cou
 
 bool valid_precision(int p) { return p == GLASSO_FP64 || p == GLASSO_MIXED_FP32 || p == GLASSO_MIXED_BF16X3; }
 
+// Default line-search width: up to LS_WIDTH step sizes per round for padded sizes
+// up to LS_WIDE_MAX_NP, where one trial (pass + factorisation) leaves most of the
+// chip idle.
+constexpr int LS_WIDTH = 4, LS_WIDTH_MAX = 16;
+constexpr int64_t LS_WIDE_MAX_NP = 2048;
+int ls_width(int64_t np) { return np <= LS_WIDE_MAX_NP ? LS_WIDTH : 1; }
+
 glasso_err check_options(const glasso_options* o) {
   if (!valid_precision(o->precision)) return GLASSO_ERR_INVALID_ARG;
   if (o->max_iter < 0 || o->tile_policy < GLASSO_TILES_AUTO || o->w_mixed < -1 || o->w_mixed > 1)
     return GLASSO_ERR_INVALID_ARG;
+  if (o->ls_width < 0 || o->ls_width > LS_WIDTH_MAX) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -452,11 +460,7 @@ glasso_err cond_fallback_step(glasso_handle h, hipStream_t st, int b, int64_t n,
 // on it (both tile edges accumulate every output in the same order).
 constexpr int TUNE_CANDIDATES[] = {0, 64, 256, 1024, 1 << 30};
 
-// Line-search width: up to LS_WIDTH step sizes per round for padded sizes up to
-// LS_WIDE_MAX_NP, where one trial (pass + factorisation) leaves most of the chip idle.
-constexpr int LS_WIDTH = 4;
-constexpr int64_t LS_WIDE_MAX_NP = 2048;
-int ls_width(int64_t np) { return np <= LS_WIDE_MAX_NP ? LS_WIDTH : 1; }
+
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int>, int> g_tune;
@@ -539,7 +543,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   const int64_t np = pad_to_tile(n);
   // line-search width: trial slots per problem (several step sizes of the
   // backtracking sequence per round while one round is launch-latency bound)
-  const int K = ls_width(np);
+  const int K = o.ls_width > 0 ? o.ls_width : ls_width(np);
   const int slots = count * K;
   glasso_err e = ensure_workspace(h, count, np, st, slots);
   if (e) return e;

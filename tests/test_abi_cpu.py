@@ -45,6 +45,10 @@ def test_host_only_entry_points():
     assert 9 * np_ * np_ * 8 < b < 9 * np_ * np_ * 8 + 2 * np_ * np_ + 64 * 2**20
     with pytest.raises(g.GlassoError):
         g.workspace_bytes(0)
+    # up to n = 2048 the line search holds 4 trial points and factors per problem
+    b1, np1 = g.workspace_bytes(1000), 1024
+    assert 15 * np1 * np1 * 8 < b1 < 15 * np1 * np1 * 8 + 2 * np1 * np1 + 64 * 2**20
+    assert opt.ls_width == 0
     # the mixed forms keep their reduced-precision operands inside the FP64 buffers
     assert g.workspace_bytes(10000, "fp32") == g.workspace_bytes(10000, "bf16x3") == b
     with pytest.raises(g.GlassoError):
@@ -60,6 +64,10 @@ def test_host_only_entry_points():
     lib.glasso_default_options(ctypes.byref(bad))
     bad.precision = 3
     assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
+    for width in (-1, 17):
+        lib.glasso_default_options(ctypes.byref(bad))
+        bad.ls_width = width
+        assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
     assert lib.glasso_autotune(None, 100, 1, None, None) == 1
 
 
@@ -72,8 +80,9 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
          offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
+         offsetof(glasso_options, ls_width),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
          offsetof(glasso_info, time_ms), offsetof(glasso_info, aza_gemm_products));
   return 0;
@@ -85,7 +94,8 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, g.GlassoOptions.tile_policy.offset,
-            g.GlassoOptions.graphs.offset, g.GlassoOptions.w_mixed.offset, ctypes.sizeof(g.GlassoInfo),
+            g.GlassoOptions.graphs.offset, g.GlassoOptions.w_mixed.offset, g.GlassoOptions.ls_width.offset,
+            ctypes.sizeof(g.GlassoInfo),
             g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset,
             g.GlassoInfo.aza_gemm_products.offset]
     assert [int(x) for x in out] == want

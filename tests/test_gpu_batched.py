@@ -85,3 +85,30 @@ def test_batch_warm_start_not_pd(g):
     with pytest.raises(g.GlassoError) as e:
         g.Solver(warm_start=True).solve_batched(St, [0.2, 0.3], 1e-6, A_list=[good, bad])
     assert e.value.code == 2
+
+
+@pytest.mark.parametrize("t_floor", [1e-4, 0.3])
+def test_line_search_width_invariant(g, t_floor):
+    """Several step sizes per line-search round (ls_width) give the same accepted
+    steps as one at a time: bitwise the same A and W, iterations, trial and
+    fallback counts, single and batched.  t_floor = 0.3 sends every search that
+    reaches t = 0.25 through the cond-based fallback step (Sec. 5), which a round
+    must not run ahead of."""
+    S, _ = synth.random_sparse_problem(300, 150, 5)
+    lm = synth.lambda_max(S)
+    lams = [0.5 * lm, 0.15 * lm, 0.08 * lm]
+    St = to_dev(S)
+    runs = {}
+    for width in (1, 3, 0, 16):
+        s = g.Solver(ls_width=width, t_floor=t_floor)
+        runs[width] = (s.solve_batched(St, lams, 1e-7), [s.solve(St, lam, 1e-7) for lam in lams])
+    ref_b, ref_s = runs[1]
+    assert sum(r.ls_trials for r in ref_s) > sum(r.iterations for r in ref_s)  # the searches backtrack
+    if t_floor > 0.25:
+        assert sum(r.fallback_steps for r in ref_s) > 0
+    for width, (rb, rs) in runs.items():
+        for a, b in list(zip(ref_b, rb)) + list(zip(ref_s, rs)) + list(zip(ref_s, rb)):
+            assert (a.status, a.iterations, a.ls_trials, a.fallback_steps) == \
+                (b.status, b.iterations, b.ls_trials, b.fallback_steps), width
+            assert np.array_equal(to_host(a.A), to_host(b.A)), width
+            assert np.array_equal(to_host(a.W), to_host(b.W)), width
