@@ -232,7 +232,9 @@ def bench_serve(g, count, seed=0, precision="bf16x3"):
         return [Request(i, arr[i], n, S, lam) for i, (n, S, lam) in enumerate(problems)]
 
     srv = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint)
-    srv.run(requests(None)[: min(8, count)], realtime=False)  # warmup
+    # warmup: one pass over every request, so that the first use of each padded size
+    # (tile autotuning, workspace growth of each slot's handle) is not timed
+    srv.run(requests(None), realtime=False)
     st = srv.run(requests(None), realtime=False)
     capacity = st.solves_per_s
     log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
