@@ -96,8 +96,8 @@ def test_precond_product_bf16x3(solver, n):
 @pytest.mark.parametrize("precision,n", [("fp64", 256), ("fp32", 256), ("bf16x3", 256), ("bf16x3", 2100)])
 def test_precond_product_structure(solver, precision, n):
     """Identity and permutation cases pin the MFMA lane layout exactly (small
-    integers are exact in every form; n = 2100 takes the wide BF16x3 tiles with a
-    partial last tile row)."""
+    integers are exact in every form; n = 2100 pads to 17 tiles of 128, an odd
+    count, with 52 rows of padding in the last)."""
     rng = np.random.default_rng(3)
     Z = sym(rng.integers(-3, 4, size=(n, n)).astype(np.float64))
     P = to_host(solver.precond_product(to_dev(np.eye(n)), to_dev(Z), precision=precision))
