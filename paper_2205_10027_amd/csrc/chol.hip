@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
   // (register s of lane l: R[l%16][16b + 4s + l/16]); issued after the block is in
   // LDS, they arrive while it is being factored
-  double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
+  const double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
   v4d x[8];
   if (solver) {
 #pragma unroll
@@ -130,10 +130,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
       for (int s = 0; s < 4; ++s)
         x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + li][16 * q + 4 * s + lk], x[q][s], x[b], 0, 0, 0);
   }
+  // the solved rows go out through LDS so that each store writes a whole row
+  // (1 KB per instruction) instead of 32 bytes in each of 16 rows
+  __syncthreads();  // every wave is done reading L11 and the inverse blocks
 #pragma unroll
   for (int b = 0; b < 8; ++b)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) R[16 * b + 4 * s] = x[b][s];
+    for (int s = 0; s < 4; ++s) a[16 * wave + li][16 * b + 4 * s + lk] = x[b][s];
+  __syncthreads();
+  double* const Rw = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave) * lda + 2 * lane;
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    *reinterpret_cast<double2*>(Rw + (int64_t)r * lda) = make_double2(a[16 * wave + r][2 * lane], a[16 * wave + r][2 * lane + 1]);
 }
 
 // After the factorisation, one workgroup per 128x128 diagonal block: the strict

@@ -14,6 +14,14 @@ namespace {
 
 constexpr int PW = 32;  // edge of the diagonal blocks inverted in the first stage of lds_trtri
 
+// 1/sqrt(x) for a positive normal x: the hardware estimate refined by one
+// third-order step, t (1 + e/2 + 3e^2/8) with e = 1 - x t^2 (no special cases)
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double t = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * t, t, 1.0);
+  return fma(t * e, fma(e, 0.375, 0.5), t);
+}
+
 // broadcast a double from a wave-uniform lane
 __device__ __forceinline__ double lane_bcast(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -134,7 +142,9 @@ __device__ void lds_trtri(double (*a)[NB + 1], int tid) {
 //      below (48 per wave) and are eliminated in the same steps.  The factored panel
 //      goes to LDS;
 //   3. each wave subtracts the panel's rank-16 product from its own blocks right of
-//      the panel, four independent MFMAs per block, operands from LDS.
+//      the panel, four independent MFMAs per block, operands from LDS.  (Spreading
+//      these MFMAs over the next panel's pivot steps does not hide them: the pivot
+//      chain then ran twice as long.)
 // The broadcasts grow with the square of the panel width, the update rounds only
 // linearly with the number of panels, which is why the panels are narrow.
 // Elements above the diagonal are never read as data.
@@ -177,9 +187,13 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
     __syncthreads();
     const int row = (lane < PF) ? c0 + lane : c0 + PF + wave * (64 - PF) + (lane - PF);
     const bool valid = row < NB;
+    const int lrow = valid ? row : NB - 1;  // in-bounds row for the unconditional loads
     double v[PF];
 #pragma unroll
-    for (int q = 0; q < PF; ++q) v[q] = valid ? a[row][c0 + q] : 0.0;
+    for (int q = 0; q < PF; ++q) {
+      const double t = a[lrow][c0 + q];
+      v[q] = valid ? t : 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       // column j of the block rows, unscaled, as uniform values (readlane): they do
@@ -190,7 +204,8 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
       const double piv = u[j];
       const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
       if (!ok && fail < 0) fail = c0 + j;
-      const double r = rsqrt(ok ? piv : 1.0);
+      // a failed pivot gives garbage here, and the panel is abandoned below
+      const double r = rsqrt_pos(piv);
       // L[row][j] L[c][j] = v[j] u[c] / piv
       const double y = v[j] * (r * r);
       v[j] = v[j] * r;  // lane j: sqrt(piv); rows below: L[row][j]
