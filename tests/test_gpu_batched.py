@@ -112,3 +112,21 @@ def test_line_search_width_invariant(g, t_floor):
                 (b.status, b.iterations, b.ls_trials, b.fallback_steps), width
             assert np.array_equal(to_host(a.A), to_host(b.A)), width
             assert np.array_equal(to_host(a.W), to_host(b.W)), width
+
+
+def test_batch_of_many_backtracking_problems_bitwise(g):
+    """Eight backtracking problems at n = 1100 (padded 1152, nine leaf steps, 32
+    trial slots per round) solved as one batch and one by one: bitwise the same
+    results, iteration and trial counts."""
+    S, _ = synth.random_sparse_problem(1100, 550, 7)
+    lm = synth.lambda_max(S)
+    lams = [lm * f for f in (0.3, 0.2, 0.15, 0.1, 0.08, 0.06, 0.05, 0.04)]
+    St = to_dev(S)
+    batch = g.Solver().solve_batched(St, lams, 1e-6)
+    for lam, rb in zip(lams, batch):
+        r1 = g.Solver().solve(St, lam, 1e-6)
+        assert rb.status == r1.status == g.CONVERGED
+        assert (rb.iterations, rb.ls_trials) == (r1.iterations, r1.ls_trials)
+        assert np.array_equal(to_host(rb.A), to_host(r1.A))
+        assert np.array_equal(to_host(rb.W), to_host(r1.W))
+    assert sum(r.ls_trials for r in batch) > sum(r.iterations for r in batch)
