@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--no-fp64-ref", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--path-only", action="store_true",
+                    help="run only the regularisation-path measurement and print its object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run 3 plain device copies of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -282,6 +284,9 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.path_only:
+        print(json.dumps({"batched": bench_path(g, torch, dev)}), flush=True)
+        return
     if args.copy_calibration:
         x = torch.ones(args.copy_calibration * 2**20 // 8, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
