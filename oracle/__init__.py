@@ -13,6 +13,7 @@ Sec. 5) is parity unpinned: the GPU estimates cond(A) by power iteration while
 this oracle computes it exactly; the final solution stays pinned by KKT.
 """
 from .reference import (  # noqa: F401
+    empirical_covariance,
     initial_iterate,
     cholesky_or_none,
     logdet_from_cholesky,

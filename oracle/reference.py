@@ -35,6 +35,18 @@ MAX_ITER = 1
 LS_FAILED = 2
 
 
+# --------------------------------------------------------------------------- input
+def empirical_covariance(Y: np.ndarray, center: bool = True) -> np.ndarray:
+    """S = (1/m) sum_i (y_i - mu)(y_i - mu)^T with mu = (1/m) sum_i y_i, the samples
+    y_i being the m rows of Y (Sec. 2.1, eq. empirical_cov).  center=False takes
+    mu = 0, for samples whose mean is known to be zero."""
+    Y = np.asarray(Y, dtype=np.float64)
+    m = Y.shape[0]
+    mu = Y.sum(axis=0) / m if center else np.zeros(Y.shape[1])
+    Yc = Y - mu[None, :]
+    return (Yc.T @ Yc) / m
+
+
 # --------------------------------------------------------------------------- basics
 def initial_iterate(S: np.ndarray, lam: float) -> np.ndarray:
     """A^(0) = diag(1 / (S_ii + lam)): the G-ISTA initialisation used in Sec. 5."""

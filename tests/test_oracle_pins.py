@@ -24,6 +24,35 @@ def test_soft_threshold_edges():
     assert oracle.soft_threshold(np.array([0.3]), 0.3)[0] == 0.0
 
 
+# ------------------------------------------------------------------ eq. empirical_cov
+def test_empirical_covariance_worked_example():
+    """Three samples on a line: mu = (3, 6), centred rows (-2, -4), (0, 0), (2, 4),
+    so S = (1/3) [[8, 16], [16, 32]]; without centring S = (1/3) Y^T Y by hand."""
+    Y = np.array([[1.0, 2.0], [3.0, 6.0], [5.0, 10.0]])
+    np.testing.assert_allclose(oracle.empirical_covariance(Y), np.array([[8.0, 16.0], [16.0, 32.0]]) / 3,
+                               rtol=1e-15)
+    np.testing.assert_allclose(oracle.empirical_covariance(Y, center=False),
+                               np.array([[35.0, 70.0], [70.0, 140.0]]) / 3, rtol=1e-15)
+
+
+def test_empirical_covariance_library_and_invariants():
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((40, 7)) @ rng.standard_normal((7, 7)) + 3.0
+    S = oracle.empirical_covariance(Y)
+    # the library's biased (1/m) sample covariance
+    np.testing.assert_allclose(S, np.cov(Y, rowvar=False, bias=True), rtol=1e-12, atol=1e-12)
+    # centring removes any common shift of the samples; S is symmetric PSD
+    np.testing.assert_allclose(oracle.empirical_covariance(Y + rng.standard_normal(7)[None, :]), S,
+                               rtol=1e-10, atol=1e-10)
+    assert np.array_equal(S, S.T) and np.linalg.eigvalsh(S).min() > -1e-12
+    # samples of exactly zero mean (each with its negation): both forms agree
+    Z = np.vstack([Y - Y.mean(axis=0), -(Y - Y.mean(axis=0))])
+    np.testing.assert_allclose(oracle.empirical_covariance(Z), oracle.empirical_covariance(Z, center=False),
+                               rtol=1e-12, atol=1e-12)
+    # one sample: zero covariance once centred
+    assert np.all(oracle.empirical_covariance(Y[:1]) == 0.0)
+
+
 # ------------------------------------------------------------------ closed forms
 def test_n1_closed_form():
     for s, lam in [(0.5, 0.1), (2.0, 0.7), (1e-3, 1.0)]:
