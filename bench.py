@@ -176,6 +176,29 @@ def bench_path(g, torch, dev):
     return out
 
 
+def bench_covariance(g, torch, dev, m=5000, n=10000, reps=5):
+    """The solver's input on the device: S = (1/m) sum (y - mu)(y - mu)^T from m
+    samples of n variables (the chain workload's sample shape), FP64 MFMA."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    Y = torch.randn((m, n), dtype=torch.float64, device=dev, generator=gen)
+    s = g.Solver()
+    s.covariance(Y)  # warmup (and workspace)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        s.covariance(Y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    s.close()
+    flops = float(m) * n * (n + 1)  # n (n + 1) / 2 entries, m multiply-adds each
+    tf = flops / dt / 1e12
+    log(f"[bench] covariance m={m} n={n}: {dt * 1e3:.2f} ms ({tf:.1f} TFLOP/s)")
+    return {"workload": f"sample covariance, m={m} samples of n={n} variables, centred, FP64",
+            "ms": dt * 1e3, "achieved_tflops": tf, "peak_tflops": PEAK_TFLOPS["fp64"],
+            "frac": tf / PEAK_TFLOPS["fp64"]}
+
+
 def bench_small(g, torch, dev, count=1024):
     """Many uneven-n small problems in one persistent launch (glasso_solve_small)."""
     import numpy as np
@@ -375,6 +398,7 @@ def main():
                      "frac": achieved / peak, "traffic": TRAFFIC_BYTES[args.precision], "traffic_unit": "B", "kernel": kernel,
                      "avg_launch_ms": avg_launch_s * 1000.0, "launches": launches},
     }
+    line["covariance"] = bench_covariance(g, torch, dev)
     if not args.no_path:
         line["batched"] = bench_path(g, torch, dev)
     if not args.no_serve:

@@ -188,6 +188,17 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
  * on its own.  They use the handle's workspace and synchronise the stream.
  * -------------------------------------------------------------------------- */
 
+/* Sample covariance, the solver's input (Sec. 2.1, eq. empirical_cov):
+ * S = (1/m) sum_i (y_i - mu)(y_i - mu)^T over the m samples y_i, the rows of Y
+ * (device, m x n, row-major, ld n), with mu = (1/m) sum_i y_i when center != 0
+ * and mu = 0 otherwise (samples of known zero mean).  S (device, n x n, full
+ * symmetric) is formed as the lower triangle of one FP64 MFMA product and
+ * mirrored.  The handle keeps a workspace of (m + n) x n + n doubles (rounded up
+ * to whole tiles) for the padded samples and product; it is freed with the handle.
+ * Errors: INVALID_ARG for null pointers, m < 1 or n < 1; OOM. */
+glasso_err glasso_covariance(glasso_handle h, const double* Y, int64_t m, int64_t n, int center, double* S,
+                             void* stream);
+
 /* Lower Cholesky factor L of SPD A (the PD test of condition t_cond_pd,
  * Sec. 3.3.2): L (n x n, output) gets L in its lower triangle and zeros above.
  * *info = 0 on success, else the 1-based column of the first non-positive or

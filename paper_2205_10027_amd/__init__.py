@@ -195,6 +195,16 @@ class Solver:
         return out
 
     # ---------------------------------------------------------------- single steps
+    def covariance(self, Y: torch.Tensor, center: bool = True, stream=None) -> torch.Tensor:
+        """Sample covariance of the rows of Y (m x n, device FP64), eq. empirical_cov."""
+        if Y.dim() != 2:
+            raise ValueError(f"Y must be m x n, got {tuple(Y.shape)}")
+        m, n = Y.shape
+        S = torch.empty((n, n), dtype=torch.float64, device=Y.device)
+        _check(_lib.glasso_covariance(self._h, _dev(Y, "Y"), m, n, int(bool(center)), S.data_ptr(),
+                                      _stream(stream)), "glasso_covariance")
+        return S
+
     def cholesky(self, A: torch.Tensor, stream=None):
         n = _square(A, "A")
         L = torch.empty_like(A)

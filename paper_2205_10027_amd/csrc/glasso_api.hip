@@ -133,6 +133,8 @@ struct glasso_handle_s {
   Graphs graphs;
   void* small_base = nullptr;  // workspace of the persistent small-problem solver
   size_t small_bytes = 0;
+  void* cov_base = nullptr;  // workspace of glasso_covariance (padded samples, padded S, means)
+  size_t cov_bytes = 0;
 };
 
 namespace {
@@ -1018,6 +1020,7 @@ glasso_err glasso_destroy(glasso_handle h) {
   drop_graphs(h->graphs);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->small_base) (void)hipFree(h->small_base);
+  if (h->cov_base) (void)hipFree(h->cov_base);
   if (h->ws.base) (void)hipFree(h->ws.base);
   free_host(h->hm);
   for (auto& e : h->ev)
@@ -1187,6 +1190,36 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
 }
 
 // ------------------------------------------------------------------ step-level entry points
+glasso_err glasso_covariance(glasso_handle h, const double* Y, int64_t m, int64_t n, int center, double* S,
+                             void* stream) {
+  if (!h || !Y || !S || m < 1 || n < 1 || n > (1 << 20) || m > ((int64_t)1 << 31) - 16) return GLASSO_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = pad_to_tile(n);
+  const int64_t mp = (m + 15) / 16 * 16;  // K of the product, padded with zero samples
+  const size_t bytes = ((size_t)mp * np + (size_t)np * np + (size_t)np) * sizeof(double);
+  if (bytes > h->cov_bytes) {
+    if (h->cov_base) (void)hipFree(h->cov_base);
+    h->cov_base = nullptr;
+    h->cov_bytes = 0;
+    if (hipMalloc(&h->cov_base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return GLASSO_ERR_OOM;
+    }
+    h->cov_bytes = bytes;
+  }
+  double* Yp = static_cast<double*>(h->cov_base);
+  double* Sp = Yp + mp * np;
+  double* mu = Sp + np * np;
+  if (center) K_TRY(column_mean(st, Y, m, n, mu));
+  K_TRY(center_pad(st, Y, m, n, center ? mu : nullptr, Yp, mp, np));
+  // lower triangle of (1/m) Yp^T Yp on FP64 MFMA, then mirrored into the n x n output
+  // (op(A) = op(B) = the columns of Yp: both operands read transposed)
+  K_TRY(gemm_f64(st, 1, 1, (int)np, (int)np, (int)mp, 1.0 / (double)m, Yp, np, Yp, np, 0.0, Sp, np, 1, 0, 0, nullptr));
+  K_TRY(sym_copy_out(st, Sp, np, S, n, 1));
+  HIP_TRY(hipStreamSynchronize(st));
+  return GLASSO_OK;
+}
+
 glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* L, int64_t* info, double* logdet,
                            void* stream) {
   if (!h || !A || !L || n < 1) return GLASSO_ERR_INVALID_ARG;

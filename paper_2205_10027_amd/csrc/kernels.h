@@ -147,6 +147,11 @@ int accept_trials(hipStream_t stream, const int* accept, int count, double* A, c
                   double* L, const double* Lt, double* dL, const double* dLt, int64_t np);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
+// sample covariance (eq. empirical_cov): column means of Y (m x n row-major) into mu;
+// Yp (mp x np) = Y - 1 mu^T with zero padding (mu may be null: no centring)
+int column_mean(hipStream_t stream, const double* Y, int64_t m, int64_t n, double* mu);
+int center_pad(hipStream_t stream, const double* Y, int64_t m, int64_t n, const double* mu, double* Yp, int64_t mp,
+               int64_t np);
 // ---- persistent small-problem solver (n <= SMALL_MAX_N, one workgroup per problem)
 constexpr int SMALL_MAX_N = 64;
 constexpr int GLASSO_CONVERGED_DEV = 0, GLASSO_MAX_ITER_DEV = 1, GLASSO_LS_FAILED_DEV = 2;  // glasso_status

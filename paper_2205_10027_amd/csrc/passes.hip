@@ -495,6 +495,36 @@ __global__ __launch_bounds__(256) void normalize_kernel(const double* __restrict
   if (threadIdx.x == 0 && out) *out = nrm;
 }
 
+// ------------------------------------------------------------------ sample covariance
+// Column means of Y (m x n, row-major: one sample per row), eq. empirical_cov: one
+// workgroup per 64 columns, lane = column, the four waves summing every fourth row,
+// then their partial sums in a fixed order.
+__global__ __launch_bounds__(256) void column_mean_kernel(const double* __restrict__ Y, int64_t m, int64_t n,
+                                                          double* __restrict__ mu) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  double s = 0.0;
+  if (j < n)
+    for (int64_t i = wave; i < m; i += 4) s += Y[i * n + j];
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && j < n) mu[j] = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) / (double)m;
+}
+
+// Yp (mp x np) = Y - 1 mu^T (mu null: Y itself), zeros in the padding rows and columns
+__global__ __launch_bounds__(256) void center_pad_kernel(const double* __restrict__ Y, int64_t m, int64_t n,
+                                                         const double* __restrict__ mu, double* __restrict__ Yp,
+                                                         int64_t mp, int64_t np) {
+  const int64_t total = mp * np;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / np, j = e - i * np;
+    double v = 0.0;
+    if (i < m && j < n) v = mu ? Y[i * n + j] - mu[j] : Y[i * n + j];
+    Yp[e] = v;
+  }
+}
+
 // Accept trial slot j = accept[b] - 1 of every problem b with accept[b] != 0:
 // A_b <- At_j, L_b <- Lt_j (np x np each), dL_b <- dLt_j (np).
 __global__ void accept_kernel(const int* accept, double* A, const double* At, double* L, const double* Lt,
@@ -513,6 +543,18 @@ __global__ void accept_kernel(const int* accept, double* A, const double* At, do
 }
 
 }  // namespace
+
+int column_mean(hipStream_t stream, const double* Y, int64_t m, int64_t n, double* mu) {
+  hipLaunchKernelGGL(column_mean_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, stream, Y, m, n, mu);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int center_pad(hipStream_t stream, const double* Y, int64_t m, int64_t n, const double* mu, double* Yp, int64_t mp,
+               int64_t np) {
+  const int blocks = (int)std::min<int64_t>((mp * np + 255) / 256, 16384);
+  hipLaunchKernelGGL(center_pad_kernel, dim3(blocks), dim3(256), 0, stream, Y, m, n, mu, Yp, mp, np);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At, double* L,
                   const double* Lt, double* dL, const double* dLt, int64_t np) {
