@@ -233,7 +233,9 @@ def bench_small(g, torch, dev, count=1024):
 
 
 def bench_serve(g, count, seed=0, precision="bf16x3"):
-    """Serving: closed-loop capacity, then Poisson replays at 0.5, 0.8, 1.0 x capacity."""
+    """Serving: every request brings its m = n/2 samples; closed-loop capacity, then
+    Poisson replays at 0.5, 0.8, 1.0 x capacity.  The same requests bringing their
+    S instead (twice the upload, no covariance step) are timed closed-loop beside."""
     import numpy as np
 
     import synth
@@ -243,33 +245,41 @@ def bench_serve(g, count, seed=0, precision="bf16x3"):
     base = synth.serving_requests(count, seed, rate=1.0)
     problems = []
     for (_, n, rs) in base:
-        S, _ = synth.random_sparse_problem(n, n // 2, rs)
-        problems.append((n, S, 0.3 * synth.lambda_max(S)))
+        X, _ = synth.random_sparse_samples(n, n // 2, rs)
+        S = synth.sample_covariance(X)
+        problems.append((n, np.ascontiguousarray(X.T), S, 0.3 * synth.lambda_max(S)))
     log(f"[bench] serving: generated {count} requests in {time.perf_counter() - t:.1f}s")
     slots = 4
     budget = 64 * 2**30
     eng = GpuEngine(slots=slots, precision=precision, tol=1e-5)
+    fp = lambda n: gpu_footprint(n, precision, m=n // 2)  # noqa: E731
 
-    def requests(rate):
+    def requests(rate, samples=True):
         arr = [a / rate for (a, _, _) in base] if rate else [0.0] * count
-        return [Request(i, arr[i], n, S, lam) for i, (n, S, lam) in enumerate(problems)]
+        return [Request(i, arr[i], n, None if samples else S, lam, Y=Y if samples else None)
+                for i, (n, Y, S, lam) in enumerate(problems)]
 
-    srv = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint)
+    srv = Server(eng, slots=slots, hbm_budget=budget, footprint=fp)
     # warmup: one pass over every request, so that the first use of each padded size
     # (tile autotuning, workspace growth of each slot's handle) is not timed
     srv.run(requests(None), realtime=False)
     st = srv.run(requests(None), realtime=False)
     capacity = st.solves_per_s
     log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
-    serial = Server(eng, slots=1, hbm_budget=budget, footprint=gpu_footprint).run(requests(None), realtime=False)
+    serial = Server(eng, slots=1, hbm_budget=budget, footprint=fp).run(requests(None), realtime=False)
     log(f"[bench] serving one slot: {serial.solves_per_s:.2f} solves/s")
-    out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2, lambda=0.3 lambda_max, "
-                       f"random sparse, {precision} form, tol 1e-5, {slots} slots, HBM budget {budget >> 30} GiB",
+    from_s = Server(eng, slots=slots, hbm_budget=budget, footprint=lambda n: gpu_footprint(n, precision)).run(
+        requests(None, samples=False), realtime=False)
+    log(f"[bench] serving closed loop, requests bringing S: {from_s.solves_per_s:.2f} solves/s")
+    out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2 samples each (S formed on the "
+                       f"device), lambda=0.3 lambda_max, random sparse, {precision} form, tol 1e-5, {slots} slots, "
+                       f"HBM budget {budget >> 30} GiB",
            "closed_loop_solves_per_s": capacity, "one_slot_solves_per_s": serial.solves_per_s,
-           "speedup_vs_one_slot": capacity / serial.solves_per_s, "rates": {}}
+           "speedup_vs_one_slot": capacity / serial.solves_per_s,
+           "closed_loop_solves_per_s_requests_bringing_S": from_s.solves_per_s, "rates": {}}
     for frac in (0.5, 0.8, 1.0):
         rate = frac * capacity
-        st = Server(eng, slots=slots, hbm_budget=budget, footprint=gpu_footprint).run(requests(rate))
+        st = Server(eng, slots=slots, hbm_budget=budget, footprint=fp).run(requests(rate))
         out["rates"][f"{frac:.1f}x"] = {"arrival_rate_per_s": rate, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
                                         "solves_per_s": st.solves_per_s, "mean_in_flight": st.mean_active,
                                         "peak_hbm_gib": st.peak_bytes / 2**30}

@@ -4,10 +4,13 @@ Requests arrive over time (e.g. a Poisson stream).  A dispatcher admits the
 oldest waiting request that fits into a free slot and into the HBM budget
 (first fit over the queue, so one large request does not block smaller ones);
 each slot is a worker with its own libglasso handle and HIP stream, so the
-work of all admitted requests overlaps on the device.  A request holds its S,
-A and W on the device for its whole solve; its footprint is the solver
-workspace (glasso_workspace_size) plus those three matrices, and it is released
-when the request finishes.  Latency is measured from arrival to the result.
+work of all admitted requests overlaps on the device.  A request brings either
+its sample covariance S or its samples Y (m x n, known zero mean), from which
+the slot forms S on the device (glasso_covariance): half the upload at m = n/2.
+A request holds its S, A and W (and samples) on the device for its whole solve;
+its footprint is the solver workspace (glasso_workspace_size) plus those
+matrices and, for samples, the covariance workspace, released when the request
+finishes.  Latency is measured from arrival to the result.
 
 The engine and the footprint function are injectable so the scheduler can run
 on the CPU with a stand-in engine.
@@ -27,7 +30,7 @@ class Request:
     rid: int
     arrival: float          # seconds, relative to the start of the run
     n: int
-    S: np.ndarray           # host FP64 (pinned when given as a torch tensor)
+    S: np.ndarray | None    # host FP64 (pinned when given as a torch tensor), or None with Y
     lam: float
     admitted: float = -1.0
     finished: float = -1.0
@@ -35,6 +38,7 @@ class Request:
     result: object = None
     error: str | None = None
     footprint: int = 0
+    Y: np.ndarray | None = None  # host FP64 samples (m x n, rows), used when S is None
 
     @property
     def latency(self) -> float:
@@ -68,11 +72,17 @@ class Stats:
         return self.count / self.makespan_s if self.makespan_s > 0 else float("nan")
 
 
-def gpu_footprint(n: int, precision: str = "bf16x3") -> int:
-    """Device bytes a request of size n holds while it runs."""
+def gpu_footprint(n: int, precision: str = "bf16x3", m: int | None = None) -> int:
+    """Device bytes a request of size n holds while it runs; with m, a request that
+    brings m samples (their upload and the covariance workspace included)."""
     import paper_2205_10027_amd as g
 
-    return g.workspace_bytes(n, precision) + 3 * n * n * 8
+    b = g.workspace_bytes(n, precision) + 3 * n * n * 8
+    if m is not None:
+        npad = -(-n // 128) * 128
+        mpad = -(-m // 16) * 16
+        b += m * n * 8 + (mpad * npad + npad * npad + npad) * 8
+    return b
 
 
 class GpuEngine:
@@ -93,11 +103,14 @@ class GpuEngine:
         torch = self.torch
         st = self.streams[slot]
         with torch.cuda.stream(st):
-            S = req.S
-            if not isinstance(S, torch.Tensor):
-                S = torch.from_numpy(S)
-            # blocking upload: the solve must not read S before the copy has landed
-            Sd = S.to(self.device)
+            if req.S is None:
+                Y = req.Y if isinstance(req.Y, torch.Tensor) else torch.from_numpy(req.Y)
+                # blocking upload, then S on the device from the samples
+                Sd = self.solvers[slot].covariance(Y.to(self.device), center=False, stream=st)
+            else:
+                S = req.S if isinstance(req.S, torch.Tensor) else torch.from_numpy(req.S)
+                # blocking upload: the solve must not read S before the copy has landed
+                Sd = S.to(self.device)
             res = self.solvers[slot].solve(Sd, req.lam, self.tol, want_W=True, stream=st)
         st.synchronize()
         return res

@@ -10,6 +10,7 @@ from .generators import (  # noqa: F401
     sample_covariance,
     chain_problem,
     random_sparse_problem,
+    random_sparse_samples,
     lambda_max,
     lambda_path,
     serving_requests,

@@ -95,12 +95,18 @@ def chain_problem(n: int, m: int, seed: int, diag: float = 1.25, off: float = -0
     return sample_covariance(X), chain_precision(n, diag, off)
 
 
-def random_sparse_problem(n: int, m: int, seed: int):
-    """(S, A_true) for the random-sparse recipe.  The precision structure and the
-    samples come from two streams derived from the same seed."""
+def random_sparse_samples(n: int, m: int, seed: int):
+    """(X, A_true) for the random-sparse recipe: X (n x m) holds the m samples as
+    columns.  The precision structure and the samples come from two streams
+    derived from the same seed."""
     A_true = random_sparse_precision(n, seed)
     rng = _rng(seed + 1_000_003)
-    X = _samples_dense(A_true, m, rng)
+    return _samples_dense(A_true, m, rng), A_true
+
+
+def random_sparse_problem(n: int, m: int, seed: int):
+    """(S, A_true) for the random-sparse recipe (S from random_sparse_samples)."""
+    X, A_true = random_sparse_samples(n, m, seed)
     return sample_covariance(X), A_true
 
 

@@ -68,3 +68,34 @@ def test_fresh_handle_on_nonblocking_stream_while_null_stream_busy():
         assert np.array_equal(to_host(r.A), to_host(ref.A))
         s.close()
     del c
+
+
+def test_mix_equals_alone_from_samples():
+    """Requests that bring their samples instead of S: each slot forms S on the
+    device (glasso_covariance) and solves; every result equals the same request
+    formed and solved alone, and meets the KKT bar on the S it was solved for."""
+    device()
+    import paper_2205_10027_amd as g
+    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_footprint
+
+    specs = [(64, 31), (300, 32), (130, 33), (700, 34), (90, 35), (257, 36)]
+    reqs = []
+    for i, (n, seed) in enumerate(specs):
+        X, _ = synth.random_sparse_samples(n, n // 2, seed)
+        lam = 0.3 * synth.lambda_max(synth.sample_covariance(X))
+        reqs.append(Request(i, 0.002 * i, n, None, lam, Y=np.ascontiguousarray(X.T)))
+    eng = GpuEngine(slots=3, tol=1e-5)
+    fp = lambda n: gpu_footprint(n, "bf16x3", m=n // 2)  # noqa: E731
+    srv = Server(eng, slots=3, hbm_budget=sum(fp(n) for n, _ in specs[:4]), footprint=fp)
+    st = srv.run(reqs)
+    assert st.count == len(reqs)
+    alone_solver = g.Solver(precision="bf16x3")
+    for r in reqs:
+        assert r.error is None, r.error
+        S = alone_solver.covariance(to_dev(r.Y), center=False)
+        alone = alone_solver.solve(S, r.lam, 1e-5)
+        assert r.result.status == alone.status == g.CONVERGED
+        assert np.array_equal(to_host(r.result.A), to_host(alone.A))
+        chk = oracle.check_solution(to_host(S), to_host(r.result.A), r.lam)
+        assert chk["kkt_rel1"] <= 1e-5 * 1.0001
+    eng.close()
