@@ -11,6 +11,8 @@ from .generators import (  # noqa: F401
     chain_problem,
     random_sparse_problem,
     random_sparse_samples,
+    planar_precision,
+    support_samples,
     lambda_max,
     lambda_path,
     serving_requests,

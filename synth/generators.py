@@ -95,6 +95,33 @@ def chain_problem(n: int, m: int, seed: int, diag: float = 1.25, off: float = -0
     return sample_covariance(X), chain_precision(n, diag, off)
 
 
+def planar_precision(n: int, seed: int, shift: float = 0.1) -> np.ndarray:
+    """Planar-graph precision (Sec. 5.1.1): the graph Laplacian of a Delaunay
+    triangulation of n uniform points in the unit square (A_ij = -1 on edges,
+    A_ii = degree) plus shift * I.  The Laplacian's smallest eigenvalue is 0, so
+    the paper's diagonal term max(-1.2 lambda_min, 0.1) is 0.1."""
+    from scipy.spatial import Delaunay
+
+    rng = _rng(seed)
+    pts = rng.uniform(size=(n, 2))
+    A = np.zeros((n, n))
+    for a, b, c in Delaunay(pts).simplices:
+        for i, j in ((a, b), (b, c), (a, c)):
+            A[i, j] = A[j, i] = -1.0
+    A[np.arange(n), np.arange(n)] = -A.sum(axis=1) + shift
+    return A
+
+
+def support_samples(kind: str, n: int, m: int, seed: int):
+    """(X, A_true) with X (n x m) the m samples as columns, for the ground truths
+    of the support-recovery sweep: "chain" (chain_precision), "random"
+    (random_sparse_precision) and "planar" (planar_precision)."""
+    if kind == "chain":
+        return _samples_chain(n, m, _rng(seed + 1_000_003), 1.25, -0.5), chain_precision(n)
+    A_true = random_sparse_precision(n, seed) if kind == "random" else planar_precision(n, seed)
+    return _samples_dense(A_true, m, _rng(seed + 1_000_003)), A_true
+
+
 def random_sparse_samples(n: int, m: int, seed: int):
     """(X, A_true) for the random-sparse recipe: X (n x m) holds the m samples as
     columns.  The precision structure and the samples come from two streams
