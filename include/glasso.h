@@ -87,7 +87,8 @@ typedef struct {
                       succeeds is taken, so the accepted steps, iterations and ls_trials
                       are the same for every width.  Each unit of width holds one more
                       trial point and factor (2 n^2 doubles) per problem.  0 (default):
-                      4 for n <= 2048, 1 above; else 1 .. 16. */
+                      4 for n <= 2048 (1 when that workspace does not fit in device
+                      memory), 1 above; else 1 .. 16. */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)

@@ -545,10 +545,16 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   const int64_t np = pad_to_tile(n);
   // line-search width: trial slots per problem (several step sizes of the
   // backtracking sequence per round while one round is launch-latency bound)
-  const int K = o.ls_width > 0 ? o.ls_width : ls_width(np);
-  const int slots = count * K;
-  glasso_err e = ensure_workspace(h, count, np, st, slots);
+  int K = o.ls_width > 0 ? o.ls_width : ls_width(np);
+  glasso_err e = ensure_workspace(h, count, np, st, count * K);
+  if (e == GLASSO_ERR_OOM && o.ls_width == 0 && K > 1) {
+    // the automatic width falls back to one step size per round when the extra
+    // trial slots do not fit in device memory
+    K = 1;
+    e = ensure_workspace(h, count, np, st, count);
+  }
   if (e) return e;
+  const int slots = count * K;
   e = apply_tile_policy(h, st, o.precision);
   if (e) return e;
   Workspace& w = h->ws;

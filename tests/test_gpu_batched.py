@@ -130,3 +130,30 @@ def test_batch_of_many_backtracking_problems_bitwise(g):
         assert np.array_equal(to_host(rb.A), to_host(r1.A))
         assert np.array_equal(to_host(rb.W), to_host(r1.W))
     assert sum(r.ls_trials for r in batch) > sum(r.iterations for r in batch)
+
+
+def test_wide_line_search_falls_back_when_memory_is_short(g):
+    """A batch sized so that the automatic four trial slots per problem cannot fit
+    in the free device memory but one slot can: the solve still runs (one step size
+    per round) and gives the bits of the same problems solved one by one."""
+    import torch
+
+    n, np_ = 2048, 2048
+    free, _ = torch.cuda.mem_get_info()
+    per1 = (9 * 8 + 1) * np_ * np_ + 4 * np_ * 128 * 8 + 8 * n * n  # workspace at width 1 + the output A
+    count = int(0.75 * free // per1)
+    per4 = per1 + 6 * 8 * np_ * np_
+    assert count * per4 > free  # width 4 does not fit
+    S, _ = synth.random_sparse_problem(n, n // 2, 9)
+    lam = 0.3 * synth.lambda_max(S)
+    St = to_dev(S)
+    s = g.Solver(max_iter=2)
+    res = s.solve_batched(St, [lam] * count, 1e-5, want_W=False)
+    assert len(res) == count
+    one = g.Solver(max_iter=2).solve(St, lam, 1e-5, want_W=False)
+    for r in (res[0], res[-1]):
+        assert (r.status, r.iterations, r.ls_trials) == (one.status, one.iterations, one.ls_trials)
+        assert np.array_equal(to_host(r.A), to_host(one.A))
+    s.close()
+    del res
+    torch.cuda.empty_cache()
