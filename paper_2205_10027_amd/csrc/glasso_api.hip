@@ -1129,8 +1129,8 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   const size_t ws_bytes = (size_t)grid * SMALL_WS_DOUBLES * sizeof(double);
   const size_t gm_bytes = (size_t)grid * SMALL_GM_BYTES;
   const size_t pr_bytes = ((size_t)count * sizeof(SmallProblem) + 255) / 256 * 256;
-  const size_t out_bytes = (size_t)count * sizeof(SmallOut);
-  const size_t bytes = ws_bytes + gm_bytes + pr_bytes + out_bytes;
+  const size_t out_bytes = ((size_t)count * sizeof(SmallOut) + 255) / 256 * 256;
+  const size_t bytes = ws_bytes + gm_bytes + pr_bytes + out_bytes + 256;  // + the work-queue counter
   if (bytes > h->small_bytes) {
     if (h->small_base) (void)hipFree(h->small_base);
     h->small_base = nullptr;
@@ -1157,6 +1157,7 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   SmallOut* dout = reinterpret_cast<SmallOut*>(base + ws_bytes + gm_bytes + pr_bytes);
   p.prob = dpr;
   p.out = dout;
+  p.next = reinterpret_cast<int*>(base + ws_bytes + gm_bytes + pr_bytes + out_bytes);
   p.count = count;
   const glasso_options& o = h->opt;
   p.tol = tol;
@@ -1169,7 +1170,7 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   HIP_TRY(hipMemcpyAsync(dpr, pr.data(), (size_t)count * sizeof(SmallProblem), hipMemcpyHostToDevice, st));
   K_TRY(solve_small(st, p, grid));
   std::vector<SmallOut> out(count);
-  HIP_TRY(hipMemcpyAsync(out.data(), dout, out_bytes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(out.data(), dout, (size_t)count * sizeof(SmallOut), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const double total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   glasso_err err = GLASSO_OK;

@@ -174,6 +174,7 @@ struct SmallParams {
   int count;
   double* ws;  // per workgroup: 6 x 64 x 64 doubles (S, A, At, W, Z, P)
   int8_t* gm;  // per workgroup: 64 x 64
+  int* next;   // work queue: the next problem index to take (set to the grid size by solve_small)
   double tol, t0, shrink, t_floor, t_min;
   int max_iter, warm_start;
 };

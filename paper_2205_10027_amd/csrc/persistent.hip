@@ -1,6 +1,8 @@
 // Persistent solver for many small problems in one launch (n <= 64 each, sizes
-// may differ).  Each workgroup takes problems blockIdx.x, blockIdx.x + gridDim.x,
-// ... and runs the whole of Alg. 1 (Sec. 5 settings) for each on the device:
+// may differ).  Each workgroup starts with problem blockIdx.x and then takes the
+// next untaken problem from a work queue (one atomic counter) until none is left,
+// so problems that need many iterations do not hold up a fixed share of the
+// others.  It runs the whole of Alg. 1 (Sec. 5 settings) for each on the device:
 // factor, inverse, gradient pass and stopping test, A Z A, the backtracking line
 // search with the cond-based fallback, and the accept step, with no host round
 // trip.  FP64 throughout, with the same per-element formulas as the blocked passes.
@@ -80,12 +82,23 @@ __device__ double power_lmax(const double* M, int n, double* x, double* y, doubl
   return nrm;
 }
 
+// the next problem of the queue, the same in every thread of the workgroup
+__device__ __forceinline__ int next_problem(int* next, int* slot, int tid) {
+  __syncthreads();
+  if (tid == 0) *slot = atomicAdd(next, 1);
+  __syncthreads();
+  return *slot;
+}
+
+__global__ void set_counter_kernel(int* next, int value) { *next = value; }
+
 __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
   __shared__ double a[SN][SLD];  // factor / inverse
   __shared__ double b[SN][SLD];  // A Z A operand
   __shared__ double dl[SN];      // diag of the factor of the current A
   __shared__ double xv[SN], yv[SN];
   __shared__ double sh[4];
+  __shared__ int taken;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* const S = p.ws + (int64_t)blockIdx.x * 6 * SNN;
   double* const A = S + SNN;
@@ -95,7 +108,7 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
   double* const P = Z + SNN;
   int8_t* const GM = p.gm + (int64_t)blockIdx.x * SNN;
 
-  for (int prob = blockIdx.x; prob < p.count; prob += gridDim.x) {
+  for (int prob = blockIdx.x; prob < p.count; prob = next_problem(p.next, &taken, tid)) {
     const SmallProblem pr = p.prob[prob];
     SmallOut o = {};
     const int n = (int)pr.n;
@@ -298,6 +311,7 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
 int solve_small(hipStream_t stream, const SmallParams& p, int grid) {
   if (p.count <= 0) return 0;
   if (grid <= 0) return -1;
+  hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(1), 0, stream, p.next, grid);
   hipLaunchKernelGGL(pista_small_kernel, dim3(grid), dim3(256), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
