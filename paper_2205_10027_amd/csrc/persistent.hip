@@ -101,9 +101,10 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
   __shared__ int taken;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* const S = p.ws + (int64_t)blockIdx.x * 6 * SNN;
-  double* const A = S + SNN;
-  double* const At = A + SNN;
-  double* const W = At + SNN;
+  // the current iterate and the trial point; an accepted trial exchanges the two
+  double* A = S + SNN;
+  double* At = A + SNN;
+  double* const W = S + 3 * SNN;
   double* const Z = W + SNN;
   double* const P = Z + SNN;
   int8_t* const GM = p.gm + (int64_t)blockIdx.x * SNN;
@@ -172,28 +173,42 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
         });
       }
       __syncthreads();
-      // a2: gradient pass over the lower triangle (weights 1 on, 2 off the diagonal)
+      // a2: gradient pass over the lower triangle (weights 1 on, 2 off the diagonal);
+      // all of a thread's elements are read and computed before any is stored, so
+      // the loads are not serialised behind stores the compiler cannot disambiguate
       double s_absz = 0.0, s_z2 = 0.0, m_absz = 0.0, s_absa = 0.0, s_nnz = 0.0, s_sa = 0.0;
-      for (int e = tid; e < SNN; e += 256) {
-        const int i = e / SN, j = e % SN;
-        if (j > i) continue;
-        double z = 0.0;
-        int8_t gm = 0;
-        if (i < n) {
-          const double av = A[e], s = S[e];
-          grad_element(av, s, W[e], lam, z, gm);
-          const double wgt = (i == j) ? 1.0 : 2.0;
-          s_absz += wgt * fabs(z);
-          s_z2 += wgt * (z * z);
-          m_absz = fmax(m_absz, fabs(z));
-          s_absa += wgt * fabs(av);
-          s_nnz += (av != 0.0) ? wgt : 0.0;
-          s_sa += wgt * (s * av);
+      constexpr int CH = 4;  // elements per chunk: e = tid + 256 k
+#pragma unroll 1
+      for (int k0 = 0; k0 < SNN / 256; k0 += CH) {
+        double zv[CH];
+        int8_t gv[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int e = tid + 256 * (k0 + k), i = e / SN, j = e % SN;
+          zv[k] = 0.0;
+          gv[k] = 0;
+          if (j <= i && i < n) {
+            const double av = A[e], s = S[e];
+            grad_element(av, s, W[e], lam, zv[k], gv[k]);
+            const double z = zv[k];
+            const double wgt = (i == j) ? 1.0 : 2.0;
+            s_absz += wgt * fabs(z);
+            s_z2 += wgt * (z * z);
+            m_absz = fmax(m_absz, fabs(z));
+            s_absa += wgt * fabs(av);
+            s_nnz += (av != 0.0) ? wgt : 0.0;
+            s_sa += wgt * (s * av);
+          }
         }
-        Z[e] = z;
-        Z[j * SN + i] = z;
-        GM[e] = gm;
-        GM[j * SN + i] = gm;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const int e = tid + 256 * (k0 + k), i = e / SN, j = e % SN;
+          if (j > i) continue;
+          Z[e] = zv[k];
+          Z[j * SN + i] = zv[k];
+          GM[e] = gv[k];
+          GM[j * SN + i] = gv[k];
+        }
       }
       const double sz = block_sum(s_absz, sh);
       const double sz2 = block_sum(s_z2, sh);
@@ -248,26 +263,39 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
         }
         if (t < p.t_min) break;
         double s_tr = 0.0, s_l1 = 0.0;
-        for (int e = tid; e < SNN; e += 256) {
-          const int i = e / SN, j = e % SN;
-          if (j > i) continue;
-          double at = 0.0;
-          if (i < n) {
-            const int8_t gm = GM[e];
-            if (gm != 0) {
-              const double av = A[e];
-              const double Cij = c_element(i == j, A[i * SN + i], A[j * SN + j], av, lam);
-              at = trial_element(av, P[e], Cij, (double)gm, t);
-              const double wgt = (i == j) ? 1.0 : 2.0;
-              s_tr += wgt * (S[e] * (at - av));
-              s_l1 += wgt * (fabs(at) - fabs(av));
+        constexpr int CHT = 4;
+#pragma unroll 1
+        for (int k0 = 0; k0 < SNN / 256; k0 += CHT) {
+          double atv[CHT];
+#pragma unroll
+          for (int k = 0; k < CHT; ++k) {
+            const int e = tid + 256 * (k0 + k), i = e / SN, j = e % SN;
+            double at = 0.0;
+            if (j <= i) {
+              if (i < n) {
+                const int8_t gm = GM[e];
+                if (gm != 0) {
+                  const double av = A[e];
+                  const double Cij = c_element(i == j, A[i * SN + i], A[j * SN + j], av, lam);
+                  at = trial_element(av, P[e], Cij, (double)gm, t);
+                  const double wgt = (i == j) ? 1.0 : 2.0;
+                  s_tr += wgt * (S[e] * (at - av));
+                  s_l1 += wgt * (fabs(at) - fabs(av));
+                }
+              } else {
+                at = (i == j) ? 1.0 : 0.0;
+              }
             }
-          } else {
-            at = (i == j) ? 1.0 : 0.0;
+            atv[k] = at;
           }
-          At[e] = at;
-          At[j * SN + i] = at;
-          a[i][j] = at;
+#pragma unroll
+          for (int k = 0; k < CHT; ++k) {
+            const int e = tid + 256 * (k0 + k), i = e / SN, j = e % SN;
+            if (j > i) continue;
+            At[e] = atv[k];
+            At[j * SN + i] = atv[k];
+            a[i][j] = atv[k];
+          }
         }
         const double dtr = block_sum(s_tr, sh);
         const double dl1 = block_sum(s_l1, sh);
@@ -280,8 +308,10 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
         }
         __syncthreads();
         if (ok) {
-          // a7: A <- At; the factor of At stays in a
-          for (int e = tid; e < SNN; e += 256) A[e] = At[e];
+          // a7: A <- At by exchanging the two buffers; the factor of At stays in a
+          double* const tmp = A;
+          A = At;
+          At = tmp;
           if (tid < SN) dl[tid] = a[tid][tid];
           __syncthreads();
           ++o.iterations;
