@@ -69,6 +69,12 @@ def test_host_only_entry_points():
         bad.ls_width = width
         assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
     assert lib.glasso_autotune(None, 100, 1, None, None) == 1
+    # the covariance rejects a null handle or buffers and empty shapes before any device call
+    assert lib.glasso_covariance(None, None, 10, 10, 1, None, None) == 1
+    fake = ctypes.c_void_p(1)
+    assert lib.glasso_covariance(fake, None, 10, 10, 1, None, None) == 1
+    assert lib.glasso_covariance(fake, fake, 0, 10, 1, fake, None) == 1
+    assert lib.glasso_covariance(fake, fake, 10, 0, 1, fake, None) == 1
 
 
 def test_struct_layout_matches_c():
