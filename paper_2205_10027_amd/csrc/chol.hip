@@ -18,7 +18,8 @@ namespace {
 
 constexpr int NB = 128;        // leaf block (= GEMM tile)
 constexpr int LDL = NB + 1;    // LDS row stride of the leaf
-constexpr int OUTER = 1024;    // outer panel width of the two-level Cholesky
+constexpr int OUTER = 1024;    // outer panel width of the blocked Cholesky
+constexpr int MID = 512;       // middle panel width: K = 128 updates stay inside it
 
 // One step of the blocked Cholesky: the 128-column block whose diagonal block is at
 // A, with `rest` rows of the panel below it (a multiple of 64).
@@ -217,18 +218,28 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
   int rc = 0;
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
-    for (int k = K0; k < K1 && rc == 0; k += NB) {
-      // factor the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
-      double* Akk = A + (int64_t)k * lda + k;
-      const int rest = n - k - NB;
-      hipLaunchKernelGGL(leaf_potrf_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k, rest,
-                         dL + k, info, fb);
-      if (hipGetLastError() != hipSuccess) return -2;
-      if (k + NB < K1) {
-        // update of the remaining columns of the outer panel
-        const double* Pk = A + (int64_t)(k + NB) * lda + k;
-        rc = gemm_f64(stream, 0, 0, rest, K1 - k - NB, NB, -1.0, Pk, lda, Pk, lda, 1.0,
-                      A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
+    for (int M0 = K0; M0 < K1 && rc == 0; M0 += MID) {
+      const int M1 = min(M0 + MID, K1);
+      for (int k = M0; k < M1 && rc == 0; k += NB) {
+        // factor the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
+        double* Akk = A + (int64_t)k * lda + k;
+        const int rest = n - k - NB;
+        hipLaunchKernelGGL(leaf_potrf_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k,
+                           rest, dL + k, info, fb);
+        if (hipGetLastError() != hipSuccess) return -2;
+        if (k + NB < M1) {
+          // update of the remaining columns of the middle panel (K = 128)
+          const double* Pk = A + (int64_t)(k + NB) * lda + k;
+          rc = gemm_f64(stream, 0, 0, rest, M1 - k - NB, NB, -1.0, Pk, lda, Pk, lda, 1.0,
+                        A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
+          if (rc) return rc;
+        }
+      }
+      if (M1 < K1) {
+        // the rest of the outer panel from the whole middle panel (K = M1 - M0)
+        const double* Pm = A + (int64_t)M1 * lda + M0;
+        rc = gemm_f64(stream, 0, 0, n - M1, K1 - M1, M1 - M0, -1.0, Pm, lda, Pm, lda, 1.0,
+                      A + (int64_t)M1 * lda + M1, lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
         if (rc) return rc;
       }
     }
