@@ -3,14 +3,18 @@
 Headline (value): time-to-KKT <= 1e-5 on the chain workload n = 10000,
 m = 5000 (seed 0), lambda in {0.1, 0.2}: one step = one solve at each lambda,
 from the diagonal initialisation, with S already resident in HBM.  The form
-timed is --precision (default: the BF16x3 mixed form, A Z A as three BF16
-products; its factor, log det, PD test, W and KKT are FP64); the plain FP64 path
-is timed on the same workload and reported beside it (config.fp64_plain_s,
-config.speedup_vs_fp64).
+timed is --precision (default: the BF16x3 mixed form: W with FP32 accuracy from
+BF16 products, A Z A as the FP64 sampled sparse product where the iterate's rows
+are short, else three BF16 products; its factor, log det, PD test and KKT are
+FP64).  The plain FP64 path (FP64 throughout, dense products as in the paper) is
+timed on the same workload and reported beside it (config.fp64_plain_s,
+config.speedup_vs_fp64), and so is FP64 with the sparse product
+(config.fp64_sparse_product_s).
 
 Extra objects on the same line:
-  roofline      the A Z A GEMMs (dominant kernel): algorithmic flops per launch /
-                mean launch time from HIP events around the launches
+  roofline      the dominant work, the FP64 Cholesky of each line-search trial point:
+                n^3/3 algorithmic flops / mean factorisation time from HIP events
+                around the factorisations
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
                 from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
   serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
@@ -19,7 +23,7 @@ Extra objects on the same line:
                 lambda = 0.2 chain problem, scaled by the GPU's iteration count
 
     python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
-                    [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline]
+                    [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline] [--dense-product]
 """
 from __future__ import annotations
 
@@ -35,10 +39,6 @@ sys.path.insert(0, ROOT)
 # dense MFMA peaks; BF16x3 spends three BF16 products per algorithmic product, so its
 # peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
-# HBM bytes per A Z A launch (mean of the two launches), from FETCH_SIZE and WRITE_SIZE
-# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_gemm_*_chain10k.md).
-# Valid for the GEMM kernels as profiled; None where no counters were taken.
-TRAFFIC_BYTES = {"fp32": 11246852513, "fp64": None, "bf16x3": 18319328585}
 
 
 def log(*a):
@@ -64,8 +64,8 @@ def cpu_baseline(S, lam, gpu_iterations):
                       f"{dt:.1f} s) x {gpu_iterations} GPU iterations"}
 
 
-def time_chain(g, St, lams, tol, precision, steps, warmup, torch):
-    solver = g.Solver(precision=precision)
+def time_chain(g, St, lams, tol, precision, steps, warmup, torch, dense_product=False):
+    solver = g.Solver(precision=precision, dense_product=dense_product)
     As = [torch.empty_like(St) for _ in lams]  # the last step's solution per lambda
 
     def step():
@@ -360,6 +360,8 @@ def main():
     ap.add_argument("--support", action="store_true",
                     help="also run the support-recovery sweep (about a minute of GPU time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-product", action="store_true",
+                    help="form every A Z A with the dense GEMM pair (the paper's design)")
     ap.add_argument("--serve-requests", type=int, default=120)
     ap.add_argument("--path-only", action="store_true",
                     help="run only the regularisation-path measurement and print its object (for profiling)")
@@ -393,26 +395,37 @@ def main():
     log(f"[bench] generated S n={n} m={m} in {time.perf_counter() - t:.1f}s")
     St = torch.from_numpy(S).to(dev)
 
-    elapsed, results, A_mixed = time_chain(g, St, lams, tol, args.precision, args.steps, args.warmup, torch)
+    elapsed, results, A_mixed = time_chain(g, St, lams, tol, args.precision, args.steps, args.warmup, torch,
+                                           dense_product=args.dense_product)
     solves = args.steps * len(lams)
     value = elapsed / solves
 
-    # roofline of the A Z A GEMMs: 2 launches per iteration, 3 n^3 algorithmic flops
-    # (A Z: 2n^3; lower triangle of (A Z) A: n^3), HIP events on the solve's stream
-    # around the two GEMM launches alone
+    # roofline of the dominant work, the line search's FP64 Cholesky of each trial
+    # point (potrf_lower: leaf_potrf_kernel steps and gemm_f64_kernel updates):
+    # n^3/3 algorithmic flops per factorisation, HIP events on the solve's stream
+    # around each round's factorisations alone
     iters = sum(r.iterations for r in results)
-    aza_ms = sum(r.time_ms[5] for r in results)
-    # the first product of a diagonal start is D Z D (elementwise, no GEMM launch)
-    launches = 2 * sum(r.aza_gemm_products for r in results)
-    avg_launch_s = aza_ms / 1000.0 / launches
-    achieved = 1.5 * float(n) ** 3 / avg_launch_s / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    kernel = {"fp32": "gemm_f32_nt_kernel<float> (X = A Z) and <double> (tril(X A)), FP32 MFMA",
-              "fp64": "gemm_f64_kernel<0,0,1> (X = A Z and tril(X A)), FP64 MFMA",
-              "bf16x3": "gemm_bf16x3_nt_kernel<0> (X = A Z) and <1> (tril(X A)), three BF16 MFMA products"
-              }[args.precision]
+    trials = sum(r.ls_trials for r in results)
+    fact_ms = sum(r.time_ms[6] for r in results)
+    avg_fact_s = fact_ms / 1000.0 / trials
+    achieved = float(n) ** 3 / 3.0 / avg_fact_s / 1e12
+    peak = PEAK_TFLOPS["fp64"]
+    kernel = ("trial-point Cholesky potrf_lower: leaf_potrf_kernel (128-column steps) and "
+              "gemm_f64_kernel<0,0,0,*> (updates), FP64 MFMA")
+    # A Z A: the sampled sparse product wherever the iterate's rows are short, else the
+    # GEMM pair (2 launches, 3 n^3 algorithmic flops: A Z 2n^3, tril((A Z) A) n^3)
+    gemm_launches = 2 * sum(r.aza_gemm_products for r in results)
+    aza = {"ms_per_iteration": sum(r.time_ms[3] for r in results) / iters,
+           "sparse_products": sum(r.aza_sparse_products for r in results),
+           "gemm_products": sum(r.aza_gemm_products for r in results)}
+    if gemm_launches:
+        gemm_s = sum(r.time_ms[5] for r in results) / 1000.0 / gemm_launches
+        aza["gemm_avg_launch_ms"] = gemm_s * 1000.0
+        aza["gemm_achieved_tflops"] = 1.5 * float(n) ** 3 / gemm_s / 1e12
+        aza["gemm_peak_tflops"] = PEAK_TFLOPS[args.precision]
     config = {"workload": f"chain n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
               "precision": args.precision,
+              "aza_form": "dense GEMM pair" if args.dense_product else "sparse where the rows are short, else GEMM pair",
               "iterations": [r.iterations for r in results[:len(lams)]],
               "ls_trials": [r.ls_trials for r in results[:len(lams)]],
               "solves_per_s": solves / elapsed}
@@ -420,7 +433,6 @@ def main():
     # events: W = A^-1 (2 n^3/3 flops per iteration: triangular inverse + V^T V),
     # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
     # elementwise passes sit in the same window), A Z A (above)
-    trials = sum(r.ls_trials for r in results)
     w_ms = sum(r.time_ms[1] for r in results)
     ls_ms = sum(r.time_ms[4] for r in results)
     # mixed forms: W with FP32 accuracy from six BF16 products per pair (BF16x6)
@@ -434,12 +446,17 @@ def main():
               "line_search": {"ms_per_trial": ls_ms / trials, "achieved_tflops": ls_tf,
                               "peak_tflops": PEAK_TFLOPS["fp64"], "frac": ls_tf / PEAK_TFLOPS["fp64"],
                               "precision": "fp64 (Cholesky of each trial point)"},
-              "AZA": {"ms_per_iteration": sum(r.time_ms[3] for r in results) / iters}}
+              "AZA": aza}
     if not args.no_fp64_ref and args.precision != "fp64":
-        e64, r64, A64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
+        # FP64 plain: FP64 throughout with the paper's dense products
+        e64, r64, A64 = time_chain(g, St, lams, tol, "fp64", 1, 0, torch, dense_product=True)
         config["fp64_plain_s"] = e64 / len(lams)
         config["fp64_plain_iterations"] = [r.iterations for r in r64]
         config["speedup_vs_fp64"] = (e64 / len(lams)) / value
+        # FP64 throughout with the sparse product where it applies
+        e64s, r64s, _ = time_chain(g, St, lams, tol, "fp64", 1, 0, torch)
+        config["fp64_sparse_product_s"] = e64s / len(lams)
+        config["speedup_vs_fp64_sparse_product"] = (e64s / len(lams)) / value
         # error of every mixed result against the FP64 path (which meets the oracle bar)
         err = []
         for lam, rm, r6, Am, A6 in zip(lams, results[-len(lams):], r64, A_mixed, A64):
@@ -465,8 +482,9 @@ def main():
         "config": config,
         "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": TRAFFIC_BYTES[args.precision], "traffic_unit": "B", "kernel": kernel,
-                     "avg_launch_ms": avg_launch_s * 1000.0, "launches": launches},
+                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "avg_launch_ms": avg_fact_s * 1000.0, "launch_unit": "one trial factorisation",
+                     "launches": trials},
     }
     line["covariance"] = bench_covariance(g, torch, dev)
     if args.support:

@@ -89,6 +89,12 @@ typedef struct {
                       trial point and factor (2 n^2 doubles) per problem.  0 (default):
                       4 for n <= 2048 (1 when that workspace does not fit in device
                       memory), 1 above; else 1 .. 16. */
+  int dense_product; /* 0 (default): each iteration's A Z A is formed, per problem, by the
+                        sampled sparse product when every row of the iterate has at most 16
+                        nonzeros and every row of the free set at most 64 entries on or left
+                        of the diagonal (only entries on the free set are needed, eq. d_sol),
+                        in FP64 from the same Z; otherwise by the dense GEMM pair of
+                        `precision`.  1: always the dense pair (the paper's dense design). */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)
@@ -104,9 +110,13 @@ typedef struct {
   int status;       /* glasso_status */
   int fallback_steps; /* line searches that reached t_floor and used the cond-based step */
   double time_ms[8];  /* [0] total, [1] W = A^-1, [2] gradient pass, [3] A Z A,
-                        [4] line search, [5] the two A Z A GEMM launches alone */
+                        [4] line search, [5] the two A Z A GEMM launches alone,
+                        [6] the line search's trial factorisations alone (eager
+                        launches only; 0 with graphs) */
   int aza_gemm_products; /* A Z A products formed by the GEMM pair; the first product
                             of a diagonal start is D Z D, formed elementwise */
+  int aza_sparse_products; /* A Z A products formed by the sampled sparse product
+                              (see dense_product); time_ms[5] excludes them */
 } glasso_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -237,6 +247,19 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
 glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P, const double* S,
                               const int8_t* GM, int64_t n, double lambda, double t, double* At,
                               double* sums, void* stream);
+
+/* The preconditioned product as a solve forms it when dense_product is 0 (the
+ * sampled sparse form; the paper's design forms A Z A densely, Sec. 4): P_ij =
+ * (A Z A)_ij in FP64 for every (i, j) with GM_ij != 0 and P_ij = 0 elsewhere, n x n
+ * full symmetric (the trial point, eq. d_sol, reads P only there).  The sparse
+ * form serves the call when every row of A has at most 16 nonzeros and every row
+ * of GM at most 64 nonzeros on or left of the diagonal; otherwise the FP64 GEMM
+ * pair forms the same entries.  *used (host, may be NULL) = 1 when the sparse form
+ * served the call, else 0.  A and Z (n x n, symmetric) and GM (n x n int8) are
+ * device buffers read in full; P is a device buffer the caller owns.
+ * Errors: INVALID_ARG for a null handle or buffer or n < 1. */
+glasso_err glasso_sparse_product(glasso_handle h, const double* A, const double* Z, const int8_t* GM,
+                                 int64_t n, double* P, int* used, void* stream);
 
 #ifdef __cplusplus
 }

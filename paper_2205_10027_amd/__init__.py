@@ -74,6 +74,7 @@ class Result:
     fallback_steps: int
     time_ms: tuple
     aza_gemm_products: int = 0
+    aza_sparse_products: int = 0
 
     @property
     def status_name(self) -> str:
@@ -86,7 +87,7 @@ class Solver:
     def __init__(self, precision: str | int = "fp64", max_iter: int = 500, t0: float = 1.0,
                  shrink: float = 0.5, t_floor: float = 1e-4, t_min: float = 1e-12,
                  warm_start: bool = False, tile_policy: int = TILES_AUTO, graphs: bool = False,
-                 w_mixed: int = -1, ls_width: int = 0):
+                 w_mixed: int = -1, ls_width: int = 0, dense_product: bool = False):
         opt = GlassoOptions()
         _check(_lib.glasso_default_options(ctypes.byref(opt)), "glasso_default_options")
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -100,6 +101,7 @@ class Solver:
         opt.graphs = int(bool(graphs))
         opt.w_mixed = int(w_mixed)
         opt.ls_width = int(ls_width)
+        opt.dense_product = int(bool(dense_product))
         self.options = opt
         h = ctypes.c_void_p()
         _check(_lib.glasso_create(ctypes.byref(h), ctypes.byref(opt)), "glasso_create")
@@ -144,7 +146,8 @@ class Solver:
                                  ctypes.byref(info), _stream(stream)), "glasso_solve")
         return Result(A, W, info.objective, info.iterations, info.status, info.kkt_rel1,
                       info.kkt_fro, info.kkt_max, int(info.nnz), info.ls_trials,
-                      info.fallback_steps, tuple(info.time_ms), info.aza_gemm_products)
+                      info.fallback_steps, tuple(info.time_ms), info.aza_gemm_products,
+                      info.aza_sparse_products)
 
     def solve_batched(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
         """Solve len(lams) problems in batched launches (glasso_solve_batched).
@@ -191,7 +194,8 @@ class Solver:
             inf = infos[i]
             out.append(Result(A_list[i], W_list[i] if want_W else None, inf.objective, inf.iterations,
                               inf.status, inf.kkt_rel1, inf.kkt_fro, inf.kkt_max, int(inf.nnz),
-                              inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms), inf.aza_gemm_products))
+                              inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms), inf.aza_gemm_products,
+                              inf.aza_sparse_products))
         return out
 
     # ---------------------------------------------------------------- single steps
@@ -238,6 +242,17 @@ class Solver:
         _check(_lib.glasso_precond_product(self._h, _dev(A, "A"), _dev(Z, "Z"), n, prec,
                                            P.data_ptr(), _stream(stream)), "glasso_precond_product")
         return P
+
+    def sparse_product(self, A, Z, GM, stream=None):
+        """(A Z A) on the free set (GM != 0), zero elsewhere, FP64 (glasso_sparse_product).
+        Returns (P, used_sparse)."""
+        n = _square(A, "A")
+        P = torch.empty_like(A)
+        used = ctypes.c_int(0)
+        _check(_lib.glasso_sparse_product(self._h, _dev(A, "A"), _dev(Z, "Z"), _dev(GM, "GM", torch.int8), n,
+                                          P.data_ptr(), ctypes.byref(used), _stream(stream)),
+               "glasso_sparse_product")
+        return P, bool(used.value)
 
     def trial_point(self, A, P, S, GM, lam: float, t: float, stream=None):
         n = _square(A, "A")

@@ -23,6 +23,7 @@ class GlassoOptions(ctypes.Structure):
         ("graphs", ctypes.c_int),
         ("w_mixed", ctypes.c_int),
         ("ls_width", ctypes.c_int),
+        ("dense_product", ctypes.c_int),
     ]
 
 
@@ -39,6 +40,7 @@ class GlassoInfo(ctypes.Structure):
         ("fallback_steps", ctypes.c_int),
         ("time_ms", ctypes.c_double * 8),
         ("aza_gemm_products", ctypes.c_int),
+        ("aza_sparse_products", ctypes.c_int),
     ]
 
 
@@ -65,6 +67,7 @@ SIGNATURES = {
     "glasso_gradient_pass": (_INT, [_VP, _VP, _VP, _VP, _I64, _D, _VP, _VP, c_double_p, _VP]),
     "glasso_precond_product": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
     "glasso_trial_point": (_INT, [_VP, _VP, _VP, _VP, _VP, _I64, _D, _D, _VP, c_double_p, _VP]),
+    "glasso_sparse_product": (_INT, [_VP, _VP, _VP, _VP, _I64, _VP, ctypes.POINTER(_INT), _VP]),
 }
 
 _lib = None

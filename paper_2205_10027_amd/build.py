@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglasso.so")
 
-SOURCES = ["gemm_f64.hip", "gemm_mixed.hip", "gemm_bf16x3.hip", "gemm_bf16x6.hip", "chol.hip", "passes.hip", "persistent.hip", "glasso_api.hip"]
+SOURCES = ["gemm_f64.hip", "gemm_mixed.hip", "gemm_bf16x3.hip", "gemm_bf16x6.hip", "chol.hip", "passes.hip", "persistent.hip", "sparse_product.hip",
+           "glasso_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -143,8 +143,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_nt_kernel(GemmBf16Params p
     }
 }
 
-// FP64 -> split layout; one run of 8 elements per thread and step
-__global__ void split_bf16x2_kernel(const double* __restrict__ src, uint8_t* __restrict__ dst, int64_t runs) {
+// FP64 -> split layout; one run of 8 elements per thread and step (nothing when *skip)
+__global__ void split_bf16x2_kernel(const double* __restrict__ src, uint8_t* __restrict__ dst, int64_t runs,
+                                    const int* skip) {
+  if (skip && *skip) return;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < runs; g += (int64_t)gridDim.x * blockDim.x) {
     const double2* s = reinterpret_cast<const double2*>(src + g * 8);
     uint32_t hi[4], lo[4];
@@ -195,11 +197,12 @@ int gemm_bf16x3_nt(hipStream_t stream, int M, int N, int K, const void* A, int64
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count) {
+int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count, const int* skip) {
   if (count % 8) return -1;
   const int64_t runs = count / 8;
   const int blocks = (int)std::min<int64_t>((runs + 255) / 256, 16384);
-  hipLaunchKernelGGL(split_bf16x2_kernel, dim3(blocks), dim3(256), 0, stream, src, static_cast<uint8_t*>(dst), runs);
+  hipLaunchKernelGGL(split_bf16x2_kernel, dim3(blocks), dim3(256), 0, stream, src, static_cast<uint8_t*>(dst), runs,
+                     skip);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

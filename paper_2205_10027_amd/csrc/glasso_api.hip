@@ -46,6 +46,7 @@ struct Workspace {
   double *lam = nullptr, *t = nullptr;
   int64_t* bad = nullptr;
   double* vec = nullptr;
+  SparseRows sp;  // row lists of the sparse product
   int64_t nn() const { return np * np; }
 };
 
@@ -89,6 +90,14 @@ size_t layout(Workspace& w, int count, int slots, int64_t np, char* base) {
   w.t = (double*)take(slots * sizeof(double));
   w.bad = (int64_t*)take(sizeof(int64_t));
   w.vec = (double*)take(2 * np * sizeof(double));
+  const size_t rows = (size_t)count * np;
+  w.sp.rows = np;
+  w.sp.colA = (int*)take(rows * SPARSE_KA * sizeof(int));
+  w.sp.valA = (double*)take(rows * SPARSE_KA * sizeof(double));
+  w.sp.colM = (int*)take(rows * SPARSE_KM * sizeof(int));
+  w.sp.cnt = (int*)take(rows * 2 * sizeof(int));
+  w.sp.dense = (int*)take(count * sizeof(int));
+  w.sp.dskip = (int*)take(count * sizeof(int));
   return off;
 }
 
@@ -128,7 +137,7 @@ struct glasso_handle_s {
   int device = 0;
   Workspace ws;
   HostMirror hm;
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[10] = {};
   hipStream_t cap = nullptr;  // capture stream (graphs option)
   Graphs graphs;
   void* small_base = nullptr;  // workspace of the persistent small-problem solver
@@ -308,6 +317,7 @@ glasso_err check_options(const glasso_options* o) {
   if (o->max_iter < 0 || o->tile_policy < GLASSO_TILES_AUTO || o->w_mixed < -1 || o->w_mixed > 1)
     return GLASSO_ERR_INVALID_ARG;
   if (o->ls_width < 0 || o->ls_width > LS_WIDTH_MAX) return GLASSO_ERR_INVALID_ARG;
+  if (o->dense_product < 0 || o->dense_product > 1) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -362,11 +372,20 @@ glasso_err inverse_from_factor(Workspace& w, hipStream_t st, const int* skip) {
 // P = tril(X A^T) (A symmetric).  Mixed FP32: A and Z are rounded to FP32 (A32,
 // Z32 in the X buffer), X32 = A32 Z32^T overwrites Z (no longer needed), and
 // P = tril(X32 A32^T) is written in FP64.
+// sparse: first try the sampled sparse product (sparse_product.hip); the problems
+// it serves are then skipped by the dense pair, which serves the rest.
 // gev (optional): two events recorded around the two GEMM launches only
-glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip,
+glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const int* skip, int64_t n, bool sparse,
                            hipEvent_t* gev = nullptr, bool z_split_ready = false) {
   const int np = (int)w.np;
   const int64_t nn = w.nn();
+  if (sparse) {
+    const bool zs = precision == GLASSO_MIXED_BF16X3 && z_split_ready;
+    const void* Zsrc = zs ? static_cast<const void*>(reinterpret_cast<const uint8_t*>(w.X) + 4 * nn)
+                          : static_cast<const void*>(w.Z);
+    K_TRY(sparse_product(st, w.A, w.GM, Zsrc, zs ? 1 : 0, 8 * nn, n, w.np, w.count, skip, w.sp, w.scal, w.P));
+    skip = w.sp.dskip;
+  }
   ZBatch z;
   z.count = w.count;
   z.sA = z.sB = z.sC = nn;
@@ -408,8 +427,9 @@ glasso_err precond_product(Workspace& w, hipStream_t st, int precision, const in
     uint8_t* As = reinterpret_cast<uint8_t*>(w.X);
     uint8_t* Xs = reinterpret_cast<uint8_t*>(w.Z);
     for (int b = 0; b < w.count; ++b) {
-      K_TRY(split_bf16x2(st, w.A + b * nn, As + 2 * b * nn * 4, nn));
-      if (!z_split_ready) K_TRY(split_bf16x2(st, w.Z + b * nn, As + (2 * b + 1) * nn * 4, nn));
+      const int* sb = skip ? skip + b : nullptr;
+      K_TRY(split_bf16x2(st, w.A + b * nn, As + 2 * b * nn * 4, nn, sb));
+      if (!z_split_ready) K_TRY(split_bf16x2(st, w.Z + b * nn, As + (2 * b + 1) * nn * 4, nn, sb));
     }
     ZBatch z1;  // Xs = A Z^T (Z symmetric)
     z1.count = w.count;
@@ -491,7 +511,7 @@ glasso_err tune_tiles(glasso_handle h, hipStream_t st, int precision, int* chose
       e = inverse_from_factor(w, st, nullptr);
       if (e) return e;
       if (precision == GLASSO_FP64) {
-        e = precond_product(w, st, precision, nullptr);
+        e = precond_product(w, st, precision, nullptr, w.np, false);
         if (e) return e;
       }
       HIP_TRY(hipEventRecord(h->ev[1], st));
@@ -604,9 +624,11 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   }
 
   std::vector<int> active(count, 1), status(count, GLASSO_MAX_ITER), it(count, 0), trials(count, 0),
-      fallbacks(count, 0), ls(count, 0), fb_used(count, 0), gemm_products(count, 0), ncand(count, 0),
+      fallbacks(count, 0), ls(count, 0), fb_used(count, 0), gemm_products(count, 0), sparse_products(count, 0),
+      prod_b(count, 0), ncand(count, 0),
       last_trials(count, 1), since(count, 0);
   std::vector<double> tb(count, o.t0);  // next step size of each problem's backtracking sequence
+  const bool sparse_on = o.dense_product == 0;
   PassBatch pb;
   pb.count = count;
   pb.sS = sS;
@@ -687,9 +709,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
-    return precond_product(w, s, o.precision, w.skip, timed ? h->ev + 5 : nullptr, z_split != nullptr);
+    return precond_product(w, s, o.precision, w.skip, n, sparse_on, timed ? h->ev + 5 : nullptr, z_split != nullptr);
   };
-  auto trial = [&](hipStream_t s, bool) -> glasso_err {  // a4, a5
+  auto trial = [&](hipStream_t s, bool timed) -> glasso_err {  // a4, a5
     glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, slots);
     if (e2) return e2;
     e2 = push_doubles(s, w.t, hm.t, slots);
@@ -697,7 +719,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
     // the trial's factor is finished (diagonal blocks placed and inverted) only if
     // it is accepted, at the next head
+    if (timed) HIP_TRY(hipEventRecord(h->ev[8], s));
     K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, nullptr, w.info, fbt, 0));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[9], s));
     K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal_t, pt));
     return fetch_async(h, s);
   };
@@ -833,7 +857,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       e = run(&h->graphs.prod, prod);
       if (e) return e;
       if (graphs) HIP_TRY(hipEventRecord(h->ev[6], st));
-      for (int b = 0; b < count; ++b) gemm_products[b] += active[b];
+      for (int b = 0; b < count; ++b) prod_b[b] = active[b];
     }
     HIP_TRY(hipEventRecord(h->ev[3], st));
     // a4-a6: trial points t = t0, t0*shrink, ... until PD with a strict decrease.
@@ -887,6 +911,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       e = run(&h->graphs.trial, trial);
       if (e) return e;
       HIP_TRY(hipStreamSynchronize(st));
+      if (!graphs) phase[6] += elapsed(h->ev[8], h->ev[9]);
       int nacc = 0;
       for (int b = 0; b < count; ++b) {
         hm.accept[b] = 0;
@@ -923,7 +948,17 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     HIP_TRY(hipEventSynchronize(h->ev[4]));
     phase[3] += elapsed(h->ev[2], h->ev[3]);
     phase[4] += elapsed(h->ev[3], h->ev[4]);
-    phase[5] += elapsed(h->ev[5], h->ev[6]);
+    // which form served each problem's product (the scalars were fetched with the
+    // line search's last round); the GEMM time counts only when the pair ran
+    bool pair_ran = false;
+    for (int b = 0; b < count; ++b) {
+      if (!prod_b[b]) continue;
+      prod_b[b] = 0;
+      const bool dense = !sparse_on || hscal(h, b, SC_DENSE_PRODUCT) != 0.0;
+      (dense ? gemm_products[b] : sparse_products[b]) += 1;
+      pair_ran = pair_ran || dense;
+    }
+    if (pair_ran) phase[5] += elapsed(h->ev[5], h->ev[6]);
   }
 
   {
@@ -960,6 +995,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       in.status = status[b];
       in.fallback_steps = fallbacks[b];
       in.aza_gemm_products = gemm_products[b];
+      in.aza_sparse_products = sparse_products[b];
       for (int i = 1; i < 8; ++i) in.time_ms[i] = phase[i];
       in.time_ms[0] = total;
     }
@@ -1318,7 +1354,7 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
   Workspace& w = h->ws;
   K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
   K_TRY(pad_copy_f64(st, Z, n, np, w.Z, nullptr, 0));
-  e = precond_product(w, st, precision, nullptr);
+  e = precond_product(w, st, precision, nullptr, n, false);
   if (e) return e;
   K_TRY(sym_copy_out(st, w.P, np, P, n, 1));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1349,6 +1385,30 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
     sums[0] = hscal(h, 0, SC_DTR);
     sums[1] = hscal(h, 0, SC_DL1);
   }
+  return GLASSO_OK;
+}
+
+glasso_err glasso_sparse_product(glasso_handle h, const double* A, const double* Z, const int8_t* GM, int64_t n,
+                                 double* P, int* used, void* stream) {
+  if (!h || !A || !Z || !GM || !P || n < 1) return GLASSO_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = pad_to_tile(n);
+  glasso_err e = ensure_workspace(h, 1, np, st);
+  if (e) return e;
+  e = apply_tile_policy(h, st, h->opt.precision);
+  if (e) return e;
+  Workspace& w = h->ws;
+  K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
+  K_TRY(pad_copy_f64(st, Z, n, np, w.Z, nullptr, 0));
+  K_TRY(pad_copy_i8(st, GM, n, np, w.GM));
+  e = precond_product(w, st, GLASSO_FP64, nullptr, n, true);
+  if (e) return e;
+  // off the free set: zero (the dense pair, when it ran, filled the whole triangle)
+  K_TRY(mask_free_set(st, w.P, w.GM, w.nn()));
+  K_TRY(sym_copy_out(st, w.P, np, P, n, 1));
+  e = fetch(h, st);
+  if (e) return e;
+  if (used) *used = hscal(h, 0, SC_DENSE_PRODUCT) == 0.0 ? 1 : 0;
   return GLASSO_OK;
 }
 

@@ -44,7 +44,7 @@ int gemm_bf16x3_nt(hipStream_t stream, int M, int N, int K, const void* A, int64
                    int64_t ldb, void* C, int64_t ldc, int c_is_double, int lower_out,
                    const ZBatch& zb = ZBatch(), const int* skip = nullptr);
 // FP64 -> split layout (count a multiple of 8)
-int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count);
+int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count, const int* skip = nullptr);
 
 // V = inv(L) and V^T as three-part bf16 splits (6 bytes per element) by recursive
 // doubling from the factor L (FP64, lower, intact) and its diagonal-block inverses
@@ -104,6 +104,32 @@ int init_diag(hipStream_t stream, const double* Sp, int64_t n, int64_t np, doubl
 // P = A Z A for diagonal A (elementwise, FP64), problems with skip == 0.
 int diag_product(hipStream_t stream, const double* A, const double* Z, double* P, int64_t np, int count,
                  const int* skip);
+
+// Sampled sparse form of the preconditioned product (sparse_product.hip).  Per
+// problem: column lists of the iterate's rows (at most SPARSE_KA nonzeros) and of
+// the free set's rows left of and on the diagonal (at most SPARSE_KM), their
+// lengths, and the per-problem choice: dense[b] = 1 when some row is longer (the
+// dense GEMM pair runs, with dskip[b] = 0), else 0 (dskip[b] = 1).  All arrays
+// hold `rows` (>= np) rows per problem.
+constexpr int SPARSE_KA = 16;
+constexpr int SPARSE_KM = 64;
+struct SparseRows {
+  int* colA = nullptr;     // rows x SPARSE_KA
+  double* valA = nullptr;  // rows x SPARSE_KA
+  int* colM = nullptr;     // rows x SPARSE_KM
+  int* cnt = nullptr;      // rows x 2: nonzeros of A's row, lower free entries of the row
+  int* dense = nullptr;    // per problem
+  int* dskip = nullptr;    // per problem: skip flag for the dense pair
+  int64_t rows = 0;
+};
+// P_ij = (A Z A)_ij for (i, j) in the free set (GM != 0), j <= i < n, FP64, for
+// the problems with skip == 0 whose rows are short enough; writes SC_DENSE_PRODUCT
+// of each such problem's scalars.  Z: FP64 (z_split = 0) or the bf16 hi + lo split
+// layout (z_split = 1); sZ = bytes between problems' Z.
+int sparse_product(hipStream_t stream, const double* A, const int8_t* GM, const void* Z, int z_split, int64_t sZ,
+                   int64_t n, int64_t np, int count, const int* skip, const SparseRows& r, double* scal, double* P);
+// P_e = 0 where GM_e == 0, for `count` elements
+int mask_free_set(hipStream_t stream, double* P, const int8_t* GM, int64_t count);
 int pad_copy_f64(hipStream_t stream, const double* src, int64_t n, int64_t np, double* dst,
                  double* dst2, int pad_diag);
 int pad_copy_i8(hipStream_t stream, const int8_t* src, int64_t n, int64_t np, int8_t* dst);
@@ -208,6 +234,7 @@ enum ScalarSlot {
   SC_NNZ_AT,
   SC_POWER_A,
   SC_POWER_W,
+  SC_DENSE_PRODUCT,  // 1: the last product used the dense GEMM pair, 0: the sparse product
   SC_COUNT = 24
 };
 

@@ -68,6 +68,11 @@ def test_host_only_entry_points():
         lib.glasso_default_options(ctypes.byref(bad))
         bad.ls_width = width
         assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
+    assert opt.dense_product == 0
+    for v in (-1, 2):
+        lib.glasso_default_options(ctypes.byref(bad))
+        bad.dense_product = v
+        assert lib.glasso_create(ctypes.byref(h), ctypes.byref(bad)) == 1 and not h.value
     assert lib.glasso_autotune(None, 100, 1, None, None) == 1
     # the covariance rejects a null handle or buffers and empty shapes before any device call
     assert lib.glasso_covariance(None, None, 10, 10, 1, None, None) == 1
@@ -75,6 +80,10 @@ def test_host_only_entry_points():
     assert lib.glasso_covariance(fake, None, 10, 10, 1, None, None) == 1
     assert lib.glasso_covariance(fake, fake, 0, 10, 1, fake, None) == 1
     assert lib.glasso_covariance(fake, fake, 10, 0, 1, fake, None) == 1
+    # the sparse product rejects a null handle or buffer and n < 1 the same way
+    assert lib.glasso_sparse_product(None, fake, fake, fake, 10, fake, None, None) == 1
+    assert lib.glasso_sparse_product(fake, fake, None, fake, 10, fake, None, None) == 1
+    assert lib.glasso_sparse_product(fake, fake, fake, fake, 0, fake, None, None) == 1
 
 
 def test_struct_layout_matches_c():
@@ -86,11 +95,13 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options), offsetof(glasso_options, warm_start),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options),
+         offsetof(glasso_options, warm_start),
          offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
-         offsetof(glasso_options, ls_width),
+         offsetof(glasso_options, ls_width), offsetof(glasso_options, dense_product),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
-         offsetof(glasso_info, time_ms), offsetof(glasso_info, aza_gemm_products));
+         offsetof(glasso_info, time_ms), offsetof(glasso_info, aza_gemm_products),
+         offsetof(glasso_info, aza_sparse_products));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -101,7 +112,7 @@ int main(void) {
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     want = [ctypes.sizeof(g.GlassoOptions), g.GlassoOptions.warm_start.offset, g.GlassoOptions.tile_policy.offset,
             g.GlassoOptions.graphs.offset, g.GlassoOptions.w_mixed.offset, g.GlassoOptions.ls_width.offset,
-            ctypes.sizeof(g.GlassoInfo),
+            g.GlassoOptions.dense_product.offset, ctypes.sizeof(g.GlassoInfo),
             g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset,
-            g.GlassoInfo.aza_gemm_products.offset]
+            g.GlassoInfo.aza_gemm_products.offset, g.GlassoInfo.aza_sparse_products.offset]
     assert [int(x) for x in out] == want

@@ -45,9 +45,9 @@ def check_against_oracle(g, S, lam, tol, solver=None, ref=None, obj_rtol=1e-8):
     # W is the inverse of the returned A
     assert np.max(np.abs(W @ A - np.eye(len(S)))) <= 1e-10 * np.linalg.cond(A)
     assert res.nnz == np.count_nonzero(A)
-    # every accepted step followed one product; the first of a diagonal start is
-    # D Z D, formed without the GEMM pair
-    assert res.aza_gemm_products == max(res.iterations - 1, 0)
+    # every accepted step followed one product (the GEMM pair or the sparse form);
+    # the first of a diagonal start is D Z D, formed elementwise
+    assert res.aza_gemm_products + res.aza_sparse_products == max(res.iterations - 1, 0)
     if solver is None:
         s.close()
     return res, ref
@@ -130,7 +130,7 @@ def test_warm_start_resumes(g):
     first = g.Solver().solve(to_dev(S), 0.25, 1e-7)
     warm = g.Solver(warm_start=True).solve(to_dev(S), 0.15, 1e-7, A=first.A.clone())
     assert warm.status == g.CONVERGED
-    assert warm.aza_gemm_products == warm.iterations  # no diagonal start
+    assert warm.aza_gemm_products + warm.aza_sparse_products == warm.iterations  # no diagonal start
     assert abs(warm.objective - cold.objective) <= 1e-9 * abs(cold.objective)
 
 
