@@ -39,6 +39,10 @@ sys.path.insert(0, ROOT)
 # dense MFMA peaks; BF16x3 spends three BF16 products per algorithmic product, so its
 # peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
+# HBM bytes per trial factorisation at n = 10^4 (FP64 in every form), from FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a 1 GiB plain-copy calibration
+# (profiles/traffic_factorisation_chain10k.md)
+FACTORISATION_TRAFFIC_BYTES = 11846283223
 
 
 def log(*a):
@@ -482,7 +486,8 @@ def main():
         "config": config,
         "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": kernel,
+                     "frac": achieved / peak, "traffic": FACTORISATION_TRAFFIC_BYTES, "traffic_unit": "B",
+                     "kernel": kernel,
                      "avg_launch_ms": avg_fact_s * 1000.0, "launch_unit": "one trial factorisation",
                      "launches": trials},
     }
