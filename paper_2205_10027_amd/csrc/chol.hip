@@ -143,6 +143,17 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
 #pragma unroll
   for (int r = 0; r < 16; ++r)
     *reinterpret_cast<double2*>(Rw + (int64_t)r * lda) = make_double2(a[16 * wave + r][2 * lane], a[16 * wave + r][2 * lane + 1]);
+  if (fb.nz) {
+    // whether these 64 solved rows hold a nonzero (the updates skip zero blocks)
+    bool nzl = false;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) nzl = nzl || x[b][s] != 0.0;
+    nzl = __syncthreads_or(nzl);
+    if (tid == 0)
+      fb.nz[blockIdx.y * fb.snz + (int64_t)(k0 / NB) * fb.nz_chunks + (k0 + NB) / 64 + (int)blockIdx.x - 1] = nzl ? 1 : 0;
+  }
 }
 
 // After the factorisation, one workgroup per 128x128 diagonal block: the strict
@@ -215,6 +226,16 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
   ZBatch zA;  // operands and output inside the factored matrix
   zA.count = fb.count;
   zA.sA = zA.sB = zA.sC = fb.sA;
+  zA.nz = fb.nz;
+  zA.snz = fb.snz;
+  zA.nz_chunks = fb.nz_chunks;
+  // the updates' operands: rows from r of the panels from column c
+  auto rows = [&](int r, int c) {
+    ZBatch z = zA;
+    z.nz_row0 = z.nz_col0 = r;
+    z.nz_k0 = c;
+    return z;
+  };
   int rc = 0;
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
@@ -231,7 +252,7 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
           // update of the remaining columns of the middle panel (K = 128)
           const double* Pk = A + (int64_t)(k + NB) * lda + k;
           rc = gemm_f64(stream, 0, 0, rest, M1 - k - NB, NB, -1.0, Pk, lda, Pk, lda, 1.0,
-                        A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
+                        A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, rows(k + NB, k));
           if (rc) return rc;
         }
       }
@@ -239,7 +260,7 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
         // the rest of the outer panel from the whole middle panel (K = M1 - M0)
         const double* Pm = A + (int64_t)M1 * lda + M0;
         rc = gemm_f64(stream, 0, 0, n - M1, K1 - M1, M1 - M0, -1.0, Pm, lda, Pm, lda, 1.0,
-                      A + (int64_t)M1 * lda + M1, lda, 0, 0, 0, info, 1, 0, 0, 0, 0, zA);
+                      A + (int64_t)M1 * lda + M1, lda, 0, 0, 0, info, 1, 0, 0, 0, 0, rows(M1, M0));
         if (rc) return rc;
       }
     }
@@ -247,7 +268,7 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
       // trailing lower triangle: A22 -= L21 L21^T with K = panel width
       const double* L21 = A + (int64_t)K1 * lda + K0;
       rc = gemm_f64(stream, 0, 0, n - K1, n - K1, K1 - K0, -1.0, L21, lda, L21, lda, 1.0,
-                    A + (int64_t)K1 * lda + K1, lda, 1, 0, 0, info, 1, 0, 0, 0, 0, zA);
+                    A + (int64_t)K1 * lda + K1, lda, 1, 0, 0, info, 1, 0, 0, 0, 0, rows(K1, K0));
     }
   }
   if (rc) return rc;

@@ -58,6 +58,9 @@ struct GemmF64Params {
   int64_t sA, sB, sC;  // grid.y batch strides (elements)
   int64_t zA, zB, zC;  // grid.z batch strides (elements)
   const int* abort_flag;
+  const uint8_t* nz;  // zero-block map (ZBatch::nz), may be null
+  int64_t snz;
+  int nz_chunks, nz_row0, nz_col0, nz_k0;
 };
 
 // Stage one T x BK slice of op(X) (rows r0.., k from kt) into registers.
@@ -142,6 +145,24 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
     grouped_tile(L, p.tiles_m, p.tiles_n, ti, tj);
   }
   const int m0 = ti * T, n0 = tj * T;
+  if (p.nz) {
+    // the tile adds A B^T only if some panel of its K range has a nonzero block in
+    // both its A rows and its B rows; otherwise C stays as it is
+    const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
+    const int ca = (p.nz_row0 + m0) >> 6, cb = (p.nz_col0 + n0) >> 6;
+    bool any = false;
+    for (int s = p.nz_k0 >> 7; s < (p.nz_k0 + p.K) >> 7 && !any; ++s) {
+      const uint8_t* fs = f + (int64_t)s * p.nz_chunks;
+      bool a = false, b = false;
+#pragma unroll
+      for (int c = 0; c < T / 64; ++c) {
+        a = a || fs[ca + c] != 0;
+        b = b || fs[cb + c] != 0;
+      }
+      any = a && b;
+    }
+    if (!any) return;
+  }
 
   const double* A = p.A + (int64_t)blockIdx.y * p.sA + (int64_t)blockIdx.z * p.zA;
   const double* B = p.B + (int64_t)blockIdx.y * p.sB + (int64_t)blockIdx.z * p.zB;
@@ -271,6 +292,13 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
   p.zB = zb.sB;
   p.zC = zb.sC;
   p.abort_flag = abort_flag;
+  p.nz = zb.nz;
+  p.snz = zb.snz;
+  p.nz_chunks = zb.nz_chunks;
+  p.nz_row0 = zb.nz_row0;
+  p.nz_col0 = zb.nz_col0;
+  p.nz_k0 = zb.nz_k0;
+  if (zb.nz && (ta || tb || K % 128 || zb.nz_k0 % 128 || zb.nz_row0 % 64 || zb.nz_col0 % 64)) return -1;
   // 128x128 tiles unless the launch has too few of them to fill the chip; both
   // tile edges accumulate every output in the same k order (bitwise equal results).
   // An in-place product (C aliases A, N = 128) keeps 128-wide tiles: one workgroup

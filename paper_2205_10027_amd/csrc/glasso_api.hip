@@ -47,6 +47,7 @@ struct Workspace {
   int64_t* bad = nullptr;
   double* vec = nullptr;
   SparseRows sp;  // row lists of the sparse product
+  uint8_t* nzmap = nullptr;  // zero-block maps of the factorisations (per trial slot)
   int64_t nn() const { return np * np; }
 };
 
@@ -98,6 +99,7 @@ size_t layout(Workspace& w, int count, int slots, int64_t np, char* base) {
   w.sp.cnt = (int*)take(rows * 2 * sizeof(int));
   w.sp.dense = (int*)take(count * sizeof(int));
   w.sp.dskip = (int*)take(count * sizeof(int));
+  w.nzmap = (uint8_t*)take((size_t)std::max(count, slots) * (np / TILE) * (np / 64));
   return off;
 }
 
@@ -244,6 +246,9 @@ FactorBatch factor_batch(const Workspace& w) {
   fb.sA = w.nn();
   fb.sdL = w.np;
   fb.sDinv = w.np * TILE;
+  fb.nz = w.nzmap;
+  fb.nz_chunks = (int)(w.np / 64);
+  fb.snz = (w.np / TILE) * fb.nz_chunks;
   return fb;
 }
 

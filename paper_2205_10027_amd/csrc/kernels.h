@@ -14,6 +14,15 @@ namespace glasso {
 struct ZBatch {
   int count = 1;
   int64_t sA = 0, sB = 0, sC = 0;
+  // Optional zero-block skipping for the Cholesky updates C -= A B^T, where A and
+  // B are rows of the factor's finished panels: nz[z * snz + s * nz_chunks + c]
+  // says whether rows 64c..64c+63 of 128-column panel s hold a nonzero.  A tile
+  // whose operand rows (global rows nz_row0 + m0.., nz_col0 + n0..) meet a zero
+  // block in every panel of its K range (global columns nz_k0..) adds nothing and
+  // leaves C untouched.  nz == nullptr: no skipping.
+  const uint8_t* nz = nullptr;
+  int64_t snz = 0;
+  int nz_chunks = 0, nz_row0 = 0, nz_col0 = 0, nz_k0 = 0;
 };
 
 // ---------------------------------------------------------------- dense kernels
@@ -64,6 +73,12 @@ int gemm_bf16x6_lower(hipStream_t stream, int N, int K, const void* A, int64_t l
 struct FactorBatch {
   int count = 1;
   int64_t sA = 0, sdL = 0, sDinv = 0;
+  // optional per-problem map of the nonzero 64-row blocks of each finished
+  // 128-column panel below its diagonal block (layout of ZBatch::nz); the
+  // factorisation's updates skip the tiles it shows to be zero
+  uint8_t* nz = nullptr;
+  int64_t snz = 0;
+  int nz_chunks = 0;
 };
 
 // In-place lower Cholesky of the n x n (n multiple of 128) matrix A.  Writes the

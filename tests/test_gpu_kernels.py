@@ -124,6 +124,50 @@ def test_cholesky(solver, n):
     assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
 
 
+def banded_spd(n, seed, band):
+    rng = np.random.default_rng(seed)
+    A = np.zeros((n, n))
+    for off in range(1, band + 1):
+        A[np.arange(n - off), np.arange(off, n)] = rng.uniform(-0.5, 0.5, n - off) / band
+    A = A + A.T
+    A[np.arange(n), np.arange(n)] = 2.0 + rng.random(n)
+    return A
+
+
+def block_sparse_spd(n, seed):
+    """SPD with most 128x128 blocks zero: dense diagonal blocks plus a few far
+    off-diagonal ones (their fill-in creates more nonzero blocks below)."""
+    rng = np.random.default_rng(seed)
+    nb = (n + 127) // 128
+    X = np.zeros((n, n))
+    for i in range(nb):
+        for j in [i] + list(rng.choice(nb, 2)):
+            r, c = slice(128 * i, min(n, 128 * i + 128)), slice(128 * j, min(n, 128 * j + 128))
+            X[r, c] = rng.standard_normal((X[r, c].shape)) * (rng.random(X[r, c].shape) < 0.2)
+    return sym(X @ X.T / 64.0 + np.eye(n))
+
+
+@pytest.mark.parametrize("n", [300, 1100, 2100])
+@pytest.mark.parametrize("kind", ["band1", "band40", "blocks"])
+def test_cholesky_zero_blocks(solver, n, kind):
+    """Banded and block-sparse matrices: the updates skip tiles whose operand blocks
+    are zero; the factor still matches A to the dense bound and keeps L's zero blocks."""
+    A = block_sparse_spd(n, n) if kind == "blocks" else banded_spd(n, n, int(kind[4:]))
+    L, info, logdet = solver.cholesky(to_dev(A))
+    L = to_host(L)
+    assert info == 0
+    assert np.all(np.triu(L, 1) == 0)
+    back = np.abs(L @ L.T - A)
+    bound = 4 * n * EPS * (np.abs(L) @ np.abs(L.T)) + 1e-300
+    assert np.all(back <= bound), np.max(back / bound)
+    ref = np.linalg.cholesky(A)
+    assert np.max(np.abs(L - ref)) <= 1e-12 * np.max(np.abs(ref))
+    if kind.startswith("band"):
+        assert np.all(np.tril(L, -int(kind[4:]) - 1) == 0)  # no fill outside the band
+    sign, ld = np.linalg.slogdet(A)
+    assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
+
+
 @pytest.mark.parametrize("n,bad", [(5, 3), (300, 200), (1100, 1030), (130, 129)])
 def test_cholesky_reports_first_bad_pivot(solver, n, bad):
     A = np.eye(n)
