@@ -12,9 +12,8 @@ config.speedup_vs_fp64), and so is FP64 with the sparse product
 (config.fp64_sparse_product_s).
 
 Extra objects on the same line:
-  roofline      the dominant work, the FP64 Cholesky of each line-search trial point:
-                n^3/3 algorithmic flops / mean factorisation time from HIP events
-                around the factorisations
+  roofline      W = A^-1, the largest dense contraction of an iteration: 2n^3/3
+                algorithmic flops / mean W time from HIP events around the W phase
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
                 from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
   serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
@@ -39,10 +38,9 @@ sys.path.insert(0, ROOT)
 # dense MFMA peaks; BF16x3 spends three BF16 products per algorithmic product, so its
 # peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
-# HBM bytes per trial factorisation at n = 10^4 (FP64 in every form), from FETCH_SIZE and
-# WRITE_SIZE counter runs scaled by a 1 GiB plain-copy calibration
-# (profiles/traffic_factorisation_chain10k.md)
-FACTORISATION_TRAFFIC_BYTES = 11846283223
+# HBM bytes per W = A^-1 of the mixed forms at n = 10^4, from FETCH_SIZE and WRITE_SIZE
+# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_w_bf16x6_chain10k.md)
+W_TRAFFIC_BYTES = 24674226022
 
 
 def log(*a):
@@ -404,18 +402,24 @@ def main():
     solves = args.steps * len(lams)
     value = elapsed / solves
 
-    # roofline of the dominant work, the line search's FP64 Cholesky of each trial
-    # point (potrf_lower: leaf_potrf_kernel steps and gemm_f64_kernel updates):
-    # n^3/3 algorithmic flops per factorisation, HIP events on the solve's stream
-    # around each round's factorisations alone
+    # roofline: W = A^-1, the largest dense contraction of an iteration (2 n^3/3
+    # algorithmic flops: triangular inverse n^3/3 + V^T V n^3/3), HIP events on the
+    # solve's stream around the W phase (glasso_info.time_ms[1]).  The line search's
+    # trial factorisations take about as long, but they are a dependent chain of
+    # leaf steps plus updates that skip the factor's zero blocks, so their flop count
+    # depends on the matrix; they are reported in phases.line_search.
     iters = sum(r.iterations for r in results)
     trials = sum(r.ls_trials for r in results)
+    w_ms = sum(r.time_ms[1] for r in results)
+    # mixed forms: W with FP32 accuracy from six BF16 products per pair (BF16x6)
+    w_peak = PEAK_TFLOPS["fp64"] if args.precision == "fp64" else 2500.0 / 6.0
+    w_s = w_ms / 1000.0 / iters
+    w_tf = (2.0 / 3.0) * float(n) ** 3 / w_s / 1e12
+    achieved, peak = w_tf, w_peak
+    kernel = ("W = A^-1 from the FP64 factor: FP64 trtri + LAUUM" if args.precision == "fp64" else
+              "W = A^-1 with FP32 accuracy: tri_init_bf16x6_kernel + gemm_bf16x6_tri_kernel<1>/<2> (V = inv(L)) "
+              "+ gemm_bf16x6_nt_kernel (V^T V), six BF16 MFMA products per pair")
     fact_ms = sum(r.time_ms[6] for r in results)
-    avg_fact_s = fact_ms / 1000.0 / trials
-    achieved = float(n) ** 3 / 3.0 / avg_fact_s / 1e12
-    peak = PEAK_TFLOPS["fp64"]
-    kernel = ("trial-point Cholesky potrf_lower: leaf_potrf_kernel (128-column steps) and "
-              "gemm_f64_kernel<0,0,0,*> (updates), FP64 MFMA")
     # A Z A: the sampled sparse product wherever the iterate's rows are short, else the
     # GEMM pair (2 launches, 3 n^3 algorithmic flops: A Z 2n^3, tril((A Z) A) n^3)
     gemm_launches = 2 * sum(r.aza_gemm_products for r in results)
@@ -437,19 +441,15 @@ def main():
     # events: W = A^-1 (2 n^3/3 flops per iteration: triangular inverse + V^T V),
     # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
     # elementwise passes sit in the same window), A Z A (above)
-    w_ms = sum(r.time_ms[1] for r in results)
     ls_ms = sum(r.time_ms[4] for r in results)
-    # mixed forms: W with FP32 accuracy from six BF16 products per pair (BF16x6)
-    w_peak = PEAK_TFLOPS["fp64"] if args.precision == "fp64" else 2500.0 / 6.0
-    w_tf = (2.0 / 3.0) * float(n) ** 3 * iters / (w_ms / 1000.0) / 1e12
-    ls_tf = float(n) ** 3 / 3.0 * trials / (ls_ms / 1000.0) / 1e12
     phases = {"inverse_W": {"ms_per_iteration": w_ms / iters, "achieved_tflops": w_tf, "peak_tflops": w_peak,
                             "frac": w_tf / w_peak,
                             "precision": "fp64" if args.precision == "fp64" else
                             "FP32-accurate BF16x6 while iterating (peak: BF16 / 6), FP64 re-check before stopping"},
-              "line_search": {"ms_per_trial": ls_ms / trials, "achieved_tflops": ls_tf,
-                              "peak_tflops": PEAK_TFLOPS["fp64"], "frac": ls_tf / PEAK_TFLOPS["fp64"],
-                              "precision": "fp64 (Cholesky of each trial point)"},
+              "line_search": {"ms_per_trial": ls_ms / trials,
+                              "factorisation_ms_per_trial": fact_ms / trials,
+                              "precision": "fp64 (Cholesky of each trial point; update tiles over zero "
+                                           "blocks of the factor are skipped)"},
               "AZA": aza}
     if not args.no_fp64_ref and args.precision != "fp64":
         # FP64 plain: FP64 throughout with the paper's dense products
@@ -486,10 +486,10 @@ def main():
         "config": config,
         "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": FACTORISATION_TRAFFIC_BYTES, "traffic_unit": "B",
-                     "kernel": kernel,
-                     "avg_launch_ms": avg_fact_s * 1000.0, "launch_unit": "one trial factorisation",
-                     "launches": trials},
+                     "frac": achieved / peak,
+                     "traffic": W_TRAFFIC_BYTES if args.precision != "fp64" else None, "traffic_unit": "B",
+                     "kernel": kernel, "avg_launch_ms": w_s * 1000.0,
+                     "launch_unit": "one W per iteration (its kernels together)", "launches": iters},
     }
     line["covariance"] = bench_covariance(g, torch, dev)
     if args.support:
