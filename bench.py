@@ -12,8 +12,9 @@ config.speedup_vs_fp64), and so is FP64 with the sparse product
 (config.fp64_sparse_product_s).
 
 Extra objects on the same line:
-  roofline      W = A^-1, the largest dense contraction of an iteration: 2n^3/3
-                algorithmic flops / mean W time from HIP events around the W phase
+  roofline      V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel), the largest dense
+                contraction: n^3/3 algorithmic flops / mean launch time from HIP events
+                around that launch
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
                 from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
   serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
@@ -38,9 +39,10 @@ sys.path.insert(0, ROOT)
 # dense MFMA peaks; BF16x3 spends three BF16 products per algorithmic product, so its
 # peak in algorithmic flops is a third of the 2.5 PFLOP/s BF16 figure
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
-# HBM bytes per W = A^-1 of the mixed forms at n = 10^4, from FETCH_SIZE and WRITE_SIZE
-# counter runs scaled by a 1 GiB plain-copy calibration (profiles/traffic_w_bf16x6_chain10k.md)
-W_TRAFFIC_BYTES = 24674226022
+# HBM bytes per V^T V launch (gemm_bf16x6_nt_kernel) at n = 10^4, from FETCH_SIZE and
+# WRITE_SIZE counter runs scaled by a 1 GiB plain-copy calibration
+# (profiles/traffic_w_bf16x6_chain10k.md)
+VTV_TRAFFIC_BYTES = 11511834624
 
 
 def log(*a):
@@ -402,23 +404,21 @@ def main():
     solves = args.steps * len(lams)
     value = elapsed / solves
 
-    # roofline: W = A^-1, the largest dense contraction of an iteration (2 n^3/3
-    # algorithmic flops: triangular inverse n^3/3 + V^T V n^3/3), HIP events on the
-    # solve's stream around the W phase (glasso_info.time_ms[1]).  The line search's
-    # trial factorisations take about as long, but they are a dependent chain of
-    # leaf steps plus updates that skip the factor's zero blocks, so their flop count
-    # depends on the matrix; they are reported in phases.line_search.
+    # roofline: V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel), the largest dense
+    # contraction that skips nothing: n^3/3 algorithmic flops per launch (the lower
+    # triangle of V^T V, V = inv(L) lower), one launch per iteration after the diagonal
+    # start, HIP events on the solve's stream around that launch alone
+    # (glasso_info.time_ms[7]).  The rest of W (the doubling inverse) and the line
+    # search's factorisations skip products over zero blocks of the factor, so their
+    # flop counts depend on the matrix; they are reported as times in phases.
     iters = sum(r.iterations for r in results)
     trials = sum(r.ls_trials for r in results)
     w_ms = sum(r.time_ms[1] for r in results)
-    # mixed forms: W with FP32 accuracy from six BF16 products per pair (BF16x6)
-    w_peak = PEAK_TFLOPS["fp64"] if args.precision == "fp64" else 2500.0 / 6.0
-    w_s = w_ms / 1000.0 / iters
-    w_tf = (2.0 / 3.0) * float(n) ** 3 / w_s / 1e12
-    achieved, peak = w_tf, w_peak
-    kernel = ("W = A^-1 from the FP64 factor: FP64 trtri + LAUUM" if args.precision == "fp64" else
-              "W = A^-1 with FP32 accuracy: tri_init_bf16x6_kernel + gemm_bf16x6_tri_kernel<1>/<2> (V = inv(L)) "
-              "+ gemm_bf16x6_nt_kernel (V^T V), six BF16 MFMA products per pair")
+    vtv_s = sum(r.time_ms[7] for r in results) / 1000.0 / iters
+    achieved = float(n) ** 3 / 3.0 / vtv_s / 1e12 if vtv_s > 0 else None
+    peak = 2500.0 / 6.0
+    kernel = ("gemm_bf16x6_nt_kernel: V^T V (lower triangle) of W = A^-1 with FP32 accuracy, "
+              "six BF16 MFMA products per element pair")
     fact_ms = sum(r.time_ms[6] for r in results)
     # A Z A: the sampled sparse product wherever the iterate's rows are short, else the
     # GEMM pair (2 launches, 3 n^3 algorithmic flops: A Z 2n^3, tril((A Z) A) n^3)
@@ -442,10 +442,10 @@ def main():
     # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
     # elementwise passes sit in the same window), A Z A (above)
     ls_ms = sum(r.time_ms[4] for r in results)
-    phases = {"inverse_W": {"ms_per_iteration": w_ms / iters, "achieved_tflops": w_tf, "peak_tflops": w_peak,
-                            "frac": w_tf / w_peak,
+    phases = {"inverse_W": {"ms_per_iteration": w_ms / iters,
                             "precision": "fp64" if args.precision == "fp64" else
-                            "FP32-accurate BF16x6 while iterating (peak: BF16 / 6), FP64 re-check before stopping"},
+                            "FP32-accurate BF16x6 while iterating, FP64 re-check before stopping; the doubling "
+                            "inverse skips products over zero blocks of the factor"},
               "line_search": {"ms_per_trial": ls_ms / trials,
                               "factorisation_ms_per_trial": fact_ms / trials,
                               "precision": "fp64 (Cholesky of each trial point; update tiles over zero "
@@ -486,10 +486,9 @@ def main():
         "config": config,
         "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": W_TRAFFIC_BYTES if args.precision != "fp64" else None, "traffic_unit": "B",
-                     "kernel": kernel, "avg_launch_ms": w_s * 1000.0,
-                     "launch_unit": "one W per iteration (its kernels together)", "launches": iters},
+                     "frac": achieved / peak if achieved else None,
+                     "traffic": VTV_TRAFFIC_BYTES if args.precision != "fp64" else None, "traffic_unit": "B",
+                     "kernel": kernel, "avg_launch_ms": vtv_s * 1000.0, "launches": iters},
     }
     line["covariance"] = bench_covariance(g, torch, dev)
     if args.support:

@@ -111,7 +111,8 @@ typedef struct {
   int fallback_steps; /* line searches that reached t_floor and used the cond-based step */
   double time_ms[8];  /* [0] total, [1] W = A^-1, [2] gradient pass, [3] A Z A,
                         [4] line search, [5] the two A Z A GEMM launches alone,
-                        [6] the line search's trial factorisations alone (eager
+                        [6] the line search's trial factorisations alone, [7] the
+                        V^T V launches of the FP32-accurate W alone (both: eager
                         launches only; 0 with graphs) */
   int aza_gemm_products; /* A Z A products formed by the GEMM pair; the first product
                             of a diagonal start is D Z D, formed elementwise */

@@ -200,6 +200,14 @@ struct TriBf6Params {
   int64_t sA, sB, sC, sCT;      // grid.y (group) strides, bytes
   int64_t zA, zB, zC, zCT;      // grid.z (problem) strides, bytes
   const int* skip;
+  // optional zero-block map of the factor L (ZBatch::nz layout): T21 of group g is L's
+  // rows nz_row0 + g nz_gstep.. and columns nz_col0 + g nz_gstep .. + nz_w, untouched
+  // by the earlier levels.  KCLIP 1 (A = T21): a tile whose T21 rows are zero in every
+  // panel of its K range is zero.  KCLIP 2 (B = tmp^T, tmp = T21 V11): tmp's rows are
+  // zero where T21's are, so K stops after tmp's last nonzero 64-row block.
+  const uint8_t* nz;
+  int64_t snz;
+  int nz_chunks, nz_row0, nz_col0, nz_gstep, nz_w;
 };
 
 template <int KCLIP>
@@ -224,7 +232,34 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p)
   }
   const int m0 = ti * T6, n0 = tj * T6;
   const int kbeg = (KCLIP == 1) ? n0 : 0;
-  const int kend = (KCLIP == 2) ? min(p.K, m0 + T6) : p.K;
+  int kend = (KCLIP == 2) ? min(p.K, m0 + T6) : p.K;
+  if (p.nz) {
+    const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
+    const int r0 = p.nz_row0 + (int)blockIdx.y * p.nz_gstep;  // global row of T21's row 0
+    const int c0 = p.nz_col0 + (int)blockIdx.y * p.nz_gstep;  // global column of T21's column 0
+    // every thread reads its share of the (panel, 64-row block) entries, all loads
+    // independent, then one workgroup-wide reduction
+    if (KCLIP == 1) {
+      const int q0 = (c0 + kbeg) >> 7, nq = ((c0 + kend - 1) >> 7) - q0 + 1;
+      int any = 0;
+      for (int e = tid; e < 2 * nq; e += 256)
+        any |= f[(int64_t)(q0 + (e >> 1)) * p.nz_chunks + ((r0 + m0) >> 6) + (e & 1)];
+      if (!__syncthreads_or(any)) kend = kbeg;
+    } else {
+      __shared__ int last[4];
+      const int q0 = c0 >> 7, nq = p.nz_w >> 7, nch = p.K >> 6;
+      int mine = -1;
+      for (int e = tid; e < nch * nq; e += 256) {
+        const int c = e / nq, q = q0 + e - (e / nq) * nq;
+        if (f[(int64_t)q * p.nz_chunks + (r0 >> 6) + c]) mine = max(mine, c);
+      }
+      for (int off = 32; off > 0; off >>= 1) mine = max(mine, __shfl_xor(mine, off));
+      if (lane == 0) last[wave] = mine;
+      __syncthreads();
+      const int cmax = max(max(last[0], last[1]), max(last[2], last[3]));
+      kend = min(kend, 64 * (cmax + 1));
+    }
+  }
 
   v4f acc[4][4];
 #pragma unroll
@@ -336,12 +371,25 @@ int gemm_bf16x6_lower(hipStream_t stream, int N, int K, const void* A, int64_t l
 }
 
 namespace {
+struct TriZeros {
+  const uint8_t* nz = nullptr;
+  int64_t snz = 0;
+  int chunks = 0;
+};
 int launch_tri6(hipStream_t stream, int kclip, int M, int N, int K, float alpha, const uint8_t* A, int64_t lda,
                 const uint8_t* B, int64_t ldb, uint8_t* C, int64_t ldc, uint8_t* CT, int64_t ldct, int groups,
                 int64_t sA, int64_t sB, int64_t sC, int64_t sCT, int count, int64_t zA, int64_t zB, int64_t zC,
-                int64_t zCT, const int* skip) {
+                int64_t zCT, const int* skip, const TriZeros& zr = TriZeros(), int row0 = 0, int col0 = 0,
+                int gstep = 0, int width = 0) {
   if (M % T6 || N % T6 || K % BK6) return -1;
   TriBf6Params p;
+  p.nz = zr.nz;
+  p.snz = zr.snz;
+  p.nz_chunks = zr.chunks;
+  p.nz_row0 = row0;
+  p.nz_col0 = col0;
+  p.nz_gstep = gstep;
+  p.nz_w = width;
   p.M = M;
   p.N = N;
   p.K = K;
@@ -375,8 +423,13 @@ int launch_tri6(hipStream_t stream, int kclip, int M, int N, int K, float alpha,
 }  // namespace
 
 int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_t np, void* Tv, void* Ttv, void* tmpv,
-                 int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTt, int64_t sTmp, const int* skip) {
+                 int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTt, int64_t sTmp, const int* skip,
+                 const uint8_t* nz, int64_t snz) {
   if (np % 128 || count <= 0) return np % 128 ? -1 : 0;
+  TriZeros zr;
+  zr.nz = nz;
+  zr.snz = snz;
+  zr.chunks = (int)(np / 64);
   uint8_t* T = static_cast<uint8_t*>(Tv);
   uint8_t* Tt = static_cast<uint8_t*>(Ttv);
   uint8_t* tmp = static_cast<uint8_t*>(tmpv);
@@ -394,11 +447,12 @@ int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_
     if (full > 0) {
       // tmp^T = (T21 V11)^T, one s x s tmp^T per group
       rc = launch_tri6(stream, 1, (int)s, (int)s, (int)s, 1.f, T + 6 * s * np, np, Tt, np, nullptr, 0, tmp, s, full,
-                       gs, gs, 0, 6 * s * s, count, sT, sTt, 0, sTmp, skip);
+                       gs, gs, 0, 6 * s * s, count, sT, sTt, 0, sTmp, skip, zr, (int)s, 0, (int)(2 * s), (int)s);
       if (rc) return rc;
       // V21 = -V22 tmp into T21 and, transposed, into Tt
       rc = launch_tri6(stream, 2, (int)s, (int)s, (int)s, -1.f, T + 6 * s * (np + 1), np, tmp, s, T + 6 * s * np, np,
-                       Tt + 6 * s, np, full, gs, 6 * s * s, gs, gs, count, sT, sTmp, sT, sTt, skip);
+                       Tt + 6 * s, np, full, gs, 6 * s * s, gs, gs, count, sT, sTmp, sT, sTt, skip, zr, (int)s, 0,
+                       (int)(2 * s), (int)s);
       if (rc) return rc;
     }
     const int64_t base = (int64_t)full * 2 * s;
@@ -406,11 +460,11 @@ int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_
     if (n2 > 0) {
       rc = launch_tri6(stream, 1, (int)n2, (int)s, (int)s, 1.f, T + 6 * ((base + s) * np + base), np,
                        Tt + 6 * (base * np + base), np, nullptr, 0, tmp, n2, 1, 0, 0, 0, 0, count, sT, sTt, 0, sTmp,
-                       skip);
+                       skip, zr, (int)(base + s), (int)base, 0, (int)s);
       if (rc) return rc;
       rc = launch_tri6(stream, 2, (int)n2, (int)s, (int)n2, -1.f, T + 6 * (base + s) * (np + 1), np, tmp, n2,
                        T + 6 * ((base + s) * np + base), np, Tt + 6 * (base * np + base + s), np, 1, 0, 0, 0, 0, count,
-                       sT, sTmp, sT, sTt, skip);
+                       sT, sTmp, sT, sTt, skip, zr, (int)(base + s), (int)base, 0, (int)s);
       if (rc) return rc;
     }
   }

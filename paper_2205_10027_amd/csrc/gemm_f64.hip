@@ -148,20 +148,21 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
   if (p.nz) {
     // the tile adds A B^T only if some panel of its K range has a nonzero block in
     // both its A rows and its B rows; otherwise C stays as it is
+    // one thread per panel of the K range, all loads independent
     const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
     const int ca = (p.nz_row0 + m0) >> 6, cb = (p.nz_col0 + n0) >> 6;
-    bool any = false;
-    for (int s = p.nz_k0 >> 7; s < (p.nz_k0 + p.K) >> 7 && !any; ++s) {
+    int any = 0;
+    for (int s = (p.nz_k0 >> 7) + tid; s < (p.nz_k0 + p.K) >> 7; s += 256) {
       const uint8_t* fs = f + (int64_t)s * p.nz_chunks;
-      bool a = false, b = false;
+      int a = 0, b = 0;
 #pragma unroll
       for (int c = 0; c < T / 64; ++c) {
-        a = a || fs[ca + c] != 0;
-        b = b || fs[cb + c] != 0;
+        a |= fs[ca + c];
+        b |= fs[cb + c];
       }
-      any = a && b;
+      any |= a && b;
     }
-    if (!any) return;
+    if (!__syncthreads_or(any)) return;
   }
 
   const double* A = p.A + (int64_t)blockIdx.y * p.sA + (int64_t)blockIdx.z * p.zA;

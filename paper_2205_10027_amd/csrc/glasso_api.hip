@@ -139,7 +139,7 @@ struct glasso_handle_s {
   int device = 0;
   Workspace ws;
   HostMirror hm;
-  hipEvent_t ev[10] = {};
+  hipEvent_t ev[12] = {};
   hipStream_t cap = nullptr;  // capture stream (graphs option)
   Graphs graphs;
   void* small_base = nullptr;  // workspace of the persistent small-problem solver
@@ -349,7 +349,8 @@ glasso_err factor_all(glasso_handle h, hipStream_t st) {
 
 // W (lower) = A^{-1} with FP32 accuracy for every problem with skip == 0, from its
 // factor in w.L (left unchanged) and diagonal-block inverses.
-glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
+// vev (optional): two events recorded around the V^T V launch alone
+glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip, hipEvent_t* vev = nullptr) {
   // W = A^-1 with FP32 accuracy on the BF16 matrix cores: V = inv(L) by recursive
   // doubling and W = V^T V, every operand an exact three-part bf16 split of an FP32
   // value (6 bytes per element), six products per element pair.  V split in X,
@@ -359,8 +360,15 @@ glasso_err inverse_f32(Workspace& w, hipStream_t st, const int* skip) {
   uint8_t* Vs = reinterpret_cast<uint8_t*>(w.X);
   uint8_t* Vts = reinterpret_cast<uint8_t*>(w.P);
   uint8_t* tmp = Vts + nn * 6;
-  K_TRY(trtri_bf16x6(st, w.L, w.Dinv, w.np, Vs, Vts, tmp, w.count, nn, w.np * TILE, zb, zb, zb, skip));
+  // one problem with one trial slot: the map holds the last factorisation, which is
+  // L's (the accepted trial point, or the start's factor)
+  const FactorBatch fb = factor_batch(w);
+  const bool map = w.count == 1 && w.slots == 1;
+  K_TRY(trtri_bf16x6(st, w.L, w.Dinv, w.np, Vs, Vts, tmp, w.count, nn, w.np * TILE, zb, zb, zb, skip,
+                     map ? fb.nz : nullptr, fb.snz));
+  if (vev) HIP_TRY(hipEventRecord(vev[0], st));
   K_TRY(gemm_bf16x6_lower(st, (int)w.np, (int)w.np, Vts, w.np, Vts, w.np, w.W, w.np, 1, w.count, zb, zb, nn, skip));
+  if (vev) HIP_TRY(hipEventRecord(vev[1], st));
   return GLASSO_OK;
 }
 
@@ -684,7 +692,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
     if (w_mixed) {
-      e2 = inverse_f32(w, s, w.skip32);
+      e2 = inverse_f32(w, s, w.skip32, timed ? h->ev + 10 : nullptr);
       if (e2) return e2;
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
@@ -821,6 +829,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     HIP_TRY(hipStreamSynchronize(st));
     phase[1] += elapsed(h->ev[0], h->ev[1]);
     phase[2] += elapsed(h->ev[1], h->ev[2]);
+    if (w_mixed && !exact_w && !graphs) phase[7] += elapsed(h->ev[10], h->ev[11]);
     // a problem that would stop on an FP32-accurate W is re-checked with FP64 W first
     std::vector<int> mark(count, 0);
     int nmark = 0;

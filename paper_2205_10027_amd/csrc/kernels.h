@@ -59,8 +59,11 @@ int split_bf16x2(hipStream_t stream, const double* src, void* dst, int64_t count
 // doubling from the factor L (FP64, lower, intact) and its diagonal-block inverses
 // Dinv; tmp needs np^2/4 split elements.  Strides: sL, sD elements; sT, sTt, sTmp
 // bytes per problem.
+// nz (may be null): the zero-block map of L's factorisation (FactorBatch::nz layout,
+// snz bytes per problem); products over L's zero blocks are then skipped.
 int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_t np, void* T, void* Tt, void* tmp,
-                 int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTt, int64_t sTmp, const int* skip);
+                 int count, int64_t sL, int64_t sD, int64_t sT, int64_t sTt, int64_t sTmp, const int* skip,
+                 const uint8_t* nz = nullptr, int64_t snz = 0);
 // C = tril(A B^T) in FP64 from three-part splits (six BF16 products, FP32 accuracy);
 // N x N output, K inner; k_from_row starts tile row m0's K range at m0.  Strides of
 // the batch: bytes for A and B, elements for C.

@@ -166,3 +166,18 @@ def test_graphs_replay_the_choice(g):
     assert (graph.iterations, graph.aza_gemm_products, graph.aza_sparse_products) == \
            (eager.iterations, eager.aza_gemm_products, eager.aza_sparse_products)
     assert np.array_equal(to_host(graph.A), to_host(eager.A))
+
+
+@pytest.mark.parametrize("n", [300, 1100])
+def test_zero_block_inverse_is_exact(g, n):
+    """A single problem with one trial slot (ls_width=1) skips the FP32-accurate inverse's
+    products over zero blocks of the factor; with two slots it does not.  Skipped products
+    are exact zeros, so both runs agree bit for bit (chain trial points are banded)."""
+    S, _ = synth.chain_problem(n, 5 * n, 0)
+    one = g.Solver(precision="bf16x3", ls_width=1).solve(to_dev(S), 0.2, 1e-6)
+    two = g.Solver(precision="bf16x3", ls_width=2).solve(to_dev(S), 0.2, 1e-6)
+    assert one.status == two.status == g.CONVERGED
+    assert (one.iterations, one.ls_trials) == (two.iterations, two.ls_trials)
+    assert np.array_equal(to_host(one.A), to_host(two.A))
+    assert np.array_equal(to_host(one.W), to_host(two.W))
+    assert one.objective == two.objective
