@@ -642,6 +642,10 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       last_trials(count, 1), since(count, 0);
   std::vector<double> tb(count, o.t0);  // next step size of each problem's backtracking sequence
   const bool sparse_on = o.dense_product == 0;
+  // this iteration's product tries the sparse form (eager launches skip it when every
+  // active problem has more than SPARSE_KA nonzeros per row on average, so some row
+  // is surely too long; a captured graph always holds both forms)
+  bool sparse_now = sparse_on;
   PassBatch pb;
   pb.count = count;
   pb.sS = sS;
@@ -722,7 +726,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
-    return precond_product(w, s, o.precision, w.skip, n, sparse_on, timed ? h->ev + 5 : nullptr, z_split != nullptr);
+    return precond_product(w, s, o.precision, w.skip, n, sparse_now, timed ? h->ev + 5 : nullptr, z_split != nullptr);
   };
   auto trial = [&](hipStream_t s, bool timed) -> glasso_err {  // a4, a5
     glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, slots);
@@ -867,6 +871,12 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       K_TRY(diag_product(st, w.A, w.Z, w.P, np, count, w.skip));
       HIP_TRY(hipEventRecord(h->ev[6], st));
     } else {
+      sparse_now = sparse_on;
+      if (sparse_on && !graphs) {
+        sparse_now = false;
+        for (int b = 0; b < count && !sparse_now; ++b)
+          sparse_now = active[b] && hscal(h, b, SC_NNZ_A) <= (double)SPARSE_KA * (double)n;
+      }
       if (graphs) HIP_TRY(hipEventRecord(h->ev[5], st));
       e = run(&h->graphs.prod, prod);
       if (e) return e;
@@ -968,7 +978,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     for (int b = 0; b < count; ++b) {
       if (!prod_b[b]) continue;
       prod_b[b] = 0;
-      const bool dense = !sparse_on || hscal(h, b, SC_DENSE_PRODUCT) != 0.0;
+      const bool dense = !sparse_now || hscal(h, b, SC_DENSE_PRODUCT) != 0.0;
       (dense ? gemm_products[b] : sparse_products[b]) += 1;
       pair_ran = pair_ran || dense;
     }
