@@ -250,7 +250,7 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
                               double* sums, void* stream);
 
 /* The preconditioned product as a solve forms it when dense_product is 0 (the
- * sampled sparse form; the paper's design forms A Z A densely, Sec. 4): P_ij =
+ * sampled sparse form; the paper's design forms A Z A densely, Sec. 3.3.3): P_ij =
  * (A Z A)_ij in FP64 for every (i, j) with GM_ij != 0 and P_ij = 0 elsewhere, n x n
  * full symmetric (the trial point, eq. d_sol, reads P only there).  The sparse
  * form serves the call when every row of A has at most 16 nonzeros and every row
