@@ -41,7 +41,9 @@ def sparse_sym(n, seed, density=0.1, diag=2.0):
 
 def support_mismatch(A_gpu, A_ref, g_ref, lam, eps=1e-8):
     """Entries whose zero/nonzero status differs, except those within eps of the
-    threshold in the reference solution: |A*_ij| <= eps or ||g*_ij| - lam| <= eps."""
+    threshold in the reference solution: a nonzero with |A*_ij| <= eps, or a zero
+    with ||g*_ij| - lam| <= eps."""
     diff = (A_gpu != 0) != (A_ref != 0)
-    exempt = (np.abs(A_ref) <= eps) | (np.abs(np.abs(g_ref) - lam) <= eps)
+    nz = A_ref != 0
+    exempt = (nz & (np.abs(A_ref) <= eps)) | (~nz & (np.abs(np.abs(g_ref) - lam) <= eps))
     return int(np.sum(diff & ~exempt))

@@ -138,8 +138,53 @@ def check_diagonal_solution(orc, n=15, seed=7):
     return r.iterations == 0 and np.allclose(r.A, A_ref, rtol=1e-14, atol=0)
 
 
+def check_cond_fallback(orc, seeds=range(4)):
+    """The line-search fallback step of the Sec. 6 settings, t = (0.9 / cond A)^2,
+    pinned to the mathematics rather than to its own formula:
+      * closed forms: diag(1, 4) has cond 4, so t = (0.9/4)^2; any multiple of
+        the identity has cond 1, so t = 0.81;
+      * it lies below (beta/gamma)^2 with beta, gamma the extreme singular values of
+        A from an SVD (the step bound of the decrease lemma, Sec. 5.2), by the factor
+        0.81 exactly;
+      * taken from a real iterate of a solve, the trial point at that t is PD and
+        lowers F (the property the paper assumes of this step)."""
+    t = orc.cond_fallback_step(np.diag([1.0, 4.0]))
+    if abs(t - (0.9 / 4.0) ** 2) > 1e-15:
+        return False
+    if abs(orc.cond_fallback_step(3.0 * np.eye(5)) - 0.81) > 1e-14:
+        return False
+    for seed in seeds:
+        rng = np.random.default_rng(100 + seed)
+        X = rng.normal(size=(7, 7))
+        A = X @ X.T + 0.05 * np.eye(7)
+        sv = np.linalg.svd(A, compute_uv=False)
+        bound = (sv[-1] / sv[0]) ** 2
+        t = orc.cond_fallback_step(A)
+        if not (0.0 < t < bound) or abs(t / bound - 0.81) > 1e-8:
+            return False
+    for seed in seeds:
+        S = random_psd(12, 6, 40 + seed)
+        lam = 0.1
+        A = np.diag(1.0 / (np.diag(S) + lam))
+        for _ in range(3):  # a few plain pISTA iterations give a non-diagonal iterate
+            A = orc.pista(S, lam, 0.0, A0=A, max_iter=1).A
+        g = orc.gradient(S, np.linalg.inv(A))
+        M = orc.free_set_mask(A, g, lam)
+        G = orc.sign_guess(A, g)
+        C = orc.c_matrix(A, lam)
+        B = orc.b_matrix(A, g, G, M, C, lam)
+        t = orc.cond_fallback_step(A)
+        At = orc.trial_point(A, M, B, C, t)
+        if np.linalg.eigvalsh(At)[0] <= 0:
+            return False
+        if not f_direct(S, At, lam) < f_direct(S, A, lam):
+            return False
+    return True
+
+
 def all_pins(orc):
     return {
+        "cond_fallback": check_cond_fallback(orc),
         "scalar_lemma": check_scalar_lemma(orc, trials=40),
         "n2_closed_form": check_n2_closed_form(orc, seeds=range(3)),
         "kkt_invariants": check_kkt_invariants(orc),

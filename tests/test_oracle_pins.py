@@ -218,7 +218,7 @@ def test_objective_and_change_direct():
     assert abs(dF - (pins.f_direct(S, r.A, lam) - pins.f_direct(S, A, lam))) < 1e-10
 
 
-# ------------------------------------------------------------------ convergence (Sec. 4)
+# ------------------------------------------------------------------ convergence (Sec. 5)
 def test_monotone_decrease_and_pd():
     S, _ = synth.chain_problem(60, 30, 2)
     lam = 0.15
@@ -251,12 +251,25 @@ def test_fixed_point():
 
 
 def test_line_search_floor_fallback():
-    """Below t = 1e-4 the step falls back to (0.9/cond A)^2 (Sec. 5)."""
-    rng = np.random.default_rng(3)
-    X = rng.normal(size=(6, 6))
-    A = X @ X.T + 0.1 * np.eye(6)
-    ev = np.linalg.eigvalsh(A)
-    assert abs(oracle.cond_fallback_step(A) - (0.9 * ev[0] / ev[-1]) ** 2) < 1e-15
+    """Below t = 1e-4 the step falls back to (0.9/cond A)^2 (Sec. 6): closed forms,
+    the eigenvalue bound of the decrease lemma (Sec. 5.2) from an SVD, and a PD,
+    decreasing trial point at that step."""
+    assert pins.check_cond_fallback(oracle)
+
+
+def test_fallback_solve_reaches_the_minimiser():
+    """A solve that takes the fallback at every line search (t_floor above every
+    step that succeeds) still converges to the same minimiser: same F and support
+    as the plain solve, and the optimality conditions hold."""
+    S = pins.random_psd(14, 7, 12)
+    lam = 0.12
+    ref = oracle.pista(S, lam, 1e-8, max_iter=3000)
+    r = oracle.pista(S, lam, 1e-7, max_iter=20000, t_floor=0.99, t0=0.5)
+    assert ref.status == r.status == oracle.CONVERGED
+    assert sum(h.get("fallback", False) for h in r.history) == r.iterations
+    assert abs(r.objective - ref.objective) <= 1e-11 * abs(ref.objective)
+    assert np.array_equal(r.A != 0, ref.A != 0)
+    assert pins.kkt_violation(S, r.A, lam) < 1e-6
 
 
 def test_iteration_cap_status():
@@ -325,6 +338,9 @@ MUTANTS = {
     "diag_not_penalised_init": dict(initial_iterate=lambda S, lam: np.diag(1.0 / np.diag(S))),
     "objective_change_sign": dict(objective_change=lambda S, A, At, L, Lt, lam:
                                   -opista.objective_change(S, A, At, L, Lt, lam)),
+    "cond_fallback_always_one": dict(cond_fallback_step=lambda A, factor=0.9: 1.0),
+    "cond_fallback_unsquared": dict(cond_fallback_step=lambda A, factor=0.9:
+                                    factor * np.linalg.eigvalsh(A)[0] / np.linalg.eigvalsh(A)[-1]),
 }
 
 
@@ -333,7 +349,7 @@ def test_mutant_is_caught(name):
     m = _mutant(**MUTANTS[name])
     caught = False
     for check in (pins.check_scalar_lemma, pins.check_diagonal_solution, pins.check_n2_closed_form,
-                  pins.check_kkt_invariants, pins.check_against_gista):
+                  pins.check_kkt_invariants, pins.check_against_gista, pins.check_cond_fallback):
         try:
             ok = check(m) if check is not pins.check_scalar_lemma else check(m, trials=40)
         except Exception:
