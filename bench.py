@@ -205,7 +205,7 @@ def bench_covariance(g, torch, dev, m=5000, n=10000, reps=5):
 
 def support_mcc(A_est, A_true):
     """Matthews correlation coefficient of the estimated sparsity pattern over the
-    pairs i < j (Sec. 5.3): positive = nonzero entry."""
+    pairs i < j (Sec. 6.3): positive = nonzero entry."""
     import numpy as np
 
     iu = np.triu_indices(A_true.shape[0], 1)
@@ -219,7 +219,7 @@ def support_mcc(A_est, A_true):
 
 def bench_support(g, torch, dev, n=3000, ms=(750, 1500, 3000, 6000), kinds=("chain", "random", "planar")):
     """Support recovery as a function of lambda and the sample count (the
-    experiment of Sec. 5.3, Fig. 2, whose values the paper text does not carry):
+    experiment of Sec. 6.3, Fig. 2, whose values the paper text does not carry):
     for each ground truth and sample count, S from the samples on the device and
     one batched FP64 solve over 10 lambdas lambda_max 2^(-k/2), k = 1 .. 10, tol 1e-5;
     MCC of each solution's pattern.  (The paper stops this experiment at 1e-2 of its

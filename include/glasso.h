@@ -1,13 +1,13 @@
 /*
  * libglasso -- pISTA for the graphical lasso on AMD Instinct MI355X (gfx950).
  *
- * Problem (Shalom, Treister & Yavneh, arXiv 2205.10027, Sec. 2.1, eqs. log_MLE
+ * Problem (Shalom, Treister & Yavneh, arXiv 2205.10027, Sec. 3.1, eqs. log_MLE
  * and sparse_obj):
  *
  *     minimise  F(A) = -log det A + tr(S A) + lambda * sum_{i,j} |A_ij|   over A > 0,
  *
  * the diagonal being penalised.  The solver is Algorithm 1 (pISTA) with the
- * initialisation, line search and stopping rule of Sec. 5.
+ * initialisation, line search and stopping rule of Sec. 6.
  *
  * Conventions for every entry point below
  *  - Matrices are dense, FP64, n x n, row-major with leading dimension n, in
@@ -41,7 +41,7 @@ typedef enum {
 } glasso_err;
 
 typedef enum {
-  GLASSO_CONVERGED = 0, /* ||Z||_1 <= tol * ||A||_1 (stopping rule, Sec. 5) */
+  GLASSO_CONVERGED = 0, /* ||Z||_1 <= tol * ||A||_1 (stopping rule, Sec. 6) */
   GLASSO_MAX_ITER = 1,  /* max_iter accepted steps without meeting tol */
   GLASSO_LS_FAILED = 2  /* no step size down to t_min was PD with a strict decrease */
 } glasso_status;
@@ -60,8 +60,8 @@ typedef struct {
   int precision;   /* glasso_precision; default GLASSO_FP64 */
   int max_iter;    /* accepted steps before GLASSO_MAX_ITER; default 500 */
   double t0;       /* first step size of every line search; default 1 (Alg. 1) */
-  double shrink;   /* backtracking factor; default 0.5 (Sec. 3.3.2) */
-  double t_floor;  /* below it, t = min(t, (0.9/cond A)^2) (Sec. 5); default 1e-4 */
+  double shrink;   /* backtracking factor; default 0.5 (Sec. 4.3.2) */
+  double t_floor;  /* below it, t = min(t, (0.9/cond A)^2) (Sec. 6); default 1e-4 */
   double t_min;    /* the line search fails below it; default 1e-12 */
   int warm_start;  /* nonzero: A holds the starting iterate (Alg. 1 takes A^(0)) */
   int tile_policy; /* FP64 GEMM launches (Cholesky updates, triangular inverse, LAUUM,
@@ -101,7 +101,7 @@ typedef struct {
 
 typedef struct {
   double objective; /* F(A) of the returned A */
-  double kkt_rel1;  /* ||Z||_1 / ||A||_1, Z the minimum-norm subgradient (Sec. 3.3.1, Sec. 5) */
+  double kkt_rel1;  /* ||Z||_1 / ||A||_1, Z the minimum-norm subgradient (Sec. 4.3.1, Sec. 6) */
   double kkt_fro;   /* ||Z||_F (the measure the paper's tables report) */
   double kkt_max;   /* max |Z_ij| */
   int64_t nnz;      /* nonzeros of the returned A (full count, diagonal included) */
@@ -139,7 +139,7 @@ glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes);
 
 /* Many small problems (n <= GLASSO_SMALL_MAX_N each, sizes may differ) in ONE
  * persistent launch: each workgroup takes problems i, i + G, i + 2G, ... (G =
- * min(count, 512) workgroups) and runs the whole of Alg. 1 (Sec. 5 settings,
+ * min(count, 512) workgroups) and runs the whole of Alg. 1 (Sec. 6 settings,
  * FP64 for every step whatever opt.precision says) for each on the device, with no
  * host round trip between iterations or trials.  Arguments, outputs and errors as
  * for glasso_solve_batched (A[i] is also the starting iterate with warm_start);
@@ -161,7 +161,7 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
  * Errors: INVALID_ARG (n < 1, count < 1), OOM, HIP. */
 glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, void* stream);
 
-/* Solve the graphical lasso for one S (Alg. 1 of the paper, Sec. 5 settings).
+/* Solve the graphical lasso for one S (Alg. 1 of the paper, Sec. 6 settings).
  *   S      n x n empirical covariance (device, read-only, lower triangle read)
  *   lambda regularisation weight (alpha in the paper), > 0
  *   tol    stopping tolerance on ||Z||_1 / ||A||_1, > 0
@@ -200,7 +200,7 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
  * on its own.  They use the handle's workspace and synchronise the stream.
  * -------------------------------------------------------------------------- */
 
-/* Sample covariance, the solver's input (Sec. 2.1, eq. empirical_cov):
+/* Sample covariance, the solver's input (Sec. 3.1, eq. empirical_cov):
  * S = (1/m) sum_i (y_i - mu)(y_i - mu)^T over the m samples y_i, the rows of Y
  * (device, m x n, row-major, ld n), with mu = (1/m) sum_i y_i when center != 0
  * and mu = 0 otherwise (samples of known zero mean).  S (device, n x n, full
@@ -212,7 +212,7 @@ glasso_err glasso_covariance(glasso_handle h, const double* Y, int64_t m, int64_
                              void* stream);
 
 /* Lower Cholesky factor L of SPD A (the PD test of condition t_cond_pd,
- * Sec. 3.3.2): L (n x n, output) gets L in its lower triangle and zeros above.
+ * Sec. 4.3.2): L (n x n, output) gets L in its lower triangle and zeros above.
  * *info = 0 on success, else the 1-based column of the first non-positive or
  * non-finite pivot.  *logdet (may be NULL) = 2 sum log L_ii (eq. log_MLE). */
 glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* L, int64_t* info,
@@ -225,7 +225,7 @@ glasso_err glasso_cholesky(glasso_handle h, const double* A, int64_t n, double* 
  * Errors: NOT_PD when A is not PD. */
 glasso_err glasso_inverse(glasso_handle h, const double* A, int64_t n, double* W, void* stream);
 
-/* One gradient pass (Sec. 3.1 eqs. grad_hessian, free_set, M; eq. G+):
+/* One gradient pass (eq. grad_hessian of Sec. 3.2; eqs. free_set, M of Sec. 4.1; eq. G+):
  * g = S - W, M = (A != 0) | (|g| > lambda), G = sign(A) where A != 0 else
  * -sign(g); outputs Z = (g + lambda G) (.) M (n x n, full symmetric) and
  * GM = G (.) M (n x n int8).  kkt (host, 4 doubles, may be NULL) receives
@@ -250,7 +250,7 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
                               double* sums, void* stream);
 
 /* The preconditioned product as a solve forms it when dense_product is 0 (the
- * sampled sparse form; the paper's design forms A Z A densely, Sec. 3.3.3): P_ij =
+ * sampled sparse form; the paper's design forms A Z A densely, Sec. 4.3.3): P_ij =
  * (A Z A)_ij in FP64 for every (i, j) with GM_ij != 0 and P_ij = 0 elsewhere, n x n
  * full symmetric (the trial point, eq. d_sol, reads P only there).  The sparse
  * form serves the call when every row of A has at most 16 nonzeros and every row

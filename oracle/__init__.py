@@ -9,7 +9,7 @@ import it.  The product path never calls it and shares no code with it.
 Every function is pinned by tests under tests/ (closed forms, KKT invariants,
 an independent G-ISTA solve, brute force on tiny inputs, equivariances and
 mutation tests).  The trajectory after the line-search fallback (cond-based t,
-Sec. 5) is parity unpinned: the GPU estimates cond(A) by power iteration while
+Sec. 6) is parity unpinned: the GPU estimates cond(A) by power iteration while
 this oracle computes it exactly; the final solution stays pinned by KKT.
 """
 from .reference import (  # noqa: F401

@@ -1,6 +1,6 @@
 """Plain FP64 pISTA (graphical lasso) -- test infrastructure only.
 
-Problem (Sec. 2.1, eqs. log_MLE and sparse_obj):
+Problem (Sec. 3.1, eqs. log_MLE and sparse_obj):
     minimise F(A) = -log det A + tr(S A) + lam * sum_{i,j} |A_ij|   over A > 0,
 with the diagonal penalised.  The minimiser is unique (F is strictly convex on
 the PD cone), so any correct solver reaches the same A*.
@@ -9,17 +9,17 @@ Each function follows one equation of the paper, written from the text with
 full dense matrices and no blocking or fusion.  Readings of ambiguous passages
 (applied identically by the GPU path):
   * eq. d_sol is elementwise: ST(A_ij - t B_ij, t C_ij), as in App. B.
-  * Alg. 1 applies the masked update A + M (.) D (Sec. 3.1, eq. proximal_gen_free
-    and Sec. 3.3.2); we evaluate it as M (.) ST(A - tB, tC), which is that value
+  * Alg. 1 applies the masked update A + M (.) D (Sec. 4.1, eq. proximal_gen_free
+    and Sec. 4.3.2); we evaluate it as M (.) ST(A - tB, tC), which is that value
     without the rounding of A + (-A + s).  Off the free set A_ij is already 0.
   * Line search: t = 1, halved until the trial is PD and F strictly decreases
-    (Sec. 3.3.2).  Below t = 1e-4 the step becomes min(t, (0.9/cond(A))^2) and
-    halving continues down to 1e-12, after which the search fails (Sec. 5).
+    (Sec. 4.3.2).  Below t = 1e-4 the step becomes min(t, (0.9/cond(A))^2) and
+    halving continues down to 1e-12, after which the search fails (Sec. 6).
   * The decrease is evaluated in difference form,
         F(At) - F(A) = 2 sum_i log(L_ii / Lt_ii) + sum S (.) (At - A)
                        + lam * sum (|At| - |A|),
     so that tiny decreases near convergence are resolved.
-  * Stopping: ||Z||_1 <= tol * ||A||_1 with Z the minimum-norm subgradient (Sec. 5).
+  * Stopping: ||Z||_1 <= tol * ||A||_1 with Z the minimum-norm subgradient (Sec. 6).
   * The two halves of each product are averaged, 1/2 (P + P^T), to keep every
     iterate exactly symmetric.
 """
@@ -38,7 +38,7 @@ LS_FAILED = 2
 # --------------------------------------------------------------------------- input
 def empirical_covariance(Y: np.ndarray, center: bool = True) -> np.ndarray:
     """S = (1/m) sum_i (y_i - mu)(y_i - mu)^T with mu = (1/m) sum_i y_i, the samples
-    y_i being the m rows of Y (Sec. 2.1, eq. empirical_cov).  center=False takes
+    y_i being the m rows of Y (Sec. 3.1, eq. empirical_cov).  center=False takes
     mu = 0, for samples whose mean is known to be zero."""
     Y = np.asarray(Y, dtype=np.float64)
     m = Y.shape[0]
@@ -49,13 +49,13 @@ def empirical_covariance(Y: np.ndarray, center: bool = True) -> np.ndarray:
 
 # --------------------------------------------------------------------------- basics
 def initial_iterate(S: np.ndarray, lam: float) -> np.ndarray:
-    """A^(0) = diag(1 / (S_ii + lam)): the G-ISTA initialisation used in Sec. 5."""
+    """A^(0) = diag(1 / (S_ii + lam)): the G-ISTA initialisation used in Sec. 6."""
     return np.diag(1.0 / (np.diag(S) + lam))
 
 
 def cholesky_or_none(A: np.ndarray):
     """Lower Cholesky factor of A, or None when A is not (numerically) PD.
-    The PD test of the line search (condition t_cond_pd, Sec. 3.3.2)."""
+    The PD test of the line search (condition t_cond_pd, Sec. 4.3.2)."""
     try:
         L = np.linalg.cholesky(A)
     except np.linalg.LinAlgError:
@@ -88,7 +88,7 @@ def inverse_from_cholesky(L: np.ndarray) -> np.ndarray:
     return 0.5 * (W + W.T)
 
 
-# --------------------------------------------------------------------------- Sec. 3.1
+# --------------------------------------------------------------------------- Sec. 4.1
 def gradient(S: np.ndarray, W: np.ndarray) -> np.ndarray:
     """g = grad f(A) = S - A^{-1} (eq. grad_hessian)."""
     return S - W
@@ -106,12 +106,12 @@ def sign_guess(A: np.ndarray, g: np.ndarray) -> np.ndarray:
 
 def min_norm_subgradient(g: np.ndarray, G: np.ndarray, M: np.ndarray, lam: float) -> np.ndarray:
     """Z = (g + lam G) (.) M: G with the free-set mask gives the minimum-norm
-    subgradient of F at A (closing remark of Sec. 3.3.1)."""
+    subgradient of F at A (closing remark of Sec. 4.3.1)."""
     return np.where(M, g + lam * G, 0.0)
 
 
 def kkt_measures(Z: np.ndarray, A: np.ndarray) -> dict:
-    """Stopping measure ||Z||_1 / ||A||_1 (Sec. 5) plus the Frobenius and max norms."""
+    """Stopping measure ||Z||_1 / ||A||_1 (Sec. 6) plus the Frobenius and max norms."""
     sz = float(np.sum(np.abs(Z)))
     sa = float(np.sum(np.abs(A)))
     return {"kkt_rel1": sz / sa, "kkt_fro": float(np.sqrt(np.sum(Z * Z))),
@@ -119,7 +119,7 @@ def kkt_measures(Z: np.ndarray, A: np.ndarray) -> dict:
             "sum_abs_z": sz, "sum_abs_a": sa}
 
 
-# --------------------------------------------------------------------------- Sec. 3.3
+# --------------------------------------------------------------------------- Sec. 4.3
 def c_matrix(A: np.ndarray, lam: float) -> np.ndarray:
     """C_ii = lam A_ii A_ii, C_ij = lam (A_ii A_jj + A_ij A_ji) for i != j (eq. c):
     the diagonal of lam A (x) A belonging to entry (i, j)."""
@@ -177,7 +177,7 @@ def objective_change(S, A, At, L, Lt, lam) -> float:
 
 
 def cond_fallback_step(A: np.ndarray, factor: float = 0.9) -> float:
-    """t = (0.9 / cond(A))^2, the step assumed safe once t drops below 1e-4 (Sec. 5).
+    """t = (0.9 / cond(A))^2, the step assumed safe once t drops below 1e-4 (Sec. 6).
     cond(A) = lambda_max / lambda_min (2-norm condition number)."""
     ev = np.linalg.eigvalsh(A)
     return (factor / (ev[-1] / ev[0])) ** 2
@@ -201,7 +201,7 @@ class PistaResult:
 def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
           t0: float = 1.0, shrink: float = 0.5, t_floor: float = 1e-4,
           t_min: float = 1e-12) -> PistaResult:
-    """pISTA(S, lam, A0) (Alg. 1) with the stopping rule and line search of Sec. 5."""
+    """pISTA(S, lam, A0) (Alg. 1) with the stopping rule and line search of Sec. 6."""
     S = np.asarray(S, dtype=np.float64)
     n = S.shape[0]
     A = initial_iterate(S, lam) if A0 is None else np.array(A0, dtype=np.float64)
@@ -230,7 +230,7 @@ def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
                                km["kkt_max"], total_trials, history)
         C = c_matrix(A, lam)
         B = b_matrix(A, g, G, M, C, lam)
-        # backtracking over t (Sec. 3.3.2, Sec. 5)
+        # backtracking over t (Sec. 4.3.2, Sec. 6)
         t = t0
         fallback = False
         accepted = None

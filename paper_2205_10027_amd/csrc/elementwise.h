@@ -43,7 +43,7 @@ __device__ double block_max(double v, double* sh) {
 
 __device__ __forceinline__ double sign_of(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? -1.0 : 0.0); }
 
-// Gradient-pass element (Sec. 3.1): g = S - W, M = (A != 0) | (|g| > lam),
+// Gradient-pass element (Sec. 4.1): g = S - W, M = (A != 0) | (|g| > lam),
 // G = sign(A) or -sign(g); z = (g + lam G) on M (the minimum-norm subgradient),
 // gm = G on M; both 0 off the free set.
 __device__ __forceinline__ void grad_element(double a, double s, double w, double lam, double& z, int8_t& gm) {

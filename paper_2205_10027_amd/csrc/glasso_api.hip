@@ -1,5 +1,5 @@
 // C ABI of libglasso: handle, workspace and the pISTA driver (Alg. 1 with the
-// Sec. 5 initialisation, line search and stopping rule).  Every arithmetic step
+// Sec. 6 initialisation, line search and stopping rule).  Every arithmetic step
 // runs in the kernels of gemm_f64.hip, chol.hip and passes.hip; the host only
 // sequences launches and reads back a few scalars (KKT, decrease, pivot status).
 #include <math.h>
@@ -615,7 +615,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   e = push_doubles(st, w.lam, hm.lam, count);
   if (e) return e;
 
-  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 5); its factor.  The
+  // A^(0): warm start or diag(1/(S_ii + lambda)) (Sec. 6); its factor.  The
   // diagonal start comes with its factor and W = A^-1 in closed form.
   const bool diag_start = !o.warm_start;
   for (int b = 0; b < count; ++b) {

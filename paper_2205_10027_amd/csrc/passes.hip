@@ -1,7 +1,7 @@
 // HBM-bound elementwise passes of pISTA (FP64, gfx950) and their deterministic
 // reductions.
 //
-// pass_grad  (Sec. 3.1, eqs. grad_hessian, free_set, M, G+; stopping rule of Sec. 5):
+// pass_grad  (Sec. 4.1, eqs. grad_hessian, free_set, M, G+; stopping rule of Sec. 6):
 //   g = S - W, M = (A != 0) | (|g| > lam), G = sign(A) or -sign(g),
 //   Z = (g + lam G) (.) M  -- the minimum-norm subgradient, the input of A Z A,
 //   GM = G (.) M as int8 (both full symmetric), and sums for ||Z||_1, ||Z||_F, max|Z|, ||A||_1, nnz(A),

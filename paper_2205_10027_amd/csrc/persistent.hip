@@ -2,7 +2,7 @@
 // may differ).  Each workgroup starts with problem blockIdx.x and then takes the
 // next untaken problem from a work queue (one atomic counter) until none is left,
 // so problems that need many iterations do not hold up a fixed share of the
-// others.  It runs the whole of Alg. 1 (Sec. 5 settings) for each on the device:
+// others.  It runs the whole of Alg. 1 (Sec. 6 settings) for each on the device:
 // factor, inverse, gradient pass and stopping test, A Z A, the backtracking line
 // search with the cond-based fallback, and the accept step, with no host round
 // trip.  FP64 throughout, with the same per-element formulas as the blocked passes.

@@ -1,6 +1,6 @@
 """Seeded precision matrices and sample covariances (FP64, NumPy PCG64).
 
-Workloads follow the paper's synthetic experiments (Sec. 5.1.1): a true sparse
+Workloads follow the paper's synthetic experiments (Sec. 6.1.1): a true sparse
 precision matrix, m < n Gaussian samples drawn from N(0, A_true^{-1}), and the
 empirical covariance S of eq. (empirical_cov).  The recipes fixed here:
 
@@ -96,7 +96,7 @@ def chain_problem(n: int, m: int, seed: int, diag: float = 1.25, off: float = -0
 
 
 def planar_precision(n: int, seed: int, shift: float = 0.1) -> np.ndarray:
-    """Planar-graph precision (Sec. 5.1.1): the graph Laplacian of a Delaunay
+    """Planar-graph precision (Sec. 6.1.1): the graph Laplacian of a Delaunay
     triangulation of n uniform points in the unit square (A_ij = -1 on edges,
     A_ii = degree) plus shift * I.  The Laplacian's smallest eigenvalue is 0, so
     the paper's diagonal term max(-1.2 lambda_min, 0.1) is 0.1."""

@@ -3,7 +3,7 @@ its use inside the solves).
 
 The trial point (eq. d_sol) reads P = A Z A only on the free set, so a solve forms
 those entries from the short rows of the iterate when it can (the paper forms the
-product densely, Sec. 3.3.3).  Checks: the entry point against the plain definition
+product densely, Sec. 4.3.3).  Checks: the entry point against the plain definition
 A @ Z @ A on the free set (FP64, bound 4 n eps |A||Z||A|), zero elsewhere, with
 both the sparse form and the dense fallback; solves against the oracle; the
 automatic choice against the dense pair alone; batched problems that take

@@ -1,4 +1,4 @@
-"""Support recovery (the experiment of Sec. 5.3, Fig. 2): Matthews correlation
+"""Support recovery (the experiment of Sec. 6.3, Fig. 2): Matthews correlation
 coefficient of the estimated sparsity pattern against the ground truth, over a
 lambda grid, for the chain, random and planar ground truths.
 
