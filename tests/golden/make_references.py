@@ -1,0 +1,137 @@
+"""Reference solutions of the benchmark workloads, written by the CPU oracle.
+
+For each workload the oracle (FP64, plain NumPy/SciPy) runs pISTA from the
+diagonal start to a KKT measure ||Z||_1 / ||A||_1 <= 1e-8, a thousand times below
+the 1e-5 the GPU path stops at (in FP64 the method stalls near 3e-9 on the n = 100
+chain: steps keep decreasing F by rounding-level amounts without lowering the
+measure, so 1e-9 is not reachable on every workload), and the file keeps what the parity tests compare with:
+
+  F        the objective F(A*) (eq. sparse_obj)
+  rows, cols, vals   the nonzeros of the lower triangle of A* (the support), or,
+                     for the regularisation path and for solutions with more than
+                     MAX_LISTED of them, only
+  bits               the lower-triangle support packed one bit per entry in the
+                     order of numpy.tril_indices(n)
+  ex_rows, ex_cols   lower-triangle entries exempt from the support comparison,
+                     the entries within 1e-8 of the threshold: a nonzero with
+                     |A*_ij| <= 1e-8 (it could as well be zero), or a zero whose
+                     gradient g* = S - inv(A*) has ||g*_ij| - lambda| <= 1e-8 (it
+                     could as well be nonzero)
+  kkt, iterations, trials, status   the oracle's own measures
+
+Workloads (inputs from the seeded generators in synth/ only):
+  chain10k   chain precision, n = 10^4, m = 5000 samples, seed 0, lambda 0.2 and 0.1
+  random2000 random sparse precision, n = 2000, m = 1000, seed 0, the lambda frozen
+             in workloads.json (nnz(A*) ~ 5n)
+  path1000   random sparse, n = 1000, m = 500, seed 0, 32 lambdas geometric from
+             lambda_max = max_{i!=j} |S_ij| down to lambda_max / 100
+  chain100   chain, n = 100, m = 50, seeds 0..4, lambda 0.2
+
+Only oracle/ and synth/ are called.
+
+    python tests/golden/make_references.py [chain100 random2000 path1000 chain10k]
+    python tests/golden/make_references.py repack <name> <n> [bits]   (re-store the lists packed)
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+TOL_REF = 1e-8
+EXEMPT = 1e-8
+MAX_LISTED = 150_000
+
+
+def reference(S, lam, tag, max_iter=2000, listed=True):
+    t0 = time.time()
+    r = oracle.pista(S, lam, TOL_REF, max_iter=max_iter)
+    dt = time.time() - t0
+    A = r.A
+    g = oracle.gradient(S, r.W)
+    lo = np.tril(np.ones_like(A, dtype=bool))
+    rows, cols = np.nonzero((A != 0) & lo)
+    nz = A != 0
+    ex = lo & ((nz & (np.abs(A) <= EXEMPT)) | (~nz & (np.abs(np.abs(g) - lam) <= EXEMPT)))
+    ex_rows, ex_cols = np.nonzero(ex)
+    print(f"{tag}: lambda={lam:.10g} F={r.objective:.15g} kkt={r.kkt_rel1:.3e} it={r.iterations} "
+          f"trials={r.ls_trials} status={r.status} nnz={np.count_nonzero(A)} exempt={ex_rows.size} "
+          f"({dt:.1f} s)", flush=True)
+    out = {
+        "n": np.int64(A.shape[0]), "lam": np.float64(lam), "F": np.float64(r.objective),
+        "kkt": np.float64(r.kkt_rel1), "iterations": np.int64(r.iterations), "trials": np.int64(r.ls_trials),
+        "status": np.int64(r.status), "rows": rows.astype(np.int32), "cols": cols.astype(np.int32),
+        "vals": A[rows, cols], "ex_rows": ex_rows.astype(np.int32), "ex_cols": ex_cols.astype(np.int32),
+        "seconds": np.float64(dt),
+    }
+    return pack(out, A.shape[0], listed)
+
+
+def pack(entry, n, listed=True):
+    """Long support lists (or every list, with listed=False) become one bit per
+    lower-triangle entry."""
+    if "bits" in entry or (listed and entry["rows"].size <= MAX_LISTED):
+        return entry
+    mask = np.zeros((n, n), dtype=bool)
+    mask[entry["rows"], entry["cols"]] = True
+    r, c = np.tril_indices(n)
+    out = {k: v for k, v in entry.items() if k not in ("rows", "cols", "vals")}
+    out["n"] = np.int64(n)
+    out["bits"] = np.packbits(mask[r, c])
+    return out
+
+
+def repack(name, n, listed=True):
+    """Rewrite golden/<name>.npz with its support lists packed (same support)."""
+    path = os.path.join(HERE, name + ".npz")
+    z = np.load(path, allow_pickle=False)
+    entries = [pack({key[len(f"{k}_"):]: z[key] for key in z.files if key.startswith(f"{k}_")}, n, listed)
+               for k in range(int(z["count"]))]
+    save(name, entries)
+
+
+def save(name, entries):
+    flat = {}
+    for k, d in enumerate(entries):
+        for key, v in d.items():
+            flat[f"{k}_{key}"] = v
+    flat["count"] = np.int64(len(entries))
+    path = os.path.join(HERE, name + ".npz")
+    np.savez_compressed(path, **flat)
+    print(f"wrote {path}", flush=True)
+
+
+def main(which):
+    if "chain100" in which:
+        out = []
+        for seed in range(5):
+            S, _ = synth.chain_problem(100, 50, seed)
+            out.append(reference(S, 0.2, f"chain100 seed {seed}"))
+        save("chain100", out)
+    if "random2000" in which:
+        with open(os.path.join(HERE, "workloads.json")) as f:
+            w = json.load(f)["random_sparse_n2000"]
+        S, _ = synth.random_sparse_problem(w["n"], w["m"], w["seed"])
+        save("random2000", [reference(S, w["lambda"], "random2000")])
+    if "path1000" in which:
+        S, _ = synth.random_sparse_problem(1000, 500, 0)
+        lams = synth.lambda_path(S, 32, 100.0)
+        save("path1000", [reference(S, float(l), f"path1000 k={k}", listed=False) for k, l in enumerate(lams)])
+    if "chain10k" in which:
+        S, _ = synth.chain_problem(10000, 5000, 0)
+        for lam in (0.2, 0.1):
+            save(f"chain10k_lam{lam}", [reference(S, lam, "chain10k", max_iter=300)])
+
+
+if __name__ == "__main__":
+    if sys.argv[1:2] == ["repack"]:
+        repack(sys.argv[2], int(sys.argv[3]), listed=sys.argv[4:5] != ["bits"])
+    else:
+        main(sys.argv[1:] or ["chain100", "random2000", "path1000", "chain10k"])
