@@ -151,6 +151,29 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
                               const double* lambda, double tol, double* const* A, double* const* W,
                               glasso_info* info, void* stream);
 
+/* glasso_solve_small without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same persistent launch as glasso_solve_small, but its
+ * scratch (per-workgroup matrix slots, problem descriptors, outputs, the
+ * work-queue counter) lives in a fixed array of the library's device data,
+ * GLASSO_SMALL_STATIC_BYTES (about 51 MB) on every GPU the library runs on, held
+ * until the process ends, instead of in a handle's workspace; at most 256
+ * workgroups (one per compute unit).  No handle: opt gives the options (NULL =
+ * defaults); the host-side staging arrays are static as well.
+ *   count  1 .. GLASSO_SMALL_STATIC_MAX_COUNT problems; INVALID_ARG beyond
+ *   other arguments, outputs and errors as for glasso_solve_small; HIP when the
+ *   array's device address cannot be obtained.
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (the kernel rewrites every part it reads first).  Calls overlapping
+ * on one GPU would race on it: the library serialises the calls of a process
+ * with a lock, so calls from several host threads wait for each other.  Results
+ * are bitwise those of glasso_solve_small. */
+#define GLASSO_SMALL_STATIC_MAX_COUNT 16384
+#define GLASSO_SMALL_STATIC_BYTES 53084416u
+glasso_err glasso_solve_small_static(const glasso_options* opt, int count, const double* const* S,
+                                     const int64_t* n, const double* lambda, double tol, double* const* A,
+                                     double* const* W, glasso_info* info, void* stream);
+
 /* Tile autotuner: for problems of size n solved `count` at a time, time the
  * Cholesky, triangular inverse and LAUUM (and, with opt.precision FP64, the
  * A Z A product) of identity matrices under each candidate tile policy

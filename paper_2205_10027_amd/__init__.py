@@ -22,6 +22,7 @@ PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
 CONVERGED, MAX_ITER, LS_FAILED = 0, 1, 2
 TILES_AUTO = -1  # tile policy chosen by the autotuner (GLASSO_TILES_AUTO)
 SMALL_MAX_N = 64  # largest n of glasso_solve_small (GLASSO_SMALL_MAX_N)
+SMALL_STATIC_MAX_COUNT = 16384  # problems per glasso_solve_small_static call
 STATUS_NAMES = {CONVERGED: "converged", MAX_ITER: "max_iter", LS_FAILED: "ls_failed"}
 
 
@@ -162,6 +163,12 @@ class Solver:
         results as for solve_batched."""
         return self._multi("glasso_solve_small", S_list, lams, tol, A_list, want_W, stream)
 
+    def solve_small_static(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
+        """solve_small through the entry point that allocates nothing
+        (glasso_solve_small_static: scratch in the library's fixed device array,
+        this solver's options, no handle).  Arguments and results as solve_small."""
+        return self._multi("glasso_solve_small_static", S_list, lams, tol, A_list, want_W, stream)
+
     def _multi(self, entry, S_list, lams, tol, A_list, want_W, stream):
         lams = [float(x) for x in lams]
         count = len(lams)
@@ -188,7 +195,8 @@ class Solver:
         nn = (ctypes.c_int64 * count)(*ns)
         ll = (ctypes.c_double * count)(*lams)
         infos = (GlassoInfo * count)()
-        _check(getattr(_lib, entry)(self._h, count, Sp, nn, ll, float(tol), Ap, Wp, infos, _stream(stream)), entry)
+        first = ctypes.byref(self.options) if entry == "glasso_solve_small_static" else self._h
+        _check(getattr(_lib, entry)(first, count, Sp, nn, ll, float(tol), Ap, Wp, infos, _stream(stream)), entry)
         out = []
         for i in range(count):
             inf = infos[i]

@@ -61,6 +61,9 @@ SIGNATURES = {
                                      ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(GlassoInfo), _VP]),
     "glasso_solve_small": (_INT, [_VP, _INT, ctypes.POINTER(_VP), ctypes.POINTER(_I64), ctypes.POINTER(_D), _D,
                                    ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(GlassoInfo), _VP]),
+    "glasso_solve_small_static": (_INT, [ctypes.POINTER(GlassoOptions), _INT, ctypes.POINTER(_VP),
+                                          ctypes.POINTER(_I64), ctypes.POINTER(_D), _D, ctypes.POINTER(_VP),
+                                          ctypes.POINTER(_VP), ctypes.POINTER(GlassoInfo), _VP]),
     "glasso_covariance": (_INT, [_VP, _VP, _I64, _I64, _INT, _VP, _VP]),
     "glasso_cholesky": (_INT, [_VP, _VP, _I64, _VP, ctypes.POINTER(_I64), c_double_p, _VP]),
     "glasso_inverse": (_INT, [_VP, _VP, _I64, _VP, _VP]),

@@ -1176,33 +1176,38 @@ glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, v
   return GLASSO_OK;
 }
 
-glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
-                              const double* lambda, double tol, double* const* A, double* const* W,
-                              glasso_info* info, void* stream) {
-  if (!h || count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return GLASSO_ERR_INVALID_ARG;
+namespace {
+
+bool small_args_ok(int count, const double* const* S, const int64_t* n, const double* lambda, double tol,
+                   double* const* A) {
+  if (count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return false;
   for (int i = 0; i < count; ++i)
     if (!S[i] || !A[i] || n[i] < 1 || n[i] > GLASSO_SMALL_MAX_N || !(lambda[i] > 0.0) || !isfinite(lambda[i]))
-      return GLASSO_ERR_INVALID_ARG;
-  const auto t_start = std::chrono::steady_clock::now();
-  hipStream_t st = (hipStream_t)stream;
-  const int grid = std::min(count, 512);
-  const size_t ws_bytes = (size_t)grid * SMALL_WS_DOUBLES * sizeof(double);
-  const size_t gm_bytes = (size_t)grid * SMALL_GM_BYTES;
-  const size_t pr_bytes = ((size_t)count * sizeof(SmallProblem) + 255) / 256 * 256;
-  const size_t out_bytes = ((size_t)count * sizeof(SmallOut) + 255) / 256 * 256;
-  const size_t bytes = ws_bytes + gm_bytes + pr_bytes + out_bytes + 256;  // + the work-queue counter
-  if (bytes > h->small_bytes) {
-    if (h->small_base) (void)hipFree(h->small_base);
-    h->small_base = nullptr;
-    h->small_bytes = 0;
-    if (hipMalloc(&h->small_base, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return GLASSO_ERR_OOM;
-    }
-    h->small_bytes = bytes;
+      return false;
+  return true;
+}
+
+// Carving of the persistent solver's scratch for `grid` workgroups and `count`
+// problems: per-workgroup matrix slots, free-set signs, problem descriptors,
+// outputs and the work-queue counter.
+struct SmallLayout {
+  size_t ws, gm, pr, out, total;
+  SmallLayout(int grid, int count) {
+    ws = (size_t)grid * SMALL_WS_DOUBLES * sizeof(double);
+    gm = (size_t)grid * SMALL_GM_BYTES;
+    pr = ((size_t)count * sizeof(SmallProblem) + 255) / 256 * 256;
+    out = ((size_t)count * sizeof(SmallOut) + 255) / 256 * 256;
+    total = ws + gm + pr + out + 256;
   }
-  char* base = static_cast<char*>(h->small_base);
-  std::vector<SmallProblem> pr(count);
+};
+
+// One persistent launch over `count` problems with its scratch at `base` (device)
+// and the host staging arrays pr, out (count entries each).
+glasso_err run_small(const glasso_options& o, int count, const double* const* S, const int64_t* n,
+                     const double* lambda, double tol, double* const* A, double* const* W, glasso_info* info,
+                     hipStream_t st, char* base, int grid, SmallProblem* pr, SmallOut* out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const SmallLayout lay(grid, count);
   for (int i = 0; i < count; ++i) {
     pr[i].S = S[i];
     pr[i].A = A[i];
@@ -1212,14 +1217,13 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   }
   SmallParams p;
   p.ws = reinterpret_cast<double*>(base);
-  p.gm = reinterpret_cast<int8_t*>(base + ws_bytes);
-  SmallProblem* dpr = reinterpret_cast<SmallProblem*>(base + ws_bytes + gm_bytes);
-  SmallOut* dout = reinterpret_cast<SmallOut*>(base + ws_bytes + gm_bytes + pr_bytes);
+  p.gm = reinterpret_cast<int8_t*>(base + lay.ws);
+  SmallProblem* dpr = reinterpret_cast<SmallProblem*>(base + lay.ws + lay.gm);
+  SmallOut* dout = reinterpret_cast<SmallOut*>(base + lay.ws + lay.gm + lay.pr);
   p.prob = dpr;
   p.out = dout;
-  p.next = reinterpret_cast<int*>(base + ws_bytes + gm_bytes + pr_bytes + out_bytes);
+  p.next = reinterpret_cast<int*>(base + lay.ws + lay.gm + lay.pr + lay.out);
   p.count = count;
-  const glasso_options& o = h->opt;
   p.tol = tol;
   p.t0 = o.t0;
   p.shrink = o.shrink;
@@ -1227,10 +1231,9 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   p.t_min = o.t_min;
   p.max_iter = o.max_iter;
   p.warm_start = o.warm_start;
-  HIP_TRY(hipMemcpyAsync(dpr, pr.data(), (size_t)count * sizeof(SmallProblem), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dpr, pr, (size_t)count * sizeof(SmallProblem), hipMemcpyHostToDevice, st));
   K_TRY(solve_small(st, p, grid));
-  std::vector<SmallOut> out(count);
-  HIP_TRY(hipMemcpyAsync(out.data(), dout, (size_t)count * sizeof(SmallOut), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(out, dout, (size_t)count * sizeof(SmallOut), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const double total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   glasso_err err = GLASSO_OK;
@@ -1254,6 +1257,86 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
     }
   }
   return err;
+}
+
+}  // namespace
+
+glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                              const double* lambda, double tol, double* const* A, double* const* W,
+                              glasso_info* info, void* stream) {
+  if (!h || !small_args_ok(count, S, n, lambda, tol, A)) return GLASSO_ERR_INVALID_ARG;
+  const int grid = std::min(count, 512);
+  const SmallLayout lay(grid, count);
+  if (lay.total > h->small_bytes) {
+    if (h->small_base) (void)hipFree(h->small_base);
+    h->small_base = nullptr;
+    h->small_bytes = 0;
+    if (hipMalloc(&h->small_base, lay.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return GLASSO_ERR_OOM;
+    }
+    h->small_bytes = lay.total;
+  }
+  std::vector<SmallProblem> pr(count);
+  std::vector<SmallOut> out(count);
+  return run_small(h->opt, count, S, n, lambda, tol, A, W, info, (hipStream_t)stream,
+                   static_cast<char*>(h->small_base), grid, pr.data(), out.data());
+}
+
+// ------------------------------------------------------------------ allocation-free small solves
+//
+// glasso_solve_small_static keeps the persistent solver's scratch in `scratch`, an
+// array of this library's device data sized for SMALL_STATIC_GRID workgroups and
+// GLASSO_SMALL_STATIC_MAX_COUNT problems.  Each GPU holds its own copy at its own
+// address; host code must use that address (from hipGetSymbolAddress, taken once
+// per device with the device current), never the array's name.  The host staging
+// arrays are static too, and one lock serialises the calls of a process, which all
+// share the arrays.
+namespace {
+
+constexpr int SMALL_STATIC_GRID = 256;  // one workgroup per compute unit
+constexpr int SMALL_STATIC_MAX_DEVICES = 64;
+constexpr size_t SMALL_STATIC_BYTES =
+    (size_t)SMALL_STATIC_GRID * SMALL_WS_DOUBLES * sizeof(double) + (size_t)SMALL_STATIC_GRID * SMALL_GM_BYTES +
+    ((size_t)GLASSO_SMALL_STATIC_MAX_COUNT * sizeof(SmallProblem) + 255) / 256 * 256 +
+    ((size_t)GLASSO_SMALL_STATIC_MAX_COUNT * sizeof(SmallOut) + 255) / 256 * 256 + 256;
+static_assert(SMALL_STATIC_BYTES == GLASSO_SMALL_STATIC_BYTES, "GLASSO_SMALL_STATIC_BYTES in glasso.h");
+
+static __device__ __align__(256) unsigned char scratch[SMALL_STATIC_BYTES];
+
+std::mutex g_static_mu;
+void* g_static_ptr[SMALL_STATIC_MAX_DEVICES] = {};
+SmallProblem g_static_pr[GLASSO_SMALL_STATIC_MAX_COUNT];
+SmallOut g_static_out[GLASSO_SMALL_STATIC_MAX_COUNT];
+
+}  // namespace
+
+glasso_err glasso_solve_small_static(const glasso_options* opt, int count, const double* const* S,
+                                     const int64_t* n, const double* lambda, double tol, double* const* A,
+                                     double* const* W, glasso_info* info, void* stream) {
+  if (count > GLASSO_SMALL_STATIC_MAX_COUNT || !small_args_ok(count, S, n, lambda, tol, A))
+    return GLASSO_ERR_INVALID_ARG;
+  glasso_options o;
+  glasso_default_options(&o);
+  if (opt) {
+    if (check_options(opt)) return GLASSO_ERR_INVALID_ARG;
+    o = *opt;
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SMALL_STATIC_MAX_DEVICES) return GLASSO_ERR_INVALID_ARG;
+  if (!g_static_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return GLASSO_ERR_HIP;
+    }
+    g_static_ptr[dev] = ptr;
+  }
+  const int grid = std::min(count, SMALL_STATIC_GRID);
+  return run_small(o, count, S, n, lambda, tol, A, W, info, (hipStream_t)stream,
+                   static_cast<char*>(g_static_ptr[dev]), grid, g_static_pr, g_static_out);
 }
 
 // ------------------------------------------------------------------ step-level entry points

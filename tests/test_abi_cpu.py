@@ -54,6 +54,9 @@ def test_host_only_entry_points():
     with pytest.raises(g.GlassoError):
         g.workspace_bytes(100, 3)
     assert lib.glasso_create(None, None) == 1
+    # the allocation-free small solve checks its arguments on the host first
+    assert lib.glasso_solve_small_static(None, 0, None, None, None, 1e-6, None, None, None, None) == 1
+    assert g.SMALL_STATIC_MAX_COUNT == 16384
     # option checks run before any device call
     assert opt.tile_policy == g.TILES_AUTO == -1 and opt.graphs == 0 and opt.w_mixed == -1
     h = ctypes.c_void_p()
