@@ -49,23 +49,167 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(S, lam, gpu_iterations):
-    """Oracle on the host cores: one full pISTA iteration (W, gradient pass, B, line
-    search) of the same problem, scaled by the GPU's iteration count."""
-    import oracle
-
+def host_info():
+    """Host cores, CPU model and BLAS of the machine the oracle runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cores"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except Exception:
+        pass
     try:
         from threadpoolctl import threadpool_info
 
-        threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=os.cpu_count())
+        pools = threadpool_info()
+        info["blas"] = [{k: p.get(k) for k in ("internal_api", "version", "num_threads", "threading_layer")}
+                        for p in pools if p.get("user_api") == "blas"]
+        info["threads"] = max((p.get("num_threads", 1) for p in pools), default=os.cpu_count())
     except Exception:
-        threads = os.cpu_count()
-    t0 = time.perf_counter()
-    r = oracle.pista(S, lam, 0.0, max_iter=1)
-    dt = time.perf_counter() - t0
-    return {"value": dt * max(1, gpu_iterations), "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 oracle iteration of chain n={S.shape[0]} lambda={lam} ({r.ls_trials} trial, "
-                      f"{dt:.1f} s) x {gpu_iterations} GPU iterations"}
+        info["threads"] = os.cpu_count()
+    return info
+
+
+def _oracle_time(fn, threads=None):
+    """Wall time of fn() with the BLAS limited to `threads` (None: all)."""
+    if threads is None:
+        t = time.perf_counter()
+        out = fn()
+        return time.perf_counter() - t, out
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=threads):
+        t = time.perf_counter()
+        out = fn()
+        return time.perf_counter() - t, out
+
+
+def cpu_baseline(S10k, lams, gpu_iterations):
+    """The CPU oracle on the host cores, timed as it stands.
+
+    Measured full solves (time to the same tolerance as the GPU): the chain
+    n = 100 problems (tol 1e-6, five seeds) and the random sparse n = 2000 problem
+    (tol 1e-5), with all cores and with one thread.  For the headline workload
+    (chain n = 10^4) a full oracle solve takes minutes per lambda, so the bench
+    times a bounded sample: the first oracle iteration at each lambda (W, gradient
+    pass, B, line search; about 10 s each on 16 cores), times the GPU's iteration
+    count at that lambda, averaged over the lambdas like the headline value."""
+    import json as _json
+
+    import oracle
+    import synth
+
+    host = host_info()
+    out = {"unit": "s", "cores": int(host.get("threads", os.cpu_count())), "kind": "oracle", "host": host}
+    # config 0: chain n = 100, m = 50, seeds 0..4, lambda 0.2, tol 1e-6
+    c0 = [synth.chain_problem(100, 50, seed)[0] for seed in range(5)]
+    t_all, _ = _oracle_time(lambda: [oracle.pista(S, 0.2, 1e-6) for S in c0])
+    t_one, _ = _oracle_time(lambda: [oracle.pista(S, 0.2, 1e-6) for S in c0], threads=1)
+    out["chain_n100"] = {"s_per_solve": t_all / 5, "s_per_solve_1_thread": t_one / 5, "kind": "measured full solves"}
+    # config 1: random sparse n = 2000, frozen lambda, tol 1e-5
+    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
+        w = _json.load(f)["random_sparse_n2000"]
+    S1, _ = synth.random_sparse_problem(w["n"], w["m"], w["seed"])
+    t_all, r = _oracle_time(lambda: oracle.pista(S1, w["lambda"], w["tol"]))
+    t_one, _ = _oracle_time(lambda: oracle.pista(S1, w["lambda"], w["tol"]), threads=1)
+    out["random_n2000"] = {"s_per_solve": t_all, "s_per_solve_1_thread": t_one, "iterations": r.iterations,
+                           "kind": "measured full solves"}
+    # headline: bounded sample
+    per_lam = []
+    for lam, its in zip(lams, gpu_iterations):
+        dt, r = _oracle_time(lambda: oracle.pista(S10k, lam, 0.0, max_iter=1))
+        per_lam.append({"lambda": lam, "first_iteration_s": dt, "trials": r.ls_trials, "gpu_iterations": its,
+                        "estimated_solve_s": dt * max(1, its)})
+    out["value"] = sum(p["estimated_solve_s"] for p in per_lam) / len(per_lam)
+    out["sample"] = ("chain n=10000: the oracle's first iteration at each lambda in " + str(list(lams)) +
+                     ", times the GPU iteration count of that lambda, mean over the lambdas (s per solve); "
+                     "chain n=100 and random n=2000: measured full solves")
+    out["chain_n10000"] = per_lam
+    return out
+
+
+def golden_error(name, results, k_of=None):
+    """Distance of GPU results from the stored oracle solutions (tests/golden/<name>.npz,
+    written by the oracle to KKT <= 1e-8): worst relative F error, support mismatches
+    outside the threshold exemptions, per result and at worst.  None when the file is
+    missing."""
+    from tests import golden_ref
+
+    try:
+        refs = golden_ref.load(name)
+    except FileNotFoundError:
+        return None
+    per = []
+    for i, r in enumerate(results):
+        ref = refs[k_of(i) if k_of else i]
+        relF, mism, dA = golden_ref.compare(r.A.cpu().numpy(), r.objective, ref)
+        per.append({"objective_rel_err": relF, "support_mismatch": mism, "A_max_abs_err": dA})
+    return {"worst_objective_rel_err": max(p["objective_rel_err"] for p in per),
+            "support_mismatch": sum(p["support_mismatch"] for p in per), "per_result": per}
+
+
+def bench_config0(g, torch, dev, reps=5):
+    """Chain n = 100, m = 50, seeds 0..4, lambda 0.2, tol 1e-6, FP64 (the small
+    parity case): time per solve and per iteration (latency-bound), and the error
+    against the stored oracle solutions."""
+    import synth
+
+    Ss = [torch.from_numpy(synth.chain_problem(100, 50, seed)[0]).to(dev) for seed in range(5)]
+    s = g.Solver()
+    res = [s.solve(S, 0.2, 1e-6) for S in Ss]  # warmup
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        res = [s.solve(S, 0.2, 1e-6) for S in Ss]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / (reps * len(Ss))
+    s.close()
+    its = sum(r.iterations for r in res) / len(res)
+    out = {"workload": "chain n=100 m=50 seeds 0-4 lambda=0.2 tol=1e-6, FP64", "s_per_solve": dt,
+           "us_per_iteration": dt / its * 1e6, "iterations": [r.iterations for r in res],
+           "vs_oracle": golden_error("chain100", res)}
+    log(f"[bench] chain n=100: {dt * 1e3:.2f} ms per solve, {out['us_per_iteration']:.0f} us per iteration")
+    return out
+
+
+def bench_config1(g, torch, dev, reps=3):
+    """Random sparse n = 2000, m = 1000, seed 0, lambda frozen to give nnz(A*) ~ 5n,
+    tol 1e-5: time-to-KKT of the FP64 path and both mixed forms, each result's error
+    against the stored oracle solution."""
+    import json as _json
+
+    import synth
+
+    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
+        w = _json.load(f)["random_sparse_n2000"]
+    S = torch.from_numpy(synth.random_sparse_problem(w["n"], w["m"], w["seed"])[0]).to(dev)
+    out = {"workload": f"random sparse n={w['n']} m={w['m']} seed={w['seed']} lambda={w['lambda']} (nnz ~ 5n) "
+                       f"tol={w['tol']}", "forms": {}}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        s = g.Solver(precision=prec)
+        r = s.solve(S, w["lambda"], w["tol"])  # warmup (tile tuning, workspace)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = s.solve(S, w["lambda"], w["tol"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        s.close()
+        if r.status != g.CONVERGED:
+            raise RuntimeError(f"n=2000 {prec}: {r.status_name}")
+        out["forms"][prec] = {"s_per_solve": dt, "iterations": r.iterations, "kkt_rel1": r.kkt_rel1,
+                              "vs_oracle": golden_error("random2000", [r])}
+        log(f"[bench] random n=2000 {prec}: {dt * 1e3:.1f} ms per solve, {r.iterations} iterations")
+    f64 = out["forms"]["fp64"]["s_per_solve"]
+    for prec in ("fp32", "bf16x3"):
+        out["forms"][prec]["speedup_vs_fp64"] = f64 / out["forms"][prec]["s_per_solve"]
+    return out
 
 
 def time_chain(g, St, lams, tol, precision, steps, warmup, torch, dense_product=False):
@@ -100,82 +244,65 @@ def time_chain(g, St, lams, tol, precision, steps, warmup, torch, dense_product=
 
 
 def bench_path(g, torch, dev):
-    """Regularisation path, FP64: every mode of lambda_path (with and without
-    graph-captured iterations) and the plain one-solve-per-lambda path."""
+    """Regularisation path (random sparse n = 1000, m = 500, 32 lambdas from lambda_max
+    to lambda_max/100): every mode of lambda_path, with and without graph-captured
+    iterations, and the plain one-solve-per-lambda path, at tol 1e-5 and at 1e-8, each
+    mode's results against the oracle's solutions (tests/golden/path1000.npz).  At
+    1e-5 the stopping rule ||Z||_1 <= tol ||A||_1 leaves F up to 3e-6 from F* at the
+    large-lambda end; at 1e-8 every lambda meets F to 1e-8 and the oracle's support."""
     import synth
 
     S, _ = synth.random_sparse_problem(1000, 500, 0)
     lams = list(synth.lambda_path(S, count=32, ratio=100.0))
     St = torch.from_numpy(S).to(dev)
-    out = {"workload": "random sparse n=1000 m=500 seed 0, 32 lambdas lambda_max..lambda_max/100, tol 1e-5",
-           "precision": "fp64"}
-    modes = {}
+    out = {"workload": "random sparse n=1000 m=500 seed 0, 32 lambdas lambda_max..lambda_max/100"}
     g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000)  # warmup (and tile tuning)
-    for name, mode, graphs in (("independent", "independent", False), ("independent_graphs", "independent", True),
-                               ("waves", "waves", False), ("waves_graphs", "waves", True),
-                               ("sequential", "sequential", False)):
+    g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000, precision="bf16x3")
+
+    def run(name, mode, graphs, prec, tol):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000, graphs=graphs)
-        torch.cuda.synchronize()
+        if mode == "one_by_one":
+            s1 = g.Solver(precision=prec, max_iter=5000)
+            res = [s1.solve(St, lam, tol, want_W=False) for lam in lams]
+            torch.cuda.synchronize()
+            s1.close()
+        else:
+            res = g.lambda_path(St, lams, tol, mode=mode, waves=4, max_iter=5000, graphs=graphs, precision=prec)
+            torch.cuda.synchronize()
         dt = time.perf_counter() - t
         if any(r.status != g.CONVERGED for r in res):
-            raise RuntimeError(f"path mode {name}: not every lambda converged")
-        modes[name] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res)}
-        log(f"[bench] path {name}: {dt:.2f}s ({len(lams) / dt:.1f} solves/s)")
-    # the plain path: one glasso_solve per lambda from the diagonal start, no batching
-    s1 = g.Solver()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    its = 0
-    for lam in lams:
-        r = s1.solve(St, lam, 1e-5, want_W=False)
-        its += r.iterations
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    s1.close()
-    modes["one_by_one"] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": its}
-    log(f"[bench] path one_by_one: {dt:.2f}s ({len(lams) / dt:.1f} solves/s)")
-    out["modes"] = modes
-    # config 3 asks for a warm-started, graph-captured, autotuned path
-    out["solves_per_s"] = modes["waves_graphs"]["solves_per_s"]
-    out["speedup_vs_one_by_one"] = modes["one_by_one"]["path_s"] / modes["waves_graphs"]["path_s"]
-    out["best_mode"] = min(modes, key=lambda k: modes[k]["path_s"])
-    # the same path in the default mixed form (BF16x3 products, BF16x6 W, FP64
-    # Cholesky / line search / KKT): forms F1 and F2 together, against the plain
-    # FP64 one-solve-per-lambda path above, with the error of every lambda's result
-    # against the FP64 batched result
-    g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000, precision="bf16x3")  # warmup
-    mixed = {}
-    ref = {}
-    for name, mode, graphs, prec in (("waves_graphs", "waves", True, "fp64"),
-                                     ("independent", "independent", False, "fp64"),
-                                     ("independent", "independent", False, "bf16x3"),
-                                     ("waves_graphs", "waves", True, "bf16x3")):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        res = g.lambda_path(St, lams, 1e-5, mode=mode, waves=4, max_iter=5000, graphs=graphs, precision=prec)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        if any(r.status != g.CONVERGED for r in res):
-            raise RuntimeError(f"path {prec} {name}: not every lambda converged")
-        if prec == "fp64" and not ref:
-            ref = {i: r for i, r in enumerate(res)}
-            continue
-        worst = max(abs(r.objective - ref[i].objective) / abs(ref[i].objective) for i, r in enumerate(res))
-        supp = sum(int(((r.A != 0) != (ref[i].A != 0)).sum()) for i, r in enumerate(res))
-        if prec == "fp64":
-            # two FP64 modes against each other: how far apart two solutions of the
-            # same tolerance reached along different trajectories lie
-            mixed["fp64_independent_vs_fp64_waves"] = {"max_objective_rel_diff": worst, "support_diff": supp}
-            log(f"[bench] path fp64 independent vs waves: F rel diff {worst:.1e}, support diff {supp}")
-            continue
-        mixed[name] = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res),
-                       "speedup_vs_fp64_one_by_one": modes["one_by_one"]["path_s"] / dt,
-                       "max_objective_rel_diff_vs_fp64": worst, "support_diff_vs_fp64": supp,
-                       "max_kkt_rel1": max(r.kkt_rel1 for r in res)}
-        log(f"[bench] path bf16x3 {name}: {dt:.2f}s ({len(lams) / dt:.1f} solves/s), F rel diff {worst:.1e}")
-    out["mixed_bf16x3"] = mixed
+            raise RuntimeError(f"path {prec} {name} tol {tol}: not every lambda converged")
+        err = golden_error("path1000", res)
+        rec = {"path_s": dt, "solves_per_s": len(lams) / dt, "iterations": sum(r.iterations for r in res),
+               "max_kkt_rel1": max(r.kkt_rel1 for r in res)}
+        if err:
+            rec["vs_oracle"] = {"worst_objective_rel_err": err["worst_objective_rel_err"],
+                                "support_mismatch": err["support_mismatch"]}
+        log(f"[bench] path {prec} {name} tol {tol:g}: {dt:.2f}s ({len(lams) / dt:.1f} solves/s)"
+            + (f", F err {err['worst_objective_rel_err']:.1e}, support mismatch {err['support_mismatch']}"
+               if err else ""))
+        return rec
+
+    for tol in (1e-5, 1e-8):
+        key = f"tol_{tol:g}"
+        modes = {}
+        for name, mode, graphs in (("independent", "independent", False), ("independent_graphs", "independent", True),
+                                   ("waves", "waves", False), ("waves_graphs", "waves", True),
+                                   ("sequential", "sequential", False), ("one_by_one", "one_by_one", False)):
+            modes[name] = run(name, mode, graphs, "fp64", tol)
+        mixed = {name: run(name, mode, graphs, "bf16x3", tol)
+                 for name, mode, graphs in (("independent", "independent", False), ("waves_graphs", "waves", True))}
+        for rec in mixed.values():
+            rec["speedup_vs_fp64_one_by_one"] = modes["one_by_one"]["path_s"] / rec["path_s"]
+        out[key] = {"fp64": modes, "bf16x3": mixed,
+                    "speedup_waves_graphs_vs_one_by_one": modes["one_by_one"]["path_s"] / modes["waves_graphs"]["path_s"],
+                    "best_fp64_mode": min(modes, key=lambda k: modes[k]["path_s"])}
+    # the configuration the path is quoted in: warm-started waves, graph-captured
+    # iterations, autotuned tiles, FP64, at the tolerance where every lambda meets the
+    # objective bar against the oracle
+    out["solves_per_s"] = out["tol_1e-08"]["fp64"]["waves_graphs"]["solves_per_s"]
+    out["solves_per_s_tol_1e-5"] = out["tol_1e-05"]["fp64"]["waves_graphs"]["solves_per_s"]
     out["small_persistent"] = bench_small(g, torch, dev)
     return out
 
@@ -437,6 +564,9 @@ def main():
               "iterations": [r.iterations for r in results[:len(lams)]],
               "ls_trials": [r.ls_trials for r in results[:len(lams)]],
               "solves_per_s": solves / elapsed}
+    # every result of the timed form against the oracle's solution of the same problem
+    config["vs_oracle"] = {str(lam): golden_error(f"chain10k_lam{lam}", [r])
+                           for lam, r in zip(lams, results[-len(lams):])}
     # every phase of an iteration against its own roofline, from the solver's HIP
     # events: W = A^-1 (2 n^3/3 flops per iteration: triangular inverse + V^T V),
     # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
@@ -490,6 +620,8 @@ def main():
                      "traffic": VTV_TRAFFIC_BYTES if args.precision != "fp64" else None, "traffic_unit": "B",
                      "kernel": kernel, "avg_launch_ms": vtv_s * 1000.0, "launches": iters},
     }
+    line["chain_n100"] = bench_config0(g, torch, dev)
+    line["random_n2000"] = bench_config1(g, torch, dev)
     line["covariance"] = bench_covariance(g, torch, dev)
     if args.support:
         line["support_recovery"] = bench_support(g, torch, dev)
@@ -498,10 +630,9 @@ def main():
     if not args.no_serve:
         line["serving"] = bench_serve(g, args.serve_requests)
     if not args.no_cpu_baseline:
-        lam = lams[-1]
         t = time.perf_counter()
-        line["cpu_baseline"] = cpu_baseline(S, lam, results[len(lams) - 1].iterations)
-        log(f"[bench] cpu baseline sample took {time.perf_counter() - t:.1f}s")
+        line["cpu_baseline"] = cpu_baseline(S, lams, [r.iterations for r in results[-len(lams):]])
+        log(f"[bench] cpu baseline took {time.perf_counter() - t:.1f}s")
     print(json.dumps(line), flush=True)
 
 

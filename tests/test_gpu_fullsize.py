@@ -1,12 +1,12 @@
 """Parity at the full workload sizes, in the forms the benchmark times.
 
-The oracle needs minutes per solve at n = 10^4, so at full size the results are
-checked through properties that hold at any size and pin the unique minimiser:
-the KKT measure of the returned A recomputed on the CPU from its own Cholesky
-factor (independent of the GPU's W), F(A) recomputed on the CPU, the returned W
-against the CPU inverse, and the mixed forms against the FP64 form (same support,
-F to 1e-8).  The smaller workloads (n = 100, n = 2000) are compared with the
-oracle run itself in test_gpu_solve.py.
+Each result is compared with the oracle's own solution of the same problem, run
+to KKT <= 1e-8 and stored by tests/golden/make_references.py (F to 1e-8
+relative, the same support up to the threshold exemptions), and certified
+through properties that pin the unique minimiser at any size: the KKT measure of
+the returned A recomputed on the CPU from its own Cholesky factor (independent of
+the GPU's W), F(A) recomputed on the CPU, the duality gap, and the returned W
+against the CPU inverse.
 """
 import numpy as np
 import pytest
@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth
+from tests import golden_ref
 from tests.gpu_util import device, to_dev, to_host
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -40,7 +41,10 @@ def dual_gap(S, W, lam, F):
 
 def certify(S, res, lam, tol):
     """KKT, objective and duality gap of the returned A from an independent CPU
-    factorisation."""
+    factorisation.  The gap bound follows from the stopping rule: on the support
+    Z = g + lambda sign(A), so tr(SA) + lambda ||A||_1 - n = sum Z (.) A, and the
+    projection that makes W dual feasible moves it by Z off the support; to first
+    order the gap is at most 2 ||Z||_1 max|A| <= 2 tol ||A||_1 max|A|."""
     A = to_host(res.A)
     chk = oracle.check_solution(S, A, lam)
     assert chk["pd"]
@@ -49,50 +53,68 @@ def certify(S, res, lam, tol):
     assert abs(res.objective - chk["objective"]) <= 1e-11 * abs(chk["objective"])
     assert np.array_equal(A, A.T)
     chk["gap"] = dual_gap(S, chk["W"], lam, chk["objective"])
-    assert -1e-9 * abs(chk["objective"]) <= chk["gap"] <= 1e-3 * abs(chk["objective"]), chk["gap"]
+    bound = 2.0 * tol * np.abs(A).sum() * np.abs(A).max() + 1e-10 * abs(chk["objective"])
+    assert -1e-9 * abs(chk["objective"]) <= chk["gap"] <= bound, (chk["gap"], bound)
     return A, chk
 
 
-def test_chain_n10000(g):
+def against_oracle(res, ref, support=True):
+    """F within 1e-8 of the oracle's and, optionally, the same support."""
+    relF, mism, _ = golden_ref.compare(to_host(res.A), res.objective, ref)
+    assert relF <= 1e-8, relF
+    if support:
+        assert mism == 0, mism
+    return relF, mism
+
+
+@pytest.mark.parametrize("lam", [0.1, 0.2])
+def test_chain_n10000(g, lam):
     """Large single solve: chain n = 10^4, m = 5000, lambda in {0.1, 0.2}, tol 1e-5,
-    BF16x3 form (the benchmark's) and FP64 form."""
+    BF16x3 form (the benchmark's) and FP64 form, against the oracle's solution."""
     S, _ = synth.chain_problem(10000, 5000, 0)
     St = to_dev(S)
     tol = 1e-5
-    for lam in (0.1, 0.2):
-        r64 = g.Solver(precision="fp64").solve(St, lam, tol)
-        rbf = g.Solver(precision="bf16x3").solve(St, lam, tol)
-        assert r64.status == rbf.status == g.CONVERGED
-        A64, chk = certify(S, r64, lam, tol)
-        # the returned W is the inverse of the returned A (CPU inverse as reference)
-        W = to_host(r64.W)
-        assert np.max(np.abs(W - chk["W"])) <= 1e-9 * np.max(np.abs(chk["W"]))
-        # the mixed form reaches the same minimiser: support, F, KKT from its own W
-        Abf = to_host(rbf.A)
-        assert np.array_equal(Abf != 0, A64 != 0)
-        assert abs(rbf.objective - r64.objective) <= 1e-8 * abs(r64.objective)
-        assert np.max(np.abs(Abf - A64)) <= 1e-6 * np.max(np.abs(A64))
-        assert rbf.kkt_rel1 <= tol
-        del r64, rbf
-        torch.cuda.empty_cache()
+    ref = golden_ref.load(f"chain10k_lam{lam}")[0]
+    r64 = g.Solver(precision="fp64").solve(St, lam, tol)
+    rbf = g.Solver(precision="bf16x3").solve(St, lam, tol)
+    assert r64.status == rbf.status == g.CONVERGED
+    A64, chk = certify(S, r64, lam, tol)
+    certify(S, rbf, lam, tol)
+    # the returned W is the inverse of the returned A (CPU inverse as reference)
+    W = to_host(r64.W)
+    assert np.max(np.abs(W - chk["W"])) <= 1e-9 * np.max(np.abs(chk["W"]))
+    print(f"lambda={lam}: fp64 vs oracle {against_oracle(r64, ref, support=False)}, "
+          f"bf16x3 vs oracle {against_oracle(rbf, ref, support=False)}", flush=True)
+    against_oracle(r64, ref)
+    against_oracle(rbf, ref)
 
 
-def test_lambda_path_n1000_32(g):
+@pytest.mark.parametrize("mode,precision,graphs", [("independent", "fp64", False), ("waves", "fp64", True),
+                                                   ("independent", "bf16x3", False)])
+def test_lambda_path_n1000_32(g, mode, precision, graphs):
     """Regularisation path: random sparse n = 1000, m = 500, 32 lambdas from
-    lambda_max to lambda_max/100, warm-started waves with graph-captured
-    iterations (the benchmark's form); every lambda certified on the CPU."""
+    lambda_max to lambda_max/100, against the oracle's solution of every lambda.
+    At the path's tolerance of 1e-5 the stopping rule ||Z||_1 <= tol ||A||_1 leaves
+    F up to 3e-6 (relative) from F* at the large-lambda end (the diagonal start
+    already meets it next to lambda_max), so the bar is checked at tol 1e-8, where
+    every form reaches F to 1e-8 and the oracle's support.  Warm-started waves may
+    differ in one entry of the 25th lambda, (901, 322): the stored solution (oracle
+    to 1e-8) still carries it, while the oracle run on to 2e-9 sets it to zero with
+    |g_ij| - lambda = -4.4e-9, i.e. within 1e-8 of the threshold."""
     S, _ = synth.random_sparse_problem(1000, 500, 0)
     lams = list(synth.lambda_path(S, count=32, ratio=100.0))
-    tol = 1e-5
-    res = g.lambda_path(to_dev(S), lams, tol, mode="waves", waves=4, max_iter=5000, graphs=True)
-    indep = g.lambda_path(to_dev(S), lams, tol, mode="independent", max_iter=5000)
+    refs = golden_ref.load("path1000")
+    tol = 1e-8
+    res = g.lambda_path(to_dev(S), lams, tol, mode=mode, waves=4, max_iter=5000, graphs=graphs,
+                        precision=precision)
     assert len(res) == 32
-    for lam, r, ri in zip(lams, res, indep):
-        assert r.status == ri.status == g.CONVERGED
-        _, c1 = certify(S, r, lam, tol)
-        _, c2 = certify(S, ri, lam, tol)
-        # warm and cold starts reach the same minimiser up to their duality gaps
-        assert abs(r.objective - ri.objective) <= max(c1["gap"], c2["gap"]) + 1e-12 * abs(ri.objective)
+    mism = 0
+    for lam, r, ref in zip(lams, res, refs):
+        assert r.status == g.CONVERGED
+        assert abs(float(ref["lam"]) - lam) <= 1e-15 * lam
+        certify(S, r, lam, tol)
+        mism += against_oracle(r, ref, support=False)[1]
+    assert mism <= (1 if mode == "waves" else 0), mism
     assert res[0].iterations == 0  # lambda_max: the diagonal start is optimal
 
 
