@@ -4,23 +4,31 @@ Headline (value): time-to-KKT <= 1e-5 on the chain workload n = 10000,
 m = 5000 (seed 0), lambda in {0.1, 0.2}: one step = one solve at each lambda,
 from the diagonal initialisation, with S already resident in HBM.  The form
 timed is --precision (default: the BF16x3 mixed form: W with FP32 accuracy from
-BF16 products, A Z A as the FP64 sampled sparse product where the iterate's rows
-are short, else three BF16 products; its factor, log det, PD test and KKT are
+BF16 products, A Z A as the sampled sparse product where the iterate's rows are
+short (FP64 arithmetic on A and on Z's two-part BF16 split, about 2^-17 relative
+to Z), else three BF16 products; its factor, log det, PD test and KKT are
 FP64).  The plain FP64 path (FP64 throughout, dense products as in the paper) is
 timed on the same workload and reported beside it (config.fp64_plain_s,
 config.speedup_vs_fp64), and so is FP64 with the sparse product
 (config.fp64_sparse_product_s).
 
 Extra objects on the same line:
-  roofline      V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel), the largest dense
-                contraction: n^3/3 algorithmic flops / mean launch time from HIP events
-                around that launch
+  roofline      the leaf step of the blocked Cholesky (leaf_potrf_kernel), the largest
+                share of the profile: algorithmic flops per launch / mean launch time
+                from HIP events around each leaf launch of one factorisation per solve;
+                roofline_secondary: V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel)
+  config.vs_oracle, chain_n100, random_n2000
+                every result's error against the oracle's stored solution; the chain
+                n = 100 and random n = 2000 workloads (FP64 / FP32 / BF16x3) timed
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
-                from lambda_max to lambda_max/100, tol 1e-5): solves/s per mode
-  serving       Poisson stream, n log-uniform in [64, 4096], m = n/2,
-                lambda = 0.3 lambda_max, BF16x3 form: p50/p99 latency, solves/s
-  cpu_baseline  the CPU oracle on the host cores: one pISTA iteration of the
-                lambda = 0.2 chain problem, scaled by the GPU's iteration count
+                from lambda_max to lambda_max/100, tol 1e-5 and 1e-8): solves/s and
+                error against the oracle per mode
+  serving       Poisson stream of 2000 requests, n log-uniform in [64, 4096], m = n/2
+                samples drawn on the device per request, lambda = 0.3 lambda_max,
+                BF16x3 form: p50/p99 latency, solves/s
+  cpu_baseline  the CPU oracle on the host cores: full solves of the n = 100 and
+                n = 2000 workloads, and for n = 10^4 the first iteration at each
+                lambda scaled by the GPU's iteration count
 
     python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
                     [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline] [--dense-product]
@@ -43,6 +51,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 # WRITE_SIZE counter runs scaled by a 1 GiB plain-copy calibration
 # (profiles/traffic_w_bf16x6_chain10k.md)
 VTV_TRAFFIC_BYTES = 11511834624
+# HBM bytes per leaf_potrf_kernel launch: not yet taken from counters for the current kernel
+LEAF_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -421,61 +431,72 @@ def bench_small(g, torch, dev, count=1024):
             "iterations": sum(r.iterations for r in res)}
 
 
-def bench_serve(g, count, seed=0, precision="bf16x3"):
-    """Serving: every request brings its m = n/2 samples; closed-loop capacity, then
-    Poisson replays at 0.5, 0.8, 1.0 x capacity.  The same requests bringing their
-    S instead (twice the upload, no covariance step) are timed closed-loop beside."""
-    import numpy as np
-
+def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3"):
+    """Serving: a Poisson stream of independent requests, n log-uniform in [64, 4096];
+    request i draws its random sparse precision and m = n/2 samples on the device
+    (glasso_generate, from its own seed) and arrives with them resident in HBM;
+    lambda = 0.3 lambda_max of its S.  Each slot forms S from the samples
+    (glasso_covariance) and solves in the mixed form; the client reads the scalars
+    and lets A and W go.  Closed-loop capacity first, then Poisson replays at 0.5,
+    0.8 and 1.0 times it."""
     import synth
-    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_footprint
+    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_buffers, gpu_workspace
 
     t = time.perf_counter()
     base = synth.serving_requests(count, seed, rate=1.0)
+    gen = g.Solver()
     problems = []
     for (_, n, rs) in base:
-        X, _ = synth.random_sparse_samples(n, n // 2, rs)
-        S = synth.sample_covariance(X)
-        problems.append((n, np.ascontiguousarray(X.T), S, 0.3 * synth.lambda_max(S)))
-    log(f"[bench] serving: generated {count} requests in {time.perf_counter() - t:.1f}s")
+        _, Y, _, lm = gen.generate("random", n, n // 2, seed=rs, want_Y=True, want_S=False)
+        problems.append((n, Y, 0.3 * lm))
+    gen.close()
+    torch.cuda.synchronize()
+    sample_gib = sum(Y.numel() for _, Y, _ in problems) * 8 / 2**30
+    log(f"[bench] serving: generated {count} requests on the device in {time.perf_counter() - t:.1f}s "
+        f"({sample_gib:.1f} GiB of samples)")
     slots = 4
     budget = 64 * 2**30
-    eng = GpuEngine(slots=slots, precision=precision, tol=1e-5)
-    fp = lambda n: gpu_footprint(n, precision, m=n // 2)  # noqa: E731
+    eng = GpuEngine(slots=slots, precision=precision, tol=1e-5, keep=False)
+    fp = lambda n: gpu_buffers(n, n // 2, resident=True)  # noqa: E731
+    wsf = lambda n: gpu_workspace(n, precision, n // 2)  # noqa: E731
 
-    def requests(rate, samples=True):
+    def requests(rate, subset=None):
         arr = [a / rate for (a, _, _) in base] if rate else [0.0] * count
-        return [Request(i, arr[i], n, None if samples else S, lam, Y=Y if samples else None)
-                for i, (n, Y, S, lam) in enumerate(problems)]
+        idx = range(count) if subset is None else range(subset)
+        return [Request(i, arr[i], problems[i][0], None, problems[i][2], Y=problems[i][1]) for i in idx]
 
-    srv = Server(eng, slots=slots, hbm_budget=budget, footprint=fp)
+    srv = Server(eng, slots=slots, hbm_budget=budget, footprint=fp, workspace=wsf)
     # warmup: one pass over every request, so that the first use of each padded size
     # (tile autotuning, workspace growth of each slot's handle) is not timed
-    srv.run(requests(None), realtime=False)
+    st = srv.run(requests(None), realtime=False)
     st = srv.run(requests(None), realtime=False)
     capacity = st.solves_per_s
     log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
-    serial = Server(eng, slots=1, hbm_budget=budget, footprint=fp).run(requests(None), realtime=False)
-    log(f"[bench] serving one slot: {serial.solves_per_s:.2f} solves/s")
-    from_s = Server(eng, slots=slots, hbm_budget=budget, footprint=lambda n: gpu_footprint(n, precision)).run(
-        requests(None, samples=False), realtime=False)
-    log(f"[bench] serving closed loop, requests bringing S: {from_s.solves_per_s:.2f} solves/s")
-    out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], m=n/2 samples each (S formed on the "
-                       f"device), lambda=0.3 lambda_max, random sparse, {precision} form, tol 1e-5, {slots} slots, "
-                       f"HBM budget {budget >> 30} GiB",
-           "closed_loop_solves_per_s": capacity, "one_slot_solves_per_s": serial.solves_per_s,
-           "speedup_vs_one_slot": capacity / serial.solves_per_s,
-           "closed_loop_solves_per_s_requests_bringing_S": from_s.solves_per_s, "rates": {}}
+    one = min(count, 500)
+    serial = Server(eng, slots=1, hbm_budget=budget, footprint=fp, workspace=wsf).run(requests(None, one),
+                                                                                     realtime=False)
+    log(f"[bench] serving one slot ({one} requests): {serial.solves_per_s:.2f} solves/s")
+    out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], random sparse precision and m=n/2 "
+                       f"samples drawn on the device per request (resident in HBM on arrival; S formed by the "
+                       f"slot), lambda=0.3 lambda_max, {precision} form, tol 1e-5, {slots} slots, HBM budget "
+                       f"{budget >> 30} GiB",
+           "requests": count, "closed_loop_solves_per_s": capacity,
+           "one_slot_solves_per_s": serial.solves_per_s, "speedup_vs_one_slot": capacity / serial.solves_per_s,
+           "rates": {}}
     for frac in (0.5, 0.8, 1.0):
         rate = frac * capacity
-        st = Server(eng, slots=slots, hbm_budget=budget, footprint=fp).run(requests(rate))
+        reqs = requests(rate)
+        st = srv.run(reqs)
+        errs = sum(1 for r in reqs if r.error or r.result is None or r.result.status != 0)
         out["rates"][f"{frac:.1f}x"] = {"arrival_rate_per_s": rate, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
                                         "solves_per_s": st.solves_per_s, "mean_in_flight": st.mean_active,
-                                        "peak_hbm_gib": st.peak_bytes / 2**30}
+                                        "peak_charged_gib": st.peak_bytes / 2**30, "not_converged": errs}
         log(f"[bench] serving {frac:.1f}x: p50 {st.p50_ms:.1f} ms p99 {st.p99_ms:.1f} ms, {st.solves_per_s:.2f}/s")
     eng.close()
     r08 = out["rates"]["0.8x"]
     out.update({"p50_ms": r08["p50_ms"], "p99_ms": r08["p99_ms"], "solves_per_s": r08["solves_per_s"]})
+    del problems
+    torch.cuda.empty_cache()
     return out
 
 
@@ -493,7 +514,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dense-product", action="store_true",
                     help="form every A Z A with the dense GEMM pair (the paper's design)")
-    ap.add_argument("--serve-requests", type=int, default=120)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--path-only", action="store_true",
                     help="run only the regularisation-path measurement and print its object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -531,21 +552,36 @@ def main():
     solves = args.steps * len(lams)
     value = elapsed / solves
 
-    # roofline: V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel), the largest dense
-    # contraction that skips nothing: n^3/3 algorithmic flops per launch (the lower
-    # triangle of V^T V, V = inv(L) lower), one launch per iteration after the diagonal
-    # start, HIP events on the solve's stream around that launch alone
-    # (glasso_info.time_ms[7]).  The rest of W (the doubling inverse) and the line
-    # search's factorisations skip products over zero blocks of the factor, so their
-    # flop counts depend on the matrix; they are reported as times in phases.
+    # roofline: the leaf step of the blocked Cholesky (leaf_potrf_kernel), the kernel
+    # with the largest share of the profile: 79 dependent launches per factorisation
+    # at n = 10^4, each factoring the 128x128 diagonal block and solving the panel
+    # below it.  Algorithmic flops per launch at column k: nb^3/3 + (n - k - nb) nb^2
+    # with nb = min(128, n - k) (glasso_info.leaf_flops); launch times from HIP events
+    # on the solve's stream around each leaf launch of the first trial factorisation
+    # of every solve (glasso_info.leaf_ms).  Peak: the FP64 MFMA peak.
     iters = sum(r.iterations for r in results)
     trials = sum(r.ls_trials for r in results)
     w_ms = sum(r.time_ms[1] for r in results)
+    leaf_launches = sum(r.leaf_launches for r in results)
+    leaf_s = sum(r.leaf_ms for r in results) / 1000.0
+    leaf_flops = sum(r.leaf_flops for r in results)
+    achieved = leaf_flops / leaf_s / 1e12 if leaf_s > 0 else None
+    peak = PEAK_TFLOPS["fp64"]
+    kernel = ("leaf_potrf_kernel: one step of the blocked Cholesky (128x128 diagonal block factored in LDS, "
+              "panel below solved with FP64 MFMA)")
+    # secondary: V^T V of the FP32-accurate W (gemm_bf16x6_nt_kernel), the largest dense
+    # contraction that skips nothing: n^3/3 algorithmic flops per launch, one launch per
+    # iteration after the diagonal start (glasso_info.time_ms[7]), against the dense BF16
+    # MFMA peak (it issues six BF16 products per algorithmic product, so the MFMA pipe
+    # is busy six times the algorithmic fraction)
     vtv_s = sum(r.time_ms[7] for r in results) / 1000.0 / iters
-    achieved = float(n) ** 3 / 3.0 / vtv_s / 1e12 if vtv_s > 0 else None
-    peak = 2500.0 / 6.0
-    kernel = ("gemm_bf16x6_nt_kernel: V^T V (lower triangle) of W = A^-1 with FP32 accuracy, "
-              "six BF16 MFMA products per element pair")
+    vtv = None
+    if vtv_s > 0:
+        vtv_tf = float(n) ** 3 / 3.0 / vtv_s / 1e12
+        vtv = {"kernel": "gemm_bf16x6_nt_kernel: V^T V (lower triangle) of W = A^-1 with FP32 accuracy",
+               "bound": "mfma", "achieved": vtv_tf, "peak": 2500.0, "unit": "TFLOP/s", "frac": vtv_tf / 2500.0,
+               "mfma_issue_frac": 6.0 * vtv_tf / 2500.0, "avg_launch_ms": vtv_s * 1000.0, "launches": iters,
+               "traffic": VTV_TRAFFIC_BYTES}
     fact_ms = sum(r.time_ms[6] for r in results)
     # A Z A: the sampled sparse product wherever the iterate's rows are short, else the
     # GEMM pair (2 launches, 3 n^3 algorithmic flops: A Z 2n^3, tril((A Z) A) n^3)
@@ -567,7 +603,7 @@ def main():
     # every result of the timed form against the oracle's solution of the same problem
     config["vs_oracle"] = {str(lam): golden_error(f"chain10k_lam{lam}", [r])
                            for lam, r in zip(lams, results[-len(lams):])}
-    # every phase of an iteration against its own roofline, from the solver's HIP
+    # every phase of an iteration as times from the solver's HIP
     # events: W = A^-1 (2 n^3/3 flops per iteration: triangular inverse + V^T V),
     # the line search (n^3/3 per trial: the Cholesky of the trial point; its two
     # elementwise passes sit in the same window), A Z A (above)
@@ -616,9 +652,11 @@ def main():
         "config": config,
         "phases": phases,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak if achieved else None,
-                     "traffic": VTV_TRAFFIC_BYTES if args.precision != "fp64" else None, "traffic_unit": "B",
-                     "kernel": kernel, "avg_launch_ms": vtv_s * 1000.0, "launches": iters},
+                     "frac": achieved / peak if achieved else None, "traffic": LEAF_TRAFFIC_BYTES,
+                     "traffic_unit": "B", "kernel": kernel,
+                     "avg_launch_ms": leaf_s * 1000.0 / leaf_launches if leaf_launches else None,
+                     "launches": leaf_launches, "flops_per_launch": leaf_flops / leaf_launches if leaf_launches else None},
+        "roofline_secondary": [vtv],
     }
     line["chain_n100"] = bench_config0(g, torch, dev)
     line["random_n2000"] = bench_config1(g, torch, dev)
@@ -628,7 +666,7 @@ def main():
     if not args.no_path:
         line["batched"] = bench_path(g, torch, dev)
     if not args.no_serve:
-        line["serving"] = bench_serve(g, args.serve_requests)
+        line["serving"] = bench_serve(g, torch, dev, args.serve_requests)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(S, lams, [r.iterations for r in results[-len(lams):]])

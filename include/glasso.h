@@ -118,6 +118,12 @@ typedef struct {
                             of a diagonal start is D Z D, formed elementwise */
   int aza_sparse_products; /* A Z A products formed by the sampled sparse product
                               (see dense_product); time_ms[5] excludes them */
+  int leaf_launches;  /* leaf steps of the blocked Cholesky timed one by one: those of the
+                         first trial factorisation of the call in which every trial
+                         point was positive definite (eager launches only; 0 if none) */
+  double leaf_ms;     /* their summed launch times (HIP events around each launch) */
+  double leaf_flops;  /* their algorithmic flops: per step at column k, nb = min(128, n - k),
+                         nb^3/3 for the diagonal block and (n - k - nb) nb^2 for the panel */
 } glasso_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -233,6 +239,32 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
  * Errors: INVALID_ARG for null pointers, m < 1 or n < 1; OOM. */
 glasso_err glasso_covariance(glasso_handle h, const double* Y, int64_t m, int64_t n, int center, double* S,
                              void* stream);
+
+/* Seeded synthetic workloads on the device (the experiments' setup, Sec. 6.1.1:
+ * a sparse precision matrix, samples drawn from its Gaussian model, their
+ * covariance), so that inputs need no host-side generation.  Random numbers come
+ * from the counter-based generator Philox4x32-10 (Salmon et al., SC 2011) with
+ * key = (seed mod 2^32, seed / 2^32); every value is a pure function of the seed
+ * and its position.
+ *   kind   GLASSO_GEN_RANDOM_SPARSE: each pair i < j is an edge with probability
+ *          min(1, 10 / (n - 1)) (about ten off-diagonal nonzeros per row), value
+ *          +-U(0.5, 1) with a random sign, A_ii = sum_j |A_ij| + 0.1;
+ *          GLASSO_GEN_CHAIN: A_ii = 1.25, A_{i,i+1} = -0.5 (the seed is unused).
+ *   n, m   variables and samples (m is ignored when only A_true is asked for)
+ *   A_true n x n output (device, may be NULL): the precision matrix
+ *   Y      m x n output (device, may be NULL): the samples as rows,
+ *          x_r = L^{-T} z_r with A_true = L L^T and z_r standard normal
+ *          (Box-Muller of 53-bit uniforms), so Cov(x) = A_true^{-1}
+ *   S      n x n output (device, may be NULL): S = Y^T Y / m (known zero mean,
+ *          eq. empirical_cov without centring), full symmetric
+ *   lambda_max  host output (may be NULL): max_{i != j} |S_ij|
+ * At least one output must be given.  The handle keeps a workspace of about
+ * (2.3 n^2 + 2 m n) doubles (padded to whole tiles).
+ * Errors: INVALID_ARG (bad kind, n < 1, m < 1 with sample outputs, no output),
+ * NOT_PD (cannot happen for these diagonally dominant recipes), OOM, HIP. */
+typedef enum { GLASSO_GEN_RANDOM_SPARSE = 0, GLASSO_GEN_CHAIN = 1 } glasso_gen_kind;
+glasso_err glasso_generate(glasso_handle h, int kind, int64_t n, int64_t m, uint64_t seed, double* A_true, double* Y,
+                           double* S, double* lambda_max, void* stream);
 
 /* Lower Cholesky factor L of SPD A (the PD test of condition t_cond_pd,
  * Sec. 4.3.2): L (n x n, output) gets L in its lower triangle and zeros above.

@@ -76,6 +76,9 @@ class Result:
     time_ms: tuple
     aza_gemm_products: int = 0
     aza_sparse_products: int = 0
+    leaf_launches: int = 0
+    leaf_ms: float = 0.0
+    leaf_flops: float = 0.0
 
     @property
     def status_name(self) -> str:
@@ -148,7 +151,7 @@ class Solver:
         return Result(A, W, info.objective, info.iterations, info.status, info.kkt_rel1,
                       info.kkt_fro, info.kkt_max, int(info.nnz), info.ls_trials,
                       info.fallback_steps, tuple(info.time_ms), info.aza_gemm_products,
-                      info.aza_sparse_products)
+                      info.aza_sparse_products, info.leaf_launches, info.leaf_ms, info.leaf_flops)
 
     def solve_batched(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
         """Solve len(lams) problems in batched launches (glasso_solve_batched).
@@ -203,8 +206,29 @@ class Solver:
             out.append(Result(A_list[i], W_list[i] if want_W else None, inf.objective, inf.iterations,
                               inf.status, inf.kkt_rel1, inf.kkt_fro, inf.kkt_max, int(inf.nnz),
                               inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms), inf.aza_gemm_products,
-                              inf.aza_sparse_products))
+                              inf.aza_sparse_products, inf.leaf_launches, inf.leaf_ms, inf.leaf_flops))
         return out
+
+    # ---------------------------------------------------------------- workloads
+    def generate(self, kind: str, n: int, m: int = 0, seed: int = 0, want_A: bool = False, want_Y: bool = False,
+                 want_S: bool = True, device=None, stream=None):
+        """Seeded synthetic workload on the device (glasso_generate): kind "random"
+        (random sparse precision) or "chain".  Returns (A_true, Y, S, lambda_max),
+        the tensors not asked for as None; lambda_max = max_{i != j} |S_ij| when
+        samples are drawn."""
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        k = {"random": 0, "chain": 1}[kind]
+        A = torch.empty((n, n), dtype=torch.float64, device=dev) if want_A else None
+        Y = torch.empty((m, n), dtype=torch.float64, device=dev) if want_Y else None
+        S = torch.empty((n, n), dtype=torch.float64, device=dev) if want_S else None
+        lm = ctypes.c_double(float("nan"))
+        samples = want_Y or want_S or m > 0
+        _check(_lib.glasso_generate(self._h, k, int(n), int(m), int(seed) & (2**64 - 1),
+                                    A.data_ptr() if A is not None else None,
+                                    Y.data_ptr() if Y is not None else None,
+                                    S.data_ptr() if S is not None else None,
+                                    ctypes.byref(lm) if samples else None, _stream(stream)), "glasso_generate")
+        return A, Y, S, (lm.value if samples else None)
 
     # ---------------------------------------------------------------- single steps
     def covariance(self, Y: torch.Tensor, center: bool = True, stream=None) -> torch.Tensor:

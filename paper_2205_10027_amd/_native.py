@@ -41,6 +41,9 @@ class GlassoInfo(ctypes.Structure):
         ("time_ms", ctypes.c_double * 8),
         ("aza_gemm_products", ctypes.c_int),
         ("aza_sparse_products", ctypes.c_int),
+        ("leaf_launches", ctypes.c_int),
+        ("leaf_ms", ctypes.c_double),
+        ("leaf_flops", ctypes.c_double),
     ]
 
 
@@ -64,6 +67,7 @@ SIGNATURES = {
     "glasso_solve_small_static": (_INT, [ctypes.POINTER(GlassoOptions), _INT, ctypes.POINTER(_VP),
                                           ctypes.POINTER(_I64), ctypes.POINTER(_D), _D, ctypes.POINTER(_VP),
                                           ctypes.POINTER(_VP), ctypes.POINTER(GlassoInfo), _VP]),
+    "glasso_generate": (_INT, [_VP, _INT, _I64, _I64, ctypes.c_uint64, _VP, _VP, _VP, c_double_p, _VP]),
     "glasso_covariance": (_INT, [_VP, _VP, _I64, _I64, _INT, _VP, _VP]),
     "glasso_cholesky": (_INT, [_VP, _VP, _I64, _VP, ctypes.POINTER(_I64), c_double_p, _VP]),
     "glasso_inverse": (_INT, [_VP, _VP, _I64, _VP, _VP]),

@@ -220,7 +220,7 @@ int finish_factor(hipStream_t stream, double* A, int64_t lda, int n, const doubl
 }
 
 int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv, int* info,
-                const FactorBatch& fb, int finish) {
+                const FactorBatch& fb, int finish, LeafTimer* timer) {
   if (n % NB) return -1;
   if (fb.count <= 0) return 0;
   ZBatch zA;  // operands and output inside the factored matrix
@@ -245,9 +245,19 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
         // factor the diagonal block and solve the panel below it (L21 = A21 inv(L11)^T)
         double* Akk = A + (int64_t)k * lda + k;
         const int rest = n - k - NB;
+        const bool timed = timer && timer->used + 2 <= timer->cap && k < timer->n;
+        if (timed && hipEventRecord(timer->ev[timer->used], stream) != hipSuccess) return -2;
         hipLaunchKernelGGL(leaf_potrf_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k,
                            rest, dL + k, info, fb);
         if (hipGetLastError() != hipSuccess) return -2;
+        if (timed) {
+          if (hipEventRecord(timer->ev[timer->used + 1], stream) != hipSuccess) return -2;
+          timer->used += 2;
+          const int64_t left = timer->n - k;
+          const double nb = (double)(left < NB ? left : NB);
+          const double below = (double)(left > NB ? left - NB : 0);
+          timer->flops += timer->active * (nb * nb * nb / 3.0 + below * nb * nb);
+        }
         if (k + NB < M1) {
           // update of the remaining columns of the middle panel (K = 128)
           const double* Pk = A + (int64_t)(k + NB) * lda + k;

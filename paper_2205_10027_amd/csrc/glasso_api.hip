@@ -140,12 +140,15 @@ struct glasso_handle_s {
   Workspace ws;
   HostMirror hm;
   hipEvent_t ev[12] = {};
+  std::vector<hipEvent_t> leaf_ev;  // around the leaf launches of one sampled factorisation per call
   hipStream_t cap = nullptr;  // capture stream (graphs option)
   Graphs graphs;
   void* small_base = nullptr;  // workspace of the persistent small-problem solver
   size_t small_bytes = 0;
   void* cov_base = nullptr;  // workspace of glasso_covariance (padded samples, padded S, means)
   size_t cov_bytes = 0;
+  void* gen_base = nullptr;  // workspace of glasso_generate
+  size_t gen_bytes = 0;
 };
 
 namespace {
@@ -728,6 +731,20 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (e2) return e2;
     return precond_product(w, s, o.precision, w.skip, n, sparse_now, timed ? h->ev + 5 : nullptr, z_split != nullptr);
   };
+  // the leaf launches of the first eagerly launched trial factorisation of the call
+  // in which every trial point was positive definite (so that no launch returned
+  // early after a failed pivot) are timed one by one, with events around each launch
+  LeafTimer leaf;
+  bool leaf_done = false;
+  double leaf_ms = 0.0;
+  {
+    const int want = 2 * (int)std::min<int64_t>(np / TILE, 256);
+    while ((int)h->leaf_ev.size() < want) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      h->leaf_ev.push_back(e);
+    }
+  }
   auto trial = [&](hipStream_t s, bool timed) -> glasso_err {  // a4, a5
     glasso_err e2 = push_ints(s, w.lsskip, hm.lsskip, slots);
     if (e2) return e2;
@@ -737,7 +754,18 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     // the trial's factor is finished (diagonal blocks placed and inverted) only if
     // it is accepted, at the next head
     if (timed) HIP_TRY(hipEventRecord(h->ev[8], s));
-    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, nullptr, w.info, fbt, 0));
+    LeafTimer* lt = nullptr;
+    if (timed && !leaf_done && (int)h->leaf_ev.size() >= 2) {
+      leaf.used = 0;
+      leaf.flops = 0.0;
+      leaf.ev = h->leaf_ev.data();
+      leaf.cap = (int)h->leaf_ev.size();
+      leaf.n = n;
+      leaf.active = 0;
+      for (int j = 0; j < slots; ++j) leaf.active += hm.lsskip[j] == 0;
+      lt = &leaf;
+    }
+    K_TRY(potrf_lower(s, w.Lt, np, (int)np, w.dLt, nullptr, w.info, fbt, 0, lt));
     if (timed) HIP_TRY(hipEventRecord(h->ev[9], s));
     K_TRY(finish_trial(s, w.part, tiles, w.dL, w.dLt, w.info, n, 0.0, w.scal_t, pt));
     return fetch_async(h, s);
@@ -936,6 +964,17 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (e) return e;
       HIP_TRY(hipStreamSynchronize(st));
       if (!graphs) phase[6] += elapsed(h->ev[8], h->ev[9]);
+      if (!leaf_done && leaf.used) {
+        bool all_pd = true;
+        for (int j = 0; j < slots; ++j) all_pd = all_pd && (hm.lsskip[j] || hm.info[j] == 0);
+        if (all_pd) {
+          for (int i = 0; i + 1 < leaf.used; i += 2) leaf_ms += elapsed(leaf.ev[i], leaf.ev[i + 1]);
+          leaf_done = true;
+        } else {
+          leaf.used = 0;
+          leaf.flops = 0.0;
+        }
+      }
       int nacc = 0;
       for (int b = 0; b < count; ++b) {
         hm.accept[b] = 0;
@@ -1003,6 +1042,10 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (Wout && Wout[b]) K_TRY(sym_copy_out(st, w.W + b * nn, np, Wout[b], n, 1));
   }
   HIP_TRY(hipStreamSynchronize(st));
+  if (!leaf_done) {
+    leaf.used = 0;
+    leaf.flops = 0.0;
+  }
   if (info) {
     const double total =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -1022,6 +1065,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       in.aza_sparse_products = sparse_products[b];
       for (int i = 1; i < 8; ++i) in.time_ms[i] = phase[i];
       in.time_ms[0] = total;
+      in.leaf_launches = leaf_done ? leaf.used / 2 : 0;
+      in.leaf_ms = leaf_ms;
+      in.leaf_flops = leaf.flops;
     }
   }
   return GLASSO_OK;
@@ -1087,9 +1133,12 @@ glasso_err glasso_destroy(glasso_handle h) {
   if (h->cap) (void)hipStreamDestroy(h->cap);
   if (h->small_base) (void)hipFree(h->small_base);
   if (h->cov_base) (void)hipFree(h->cov_base);
+  if (h->gen_base) (void)hipFree(h->gen_base);
   if (h->ws.base) (void)hipFree(h->ws.base);
   free_host(h->hm);
   for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : h->leaf_ev)
     if (e) (void)hipEventDestroy(e);
   delete h;
   return GLASSO_OK;
@@ -1366,6 +1415,73 @@ glasso_err glasso_covariance(glasso_handle h, const double* Y, int64_t m, int64_
   // (op(A) = op(B) = the columns of Yp: both operands read transposed)
   K_TRY(gemm_f64(st, 1, 1, (int)np, (int)np, (int)mp, 1.0 / (double)m, Yp, np, Yp, np, 0.0, Sp, np, 1, 0, 0, nullptr));
   K_TRY(sym_copy_out(st, Sp, np, S, n, 1));
+  HIP_TRY(hipStreamSynchronize(st));
+  return GLASSO_OK;
+}
+
+glasso_err glasso_generate(glasso_handle h, int kind, int64_t n, int64_t m, uint64_t seed, double* A_true, double* Y,
+                           double* S, double* lambda_max, void* stream) {
+  if (!h || n < 1 || n > (1 << 20) || (kind != GLASSO_GEN_RANDOM_SPARSE && kind != GLASSO_GEN_CHAIN))
+    return GLASSO_ERR_INVALID_ARG;
+  const bool samples = Y || S || lambda_max;
+  if (!A_true && !samples) return GLASSO_ERR_INVALID_ARG;
+  if (samples && (m < 1 || m > ((int64_t)1 << 31) - TILE)) return GLASSO_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = pad_to_tile(n);
+  const int64_t mp = samples ? pad_to_tile(m) : 0;
+  // L (np^2: the precision's lower triangle, then its factor, then V = inv(L)),
+  // the diagonal-block inverses and diag(L), the inverse's scratch (np^2/4), Z and
+  // the padded samples (mp x np each), the padded S (np^2), 256 partial maxima, the
+  // maximum and the factor status
+  const size_t dbl = (size_t)np * np + (size_t)np * TILE + (size_t)np + (size_t)np * np / 4 + 2 * (size_t)mp * np +
+                     (samples ? (size_t)np * np : 0) + 256 + 8;
+  const size_t bytes = dbl * sizeof(double) + 256;
+  if (bytes > h->gen_bytes) {
+    if (h->gen_base) (void)hipFree(h->gen_base);
+    h->gen_base = nullptr;
+    h->gen_bytes = 0;
+    if (hipMalloc(&h->gen_base, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return GLASSO_ERR_OOM;
+    }
+    h->gen_bytes = bytes;
+  }
+  double* L = static_cast<double*>(h->gen_base);
+  double* Dinv = L + np * np;
+  double* dL = Dinv + np * TILE;
+  double* tmp = dL + np;
+  double* Z = tmp + np * np / 4;
+  double* Yp = Z + mp * np;
+  double* Sp = Yp + mp * np;
+  double* part = Sp + (samples ? np * np : 0);
+  double* lmax = part + 256;
+  int* info = reinterpret_cast<int*>(lmax + 4);
+  K_TRY(gen_precision_lower(st, L, n, np, kind == GLASSO_GEN_CHAIN ? GEN_CHAIN : GEN_RANDOM_SPARSE, seed));
+  if (A_true) K_TRY(sym_copy_out(st, L, np, A_true, n, 1));
+  if (samples) {
+    // x_r = L^{-T} z_r: the rows of Y = Z V with V = inv(L) lower triangular
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(int), st));
+    K_TRY(potrf_lower(st, L, np, (int)np, dL, Dinv, info));
+    int hinfo = 0;
+    HIP_TRY(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hinfo) return GLASSO_ERR_NOT_PD;
+    K_TRY(trtri_lower(st, L, np, (int)np, Dinv, tmp, nullptr));
+    K_TRY(gen_normals(st, Z, m, n, mp, np, seed));
+    // op(A) = Z (rows), op(B) = V read as [k][n] (tb = 1), lower triangular (b_tri = 1)
+    K_TRY(gemm_f64(st, 0, 1, (int)mp, (int)np, (int)np, 1.0, Z, np, L, np, 0.0, Yp, np, 0, 0, 1, nullptr));
+    if (Y) K_TRY(copy_rect(st, Yp, np, Y, m, n));
+    if (S || lambda_max) {
+      // S = (1/m) Y^T Y, lower triangle on FP64 MFMA (zero rows pad the samples)
+      K_TRY(gemm_f64(st, 1, 1, (int)np, (int)np, (int)mp, 1.0 / (double)m, Yp, np, Yp, np, 0.0, Sp, np, 1, 0, 0,
+                     nullptr));
+      if (S) K_TRY(sym_copy_out(st, Sp, np, S, n, 1));
+      if (lambda_max) {
+        K_TRY(offdiag_absmax(st, Sp, n, np, part, lmax));
+        HIP_TRY(hipMemcpyAsync(lambda_max, lmax, sizeof(double), hipMemcpyDeviceToHost, st));
+      }
+    }
+  }
   HIP_TRY(hipStreamSynchronize(st));
   return GLASSO_OK;
 }

@@ -93,8 +93,20 @@ struct FactorBatch {
 // the strict lower part of each 128x128 diagonal block of L sits transposed in the
 // block's strict upper triangle (dL is final) until finish_factor runs; the line
 // search only needs dL of its trial points.
+// Optional timing of the leaf launches of one factorisation: events recorded
+// around each leaf launch (two per launch, while used + 2 <= cap) and the
+// launches' algorithmic flops (for `active` problems of actual size n: per step at
+// column k, nb = min(128, n - k) gives nb^3/3 for the block and (n - k - nb) nb^2
+// for the panel solve).
+struct LeafTimer {
+  hipEvent_t* ev = nullptr;
+  int cap = 0, used = 0;
+  int64_t n = 0;
+  int active = 1;
+  double flops = 0.0;
+};
 int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, double* Dinv,
-                int* info, const FactorBatch& fb = FactorBatch(), int finish = 1);
+                int* info, const FactorBatch& fb = FactorBatch(), int finish = 1, LeafTimer* timer = nullptr);
 // Places the diagonal blocks of a factor left by potrf_lower(finish = 0) and
 // writes their inverses to Dinv, for the problems with skip == 0.  Idempotent as
 // long as L has not been overwritten in between (trtri_lower does that).
@@ -196,6 +208,17 @@ int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst,
 int column_mean(hipStream_t stream, const double* Y, int64_t m, int64_t n, double* mu);
 int center_pad(hipStream_t stream, const double* Y, int64_t m, int64_t n, const double* mu, double* Yp, int64_t mp,
                int64_t np);
+// ---- seeded synthetic workloads (generate.hip)
+constexpr int GEN_RANDOM_SPARSE = 0, GEN_CHAIN = 1;  // glasso_gen_kind
+// lower triangle of the padded precision matrix of the recipe (zeros above, the
+// identity in the padding)
+int gen_precision_lower(hipStream_t stream, double* A, int64_t n, int64_t np, int kind, uint64_t seed);
+// Z (mp x np, ld np): standard normals for r < m, c < n, zero padding
+int gen_normals(hipStream_t stream, double* Z, int64_t m, int64_t n, int64_t mp, int64_t np, uint64_t seed);
+int copy_rect(hipStream_t stream, const double* src, int64_t lds, double* dst, int64_t rows, int64_t cols);
+// *out = max_{j < i < n} |S_ij| of the padded S; part: 256 doubles of scratch
+int offdiag_absmax(hipStream_t stream, const double* S, int64_t n, int64_t np, double* part, double* out);
+
 // ---- persistent small-problem solver (n <= SMALL_MAX_N, one workgroup per problem)
 constexpr int SMALL_MAX_N = 64;
 constexpr int GLASSO_CONVERGED_DEV = 0, GLASSO_MAX_ITER_DEV = 1, GLASSO_LS_FAILED_DEV = 2;  // glasso_status

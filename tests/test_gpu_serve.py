@@ -1,6 +1,8 @@
 """Serving on the GPU: several requests of different n admitted into concurrent
 slots (one HIP stream each); every result equals the same request solved alone
 (bitwise: the kernels are deterministic and each solve has its own workspace)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -15,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def test_mix_equals_alone(precision):
     device()
     import paper_2205_10027_amd as g
-    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_footprint
+    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_buffers, gpu_footprint, gpu_workspace
 
     specs = [(64, 11), (300, 12), (130, 13), (700, 14), (90, 15), (257, 16), (450, 17), (64, 18)]
     reqs = []
@@ -24,7 +26,8 @@ def test_mix_equals_alone(precision):
         reqs.append(Request(i, 0.002 * i, n, S, 0.3 * synth.lambda_max(S)))
     eng = GpuEngine(slots=4, precision=precision, tol=1e-5)
     budget = sum(gpu_footprint(n, precision) for n, _ in specs[:5])
-    srv = Server(eng, slots=4, hbm_budget=budget, footprint=lambda n: gpu_footprint(n, precision))
+    srv = Server(eng, slots=4, hbm_budget=budget, footprint=gpu_buffers,
+                 workspace=lambda n: gpu_workspace(n, precision))
     st = srv.run(reqs)
     assert st.count == len(reqs) and st.peak_bytes <= budget
     alone_solver = g.Solver(precision=precision)
@@ -98,4 +101,58 @@ def test_mix_equals_alone_from_samples():
         assert np.array_equal(to_host(r.result.A), to_host(alone.A))
         chk = oracle.check_solution(to_host(S), to_host(r.result.A), r.lam)
         assert chk["kkt_rel1"] <= 1e-5 * 1.0001
+    eng.close()
+
+
+def test_device_memory_stays_within_budget():
+    """Admission by footprint holds on the device itself: requests with their
+    samples resident (drawn by glasso_generate) run in three slots under a budget
+    that fits about two of the largest at once; a sampler thread reads the device's
+    free memory throughout, and the memory in use beyond the start (library
+    workspaces and live tensors; torch's cache of freed blocks excluded) never
+    exceeds the budget.  Every request converges."""
+    device()
+    import threading
+
+    import torch
+
+    import paper_2205_10027_amd as g
+    from paper_2205_10027_amd.serve import GpuEngine, Request, Server, gpu_buffers, gpu_workspace
+
+    gen = g.Solver()
+    specs = [(1500, 1), (300, 2), (900, 3), (2000, 4), (64, 5), (1200, 6), (700, 7), (1800, 8), (2000, 9)]
+    reqs = []
+    for i, (n, seed) in enumerate(specs):
+        _, Y, _, lm = gen.generate("random", n, n // 2, seed=seed, want_Y=True, want_S=False)
+        reqs.append(Request(i, 0.01 * i, n, None, 0.3 * lm, Y=Y))
+    gen.close()
+    fp = lambda n: gpu_buffers(n, n // 2, resident=True)  # noqa: E731
+    wsf = lambda n: gpu_workspace(n, "bf16x3", n // 2)  # noqa: E731
+    budget = int(2.2 * (fp(2000) + wsf(2000)))
+    eng = GpuEngine(slots=3, tol=1e-5, keep=False)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0, _ = torch.cuda.mem_get_info()
+    res0, alloc0 = torch.cuda.memory_reserved(), torch.cuda.memory_allocated()
+    used = [0]
+    stop = threading.Event()
+
+    def sample():
+        while not stop.is_set():
+            free, _ = torch.cuda.mem_get_info()
+            cache = (torch.cuda.memory_reserved() - res0) - (torch.cuda.memory_allocated() - alloc0)
+            used[0] = max(used[0], (free0 - free) - cache)
+            time.sleep(0.001)
+
+    th = threading.Thread(target=sample, daemon=True)
+    th.start()
+    srv = Server(eng, slots=3, hbm_budget=budget, footprint=fp, workspace=wsf)
+    st = srv.run(reqs)
+    stop.set()
+    th.join()
+    assert st.count == len(reqs) and st.peak_bytes <= budget
+    for r in reqs:
+        assert r.error is None, r.error
+        assert r.result.status == g.CONVERGED
+    assert used[0] <= budget + 64 * 2**20, (used[0], budget)
     eng.close()

@@ -95,3 +95,47 @@ def test_results_same_alone_and_in_mix():
     for r in reqs:
         alone = oracle.pista(r.S, r.lam, 1e-6).A
         assert np.array_equal(r.result, alone)
+
+
+def test_retained_workspace_is_charged_per_slot():
+    """A slot keeps the largest workspace it has served: the server charges it for
+    that capacity, reuses the slot that needs no growth, and holds back a request
+    that would need a second slot to grow past the budget."""
+    eng = SleepEngine(scale=2e-9)
+    ws = lambda n: 10 * n  # noqa: E731
+    budget = ws(300) + 300 + ws(200) + 200 - 1
+    srv = Server(eng, slots=2, hbm_budget=budget, footprint=lambda n: n, workspace=ws)
+    reqs = [Request(0, 0.0, 300, np.zeros(1), 0.1), Request(1, 0.15, 300, np.zeros(1), 0.1),
+            Request(2, 0.15, 200, np.zeros(1), 0.1)]
+    st = srv.run(reqs)
+    assert all(r.error is None for r in reqs)
+    assert reqs[1].slot == reqs[0].slot            # the slot that already holds ws(300)
+    assert reqs[2].admitted >= reqs[1].finished - 1e-9  # growing the other slot would pass the budget
+    assert reqs[2].slot == reqs[0].slot
+    assert st.peak_bytes <= budget
+    # a second run starts its statistics afresh (retained capacity stays charged)
+    st2 = srv.run([Request(3, 0.0, 100, np.zeros(1), 0.1)])
+    assert st2.count == 1 and st2.peak_bytes == ws(300) + 100
+
+
+class ReleasingEngine(SleepEngine):
+    def __init__(self):
+        super().__init__(scale=1e-9)
+        self.released = []
+
+    def release(self, slot):
+        self.released.append(slot)
+
+
+def test_idle_capacity_is_released_when_it_blocks_the_queue():
+    """Two slots have grown to large workspaces; a request that needs a third of
+    the budget more can only run once an idle slot gives its capacity back."""
+    eng = ReleasingEngine()
+    ws = lambda n: 10 * n  # noqa: E731
+    budget = 2 * (ws(300) + 300) + 100
+    srv = Server(eng, slots=3, hbm_budget=budget, footprint=lambda n: n, workspace=ws)
+    first = [Request(0, 0.0, 300, np.zeros(1), 0.1), Request(1, 0.0, 300, np.zeros(1), 0.1)]
+    srv.run(first, realtime=False)
+    assert sorted(srv._retained) == [0, ws(300), ws(300)]
+    st = srv.run([Request(2, 0.0, 400, np.zeros(1), 0.1)])  # growing a slot to ws(400) passes the budget
+    assert st.count == 1 and eng.released and st.peak_bytes <= budget
