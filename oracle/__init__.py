@@ -32,6 +32,7 @@ from .reference import (  # noqa: F401
     direction,
     trial_point,
     objective_change,
+    predicted_change,
     cond_fallback_step,
     pista,
     PistaResult,

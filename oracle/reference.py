@@ -13,7 +13,10 @@ full dense matrices and no blocking or fusion.  Readings of ambiguous passages
     and Sec. 4.3.2); we evaluate it as M (.) ST(A - tB, tC), which is that value
     without the rounding of A + (-A + s).  Off the free set A_ij is already 0.
   * Line search: t = 1, halved until the trial is PD and F strictly decreases
-    (Sec. 4.3.2).  Below t = 1e-4 the step becomes min(t, (0.9/cond(A))^2) and
+    (Sec. 4.3.2).  Optionally (sigma > 0) the decrease must reach sigma times the
+    decrease predicted by the linear model of f plus the l1 term,
+    <g, At - A> + lam (||At||_1 - ||A||_1) (an Armijo rule); sigma = 0 is the
+    paper's strict decrease.  Below t = 1e-4 the step becomes min(t, (0.9/cond(A))^2) and
     halving continues down to 1e-12, after which the search fails (Sec. 6).
   * The decrease is evaluated in difference form,
         F(At) - F(A) = 2 sum_i log(L_ii / Lt_ii) + sum S (.) (At - A)
@@ -176,6 +179,13 @@ def objective_change(S, A, At, L, Lt, lam) -> float:
     return dlog + dtr + dl1
 
 
+def predicted_change(g: np.ndarray, A: np.ndarray, At: np.ndarray, lam: float) -> float:
+    """<g, At - A> + lam (||At||_1 - ||A||_1): the change of F that its linear model
+    (gradient of f, exact l1 term) predicts for the step from A to At; negative for
+    a descent step.  The Armijo rule accepts At when F(At) - F(A) < sigma times it."""
+    return float(np.sum(g * (At - A))) + lam * float(np.sum(np.abs(At)) - np.sum(np.abs(A)))
+
+
 def cond_fallback_step(A: np.ndarray, factor: float = 0.9) -> float:
     """t = (0.9 / cond(A))^2, the step assumed safe once t drops below 1e-4 (Sec. 6).
     cond(A) = lambda_max / lambda_min (2-norm condition number)."""
@@ -200,8 +210,10 @@ class PistaResult:
 
 def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
           t0: float = 1.0, shrink: float = 0.5, t_floor: float = 1e-4,
-          t_min: float = 1e-12) -> PistaResult:
-    """pISTA(S, lam, A0) (Alg. 1) with the stopping rule and line search of Sec. 6."""
+          t_min: float = 1e-12, sigma: float = 0.0) -> PistaResult:
+    """pISTA(S, lam, A0) (Alg. 1) with the stopping rule and line search of Sec. 6;
+    sigma > 0 asks each step for sigma times its predicted decrease (see
+    predicted_change)."""
     S = np.asarray(S, dtype=np.float64)
     n = S.shape[0]
     A = initial_iterate(S, lam) if A0 is None else np.array(A0, dtype=np.float64)
@@ -246,7 +258,8 @@ def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
             trials += 1
             if Lt is not None:
                 dF = objective_change(S, A, At, L, Lt, lam)
-                if dF < 0.0:
+                target = sigma * predicted_change(g, A, At, lam) if sigma > 0.0 else 0.0
+                if dF < target:
                     accepted = (At, Lt, dF)
                     break
             t *= shrink
@@ -256,6 +269,7 @@ def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
         if accepted is None:
             return PistaResult(A, W, F, k, LS_FAILED, km["kkt_rel1"], km["kkt_fro"],
                                km["kkt_max"], total_trials, history)
+        rec["pred"] = predicted_change(g, A, accepted[0], lam)
         A, L, dF = accepted
         rec["dF"] = dF
         F = F + dF

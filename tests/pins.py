@@ -182,8 +182,41 @@ def check_cond_fallback(orc, seeds=range(4)):
     return True
 
 
+def check_armijo(orc, seed=9):
+    """The sufficient-decrease variant of the line search (sigma > 0):
+      * predicted_change is the first-order change of F: for a step eps E that
+        keeps every sign, F(A + eps E) - F(A) minus the prediction shrinks like
+        eps^2 (F from slogdet, independent of the oracle);
+      * an Armijo solve reaches the minimiser of the plain solve, and every step it
+        accepts decreased F by at least sigma times its (negative) prediction."""
+    rng = np.random.default_rng(seed)
+    S = random_psd(10, 6, seed)
+    lam = 0.1
+    A = orc.pista(S, lam, 0.0, max_iter=3).A
+    g = S - np.linalg.inv(A)
+    E = rng.standard_normal(A.shape)
+    E = 0.5 * (E + E.T) * (A != 0)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        At = A + eps * E
+        if np.any(np.sign(At) != np.sign(A)):
+            return False
+        errs.append(abs(f_direct(S, At, lam) - f_direct(S, A, lam) - orc.predicted_change(g, A, At, lam)))
+    if not errs[1] < 0.02 * errs[0] + 1e-13:
+        return False
+    ref = orc.pista(S, lam, 1e-7, max_iter=3000)
+    r = orc.pista(S, lam, 1e-7, max_iter=3000, sigma=0.3)
+    if r.status != orc.CONVERGED or abs(r.objective - ref.objective) > 1e-10 * abs(ref.objective):
+        return False
+    if not np.array_equal(r.A != 0, ref.A != 0):
+        return False
+    steps = [h for h in r.history if "dF" in h]
+    return all(h["pred"] < 0 and h["dF"] < 0.3 * h["pred"] for h in steps)
+
+
 def all_pins(orc):
     return {
+        "armijo": check_armijo(orc),
         "cond_fallback": check_cond_fallback(orc),
         "scalar_lemma": check_scalar_lemma(orc, trials=40),
         "n2_closed_form": check_n2_closed_form(orc, seeds=range(3)),

@@ -272,6 +272,12 @@ def test_fallback_solve_reaches_the_minimiser():
     assert pins.kkt_violation(S, r.A, lam) < 1e-6
 
 
+def test_armijo_line_search():
+    """sigma > 0: the first-order prediction against finite differences and an
+    Armijo solve reaching the plain solve's minimiser (see pins.check_armijo)."""
+    assert pins.check_armijo(oracle)
+
+
 def test_iteration_cap_status():
     S, _ = synth.chain_problem(50, 25, 0)
     r = oracle.pista(S, 0.2, 1e-12, max_iter=2)
@@ -339,6 +345,8 @@ MUTANTS = {
     "objective_change_sign": dict(objective_change=lambda S, A, At, L, Lt, lam:
                                   -opista.objective_change(S, A, At, L, Lt, lam)),
     "cond_fallback_always_one": dict(cond_fallback_step=lambda A, factor=0.9: 1.0),
+    "predicted_change_sign": dict(predicted_change=lambda g, A, At, lam: -opista.predicted_change(g, A, At, lam)),
+    "predicted_change_drops_l1": dict(predicted_change=lambda g, A, At, lam: float(np.sum(g * (At - A)))),
     "cond_fallback_unsquared": dict(cond_fallback_step=lambda A, factor=0.9:
                                     factor * np.linalg.eigvalsh(A)[0] / np.linalg.eigvalsh(A)[-1]),
 }
@@ -349,7 +357,8 @@ def test_mutant_is_caught(name):
     m = _mutant(**MUTANTS[name])
     caught = False
     for check in (pins.check_scalar_lemma, pins.check_diagonal_solution, pins.check_n2_closed_form,
-                  pins.check_kkt_invariants, pins.check_against_gista, pins.check_cond_fallback):
+                  pins.check_kkt_invariants, pins.check_against_gista, pins.check_cond_fallback,
+                  pins.check_armijo):
         try:
             ok = check(m) if check is not pins.check_scalar_lemma else check(m, trials=40)
         except Exception:
