@@ -95,6 +95,21 @@ typedef struct {
                         of the diagonal (only entries on the free set are needed, eq. d_sol),
                         in FP64 from the same Z; otherwise by the dense GEMM pair of
                         `precision`.  1: always the dense pair (the paper's dense design). */
+  int screen;      /* 1: before iterating, split every problem into the connected components
+                      of the graph {|S_ij| > lambda, i != j} (its solution is block diagonal over
+                      them, each block the solution of its own problem) and solve the blocks:
+                      those of n <= GLASSO_SMALL_MAX_N in one persistent launch (FP64), the
+                      others batched in `precision`; A and W are assembled with zeros between
+                      blocks.  Each block stops on its own measure, so the whole problem meets
+                      ||Z||_1 <= tol ||A||_1; the status is CONVERGED whenever the assembled
+                      A meets it (a block may stall a little below its own share), else the
+                      worst status of the blocks.  Results equal the unscreened solve to the
+                      tolerance, not bitwise.  0 (default): no screening. */
+  double sigma;    /* sufficient-decrease fraction of the line search: a trial point is
+                      accepted when F(At) - F(A) < sigma * (<g, At - A> + lambda (||At||_1 -
+                      ||A||_1)), the decrease that the linear model of f plus the l1 term
+                      predicts (an Armijo rule); 0 (default): strict decrease, the paper's
+                      condition t_cond_min.  0 <= sigma < 1. */
 } glasso_options;
 
 #define GLASSO_TILES_AUTO (-1)
@@ -124,6 +139,8 @@ typedef struct {
   double leaf_ms;     /* their summed launch times (HIP events around each launch) */
   double leaf_flops;  /* their algorithmic flops: per step at column k, nb = min(128, n - k),
                          nb^3/3 for the diagonal block and (n - k - nb) nb^2 for the panel */
+  int components;         /* with screen: blocks the problem split into (1 otherwise) */
+  int largest_component;  /* with screen: size of the largest block (n otherwise) */
 } glasso_info;
 
 /* Fill *opt with the defaults listed above. */

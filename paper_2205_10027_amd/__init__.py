@@ -79,6 +79,8 @@ class Result:
     leaf_launches: int = 0
     leaf_ms: float = 0.0
     leaf_flops: float = 0.0
+    components: int = 1
+    largest_component: int = 0
 
     @property
     def status_name(self) -> str:
@@ -91,7 +93,8 @@ class Solver:
     def __init__(self, precision: str | int = "fp64", max_iter: int = 500, t0: float = 1.0,
                  shrink: float = 0.5, t_floor: float = 1e-4, t_min: float = 1e-12,
                  warm_start: bool = False, tile_policy: int = TILES_AUTO, graphs: bool = False,
-                 w_mixed: int = -1, ls_width: int = 0, dense_product: bool = False):
+                 w_mixed: int = -1, ls_width: int = 0, dense_product: bool = False, screen: bool = False,
+                 sigma: float = 0.0):
         opt = GlassoOptions()
         _check(_lib.glasso_default_options(ctypes.byref(opt)), "glasso_default_options")
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -106,6 +109,8 @@ class Solver:
         opt.w_mixed = int(w_mixed)
         opt.ls_width = int(ls_width)
         opt.dense_product = int(bool(dense_product))
+        opt.screen = int(bool(screen))
+        opt.sigma = float(sigma)
         self.options = opt
         h = ctypes.c_void_p()
         _check(_lib.glasso_create(ctypes.byref(h), ctypes.byref(opt)), "glasso_create")
@@ -151,7 +156,8 @@ class Solver:
         return Result(A, W, info.objective, info.iterations, info.status, info.kkt_rel1,
                       info.kkt_fro, info.kkt_max, int(info.nnz), info.ls_trials,
                       info.fallback_steps, tuple(info.time_ms), info.aza_gemm_products,
-                      info.aza_sparse_products, info.leaf_launches, info.leaf_ms, info.leaf_flops)
+                      info.aza_sparse_products, info.leaf_launches, info.leaf_ms, info.leaf_flops,
+                      info.components, info.largest_component)
 
     def solve_batched(self, S_list, lams, tol: float, A_list=None, want_W: bool = True, stream=None):
         """Solve len(lams) problems in batched launches (glasso_solve_batched).
@@ -206,7 +212,8 @@ class Solver:
             out.append(Result(A_list[i], W_list[i] if want_W else None, inf.objective, inf.iterations,
                               inf.status, inf.kkt_rel1, inf.kkt_fro, inf.kkt_max, int(inf.nnz),
                               inf.ls_trials, inf.fallback_steps, tuple(inf.time_ms), inf.aza_gemm_products,
-                              inf.aza_sparse_products, inf.leaf_launches, inf.leaf_ms, inf.leaf_flops))
+                              inf.aza_sparse_products, inf.leaf_launches, inf.leaf_ms, inf.leaf_flops,
+                              inf.components, inf.largest_component))
         return out
 
     # ---------------------------------------------------------------- workloads

@@ -24,6 +24,8 @@ class GlassoOptions(ctypes.Structure):
         ("w_mixed", ctypes.c_int),
         ("ls_width", ctypes.c_int),
         ("dense_product", ctypes.c_int),
+        ("screen", ctypes.c_int),
+        ("sigma", ctypes.c_double),
     ]
 
 
@@ -44,6 +46,8 @@ class GlassoInfo(ctypes.Structure):
         ("leaf_launches", ctypes.c_int),
         ("leaf_ms", ctypes.c_double),
         ("leaf_flops", ctypes.c_double),
+        ("components", ctypes.c_int),
+        ("largest_component", ctypes.c_int),
     ]
 
 

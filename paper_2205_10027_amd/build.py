@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglasso.so")
 
 SOURCES = ["gemm_f64.hip", "gemm_mixed.hip", "gemm_bf16x3.hip", "gemm_bf16x6.hip", "chol.hip", "passes.hip", "persistent.hip", "sparse_product.hip",
-           "generate.hip", "glasso_api.hip"]
+           "generate.hip", "screen.hip", "glasso_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

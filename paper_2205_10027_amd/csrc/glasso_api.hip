@@ -149,6 +149,8 @@ struct glasso_handle_s {
   size_t cov_bytes = 0;
   void* gen_base = nullptr;  // workspace of glasso_generate
   size_t gen_bytes = 0;
+  void* scr_base = nullptr;  // workspace of the screening (labels, packed blocks, block table)
+  size_t scr_bytes = 0;
 };
 
 namespace {
@@ -326,6 +328,7 @@ glasso_err check_options(const glasso_options* o) {
     return GLASSO_ERR_INVALID_ARG;
   if (o->ls_width < 0 || o->ls_width > LS_WIDTH_MAX) return GLASSO_ERR_INVALID_ARG;
   if (o->dense_product < 0 || o->dense_product > 1) return GLASSO_ERR_INVALID_ARG;
+  if (o->screen < 0 || o->screen > 1 || !(o->sigma >= 0.0 && o->sigma < 1.0)) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -750,7 +753,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (e2) return e2;
     e2 = push_doubles(s, w.t, hm.t, slots);
     if (e2) return e2;
-    K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt));
+    K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt,
+                     o.sigma > 0.0 ? w.W : nullptr));
     // the trial's factor is finished (diagonal blocks placed and inverted) only if
     // it is accepted, at the next head
     if (timed) HIP_TRY(hipEventRecord(h->ev[8], s));
@@ -923,6 +927,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       fb_used[b] = 0;
       tb[b] = o.t0;
     }
+    // acceptance: a strict decrease (sigma = 0, condition t_cond_min) or sigma times
+    // the decrease the linear model predicts (the trial pass read W for it)
+    auto decrease_target = [&](int j) { return o.sigma > 0.0 ? o.sigma * hscal_t(h, j, SC_PRED) : 0.0; };
     bool first_round = true;
     for (;;) {
       int nls = 0;
@@ -981,7 +988,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
         if (!ls[b]) continue;
         int got = -1;
         for (int i = 0; i < ncand[b] && got < 0; ++i)
-          if (hm.info[b * K + i] == 0 && hscal_t(h, b * K + i, SC_DF) < 0.0) got = i;
+          if (hm.info[b * K + i] == 0 && hscal_t(h, b * K + i, SC_DF) < decrease_target(b * K + i)) got = i;
         if (got >= 0) {
           trials[b] += got + 1;
           since[b] += got + 1;
@@ -1063,6 +1070,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       in.fallback_steps = fallbacks[b];
       in.aza_gemm_products = gemm_products[b];
       in.aza_sparse_products = sparse_products[b];
+      in.components = 1;
+      in.largest_component = (int)n;
       for (int i = 1; i < 8; ++i) in.time_ms[i] = phase[i];
       in.time_ms[0] = total;
       in.leaf_launches = leaf_done ? leaf.used / 2 : 0;
@@ -1134,6 +1143,7 @@ glasso_err glasso_destroy(glasso_handle h) {
   if (h->small_base) (void)hipFree(h->small_base);
   if (h->cov_base) (void)hipFree(h->cov_base);
   if (h->gen_base) (void)hipFree(h->gen_base);
+  if (h->scr_base) (void)hipFree(h->scr_base);
   if (h->ws.base) (void)hipFree(h->ws.base);
   free_host(h->hm);
   for (auto& e : h->ev)
@@ -1164,24 +1174,16 @@ glasso_err glasso_workspace_size(int64_t n, int precision, size_t* bytes) {
   return GLASSO_OK;
 }
 
-glasso_err glasso_solve(glasso_handle h, const double* S, int64_t n, double lambda, double tol, double* A,
-                        double* W, glasso_info* info, void* stream) {
-  if (!h || !S || !A || n < 1 || !(lambda > 0.0) || !(tol > 0.0) || !isfinite(lambda) || n > (1 << 20))
-    return GLASSO_ERR_INVALID_ARG;
-  const double* Sp[1] = {S};
-  double* Ap[1] = {A};
-  double* Wp[1] = {W};
-  return run_engine(h, (hipStream_t)stream, 1, n, Sp, &lambda, tol, Ap, Wp, info);
-}
+namespace {
 
-glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const* S, const int64_t* n,
-                                const double* lambda, double tol, double* const* A, double* const* W,
-                                glasso_info* info, void* stream) {
-  if (!h || count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return GLASSO_ERR_INVALID_ARG;
-  for (int i = 0; i < count; ++i)
-    if (!S[i] || !A[i] || n[i] < 1 || n[i] > (1 << 20) || !(lambda[i] > 0.0) || !isfinite(lambda[i]))
-      return GLASSO_ERR_INVALID_ARG;
-  // problems of equal padded size run together; groups run one after another
+glasso_err small_with_handle(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                             const double* lambda, double tol, double* const* A, double* const* W, glasso_info* info,
+                             hipStream_t st);
+
+// Problems of equal padded size run together; groups run one after another.
+glasso_err solve_batched_plain(glasso_handle h, hipStream_t st, int count, const double* const* S, const int64_t* n,
+                               const double* lambda, double tol, double* const* A, double* const* W,
+                               glasso_info* info) {
   std::vector<int> done(count, 0);
   for (int i = 0; i < count; ++i) {
     if (done[i]) continue;
@@ -1200,13 +1202,251 @@ glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const*
       Wg.push_back(W ? W[j] : nullptr);
       done[j] = 1;
     }
-    glasso_err e = run_engine(h, (hipStream_t)stream, (int)idx.size(), n[i], Sg.data(), lg.data(), tol, Ag.data(),
-                              Wg.data(), ig.data());
+    glasso_err e = run_engine(h, st, (int)idx.size(), n[i], Sg.data(), lg.data(), tol, Ag.data(), Wg.data(),
+                              ig.data());
     if (e) return e;
     if (info)
       for (size_t k = 0; k < idx.size(); ++k) info[idx[k]] = ig[k];
   }
   return GLASSO_OK;
+}
+
+glasso_err grow_scr(glasso_handle h, size_t bytes) {
+  if (bytes <= h->scr_bytes) return GLASSO_OK;
+  if (h->scr_base) (void)hipFree(h->scr_base);
+  h->scr_base = nullptr;
+  h->scr_bytes = 0;
+  if (hipMalloc(&h->scr_base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return GLASSO_ERR_OOM;
+  }
+  h->scr_bytes = bytes;
+  return GLASSO_OK;
+}
+
+// Block-diagonal screening (screen.hip): every problem is split into the connected
+// components of {|S_ij| > lambda}; a problem that stays in one piece is solved in
+// place, the blocks of the others are gathered, solved (n <= GLASSO_SMALL_MAX_N in
+// one persistent launch, the rest batched) and scattered back between zeros.
+glasso_err run_screened(glasso_handle h, hipStream_t st, int count, const double* const* S, const int64_t* n,
+                        const double* lambda, double tol, double* const* A, double* const* W, glasso_info* info) {
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<int64_t> loff(count + 1, 0);
+  for (int p = 0; p < count; ++p) loff[p + 1] = loff[p] + n[p];
+  const size_t lab_bytes = align_up((size_t)(loff[count] + 64) * sizeof(int));
+  glasso_err e = grow_scr(h, lab_bytes);
+  if (e) return e;
+  int* lab = static_cast<int*>(h->scr_base);
+  int* err = lab + loff[count];
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), st));
+  for (int p = 0; p < count; ++p) K_TRY(screen_components(st, S[p], n[p], n[p], lambda[p], lab + loff[p], err));
+  std::vector<int> hlab(loff[count] + 1);
+  HIP_TRY(hipMemcpyAsync(hlab.data(), lab, (size_t)(loff[count] + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hlab[loff[count]]) return GLASSO_ERR_INTERNAL;
+
+  // the blocks of every problem, variables ascending (a block is labelled by its
+  // smallest variable)
+  struct Blk {
+    int p;
+    std::vector<int> idx;
+  };
+  std::vector<Blk> blocks;
+  std::vector<int> direct, ncomp(count, 0), largest(count, 0);
+  for (int p = 0; p < count; ++p) {
+    const int* lp = hlab.data() + loff[p];
+    std::vector<int> id_of(n[p], -1);
+    const size_t first = blocks.size();
+    for (int64_t i = 0; i < n[p]; ++i) {
+      const int r = lp[i];
+      if (id_of[r] < 0) {
+        id_of[r] = (int)blocks.size();
+        blocks.push_back(Blk{p, {}});
+      }
+      blocks[id_of[r]].idx.push_back((int)i);
+    }
+    ncomp[p] = (int)(blocks.size() - first);
+    for (size_t b = first; b < blocks.size(); ++b) largest[p] = std::max(largest[p], (int)blocks[b].idx.size());
+    if (ncomp[p] == 1) {  // one piece: solved in place
+      blocks.resize(first);
+      direct.push_back(p);
+    }
+  }
+
+  // packing of the gathered blocks: S_k, A_k, W_k (k^2 each), the variables, the table
+  const int nb = (int)blocks.size();
+  std::vector<ScreenBlock> tab(nb);
+  int64_t total = 0, nidx = 0;
+  for (int b = 0; b < nb; ++b) {
+    tab[b].k = (int)blocks[b].idx.size();
+    tab[b].off = total;
+    total += (int64_t)tab[b].k * tab[b].k;
+    nidx += tab[b].k;
+  }
+  const bool want_w = W != nullptr;
+  if (nb) {
+    const size_t pack = align_up((size_t)total * sizeof(double));
+    const size_t bytes = lab_bytes + 3 * pack + align_up((size_t)nidx * sizeof(int)) +
+                         align_up((size_t)nb * sizeof(ScreenBlock)) + align_up((size_t)nb * sizeof(double));
+    e = grow_scr(h, bytes);
+    if (e) return e;
+    char* base = static_cast<char*>(h->scr_base) + lab_bytes;
+    double* Sk = reinterpret_cast<double*>(base);
+    double* Ak = reinterpret_cast<double*>(base + pack);
+    double* Wk = reinterpret_cast<double*>(base + 2 * pack);
+    int* didx = reinterpret_cast<int*>(base + 3 * pack);
+    ScreenBlock* dtab = reinterpret_cast<ScreenBlock*>(base + 3 * pack + align_up((size_t)nidx * sizeof(int)));
+    double* dsum = reinterpret_cast<double*>(reinterpret_cast<char*>(dtab) + align_up((size_t)nb * sizeof(ScreenBlock)));
+    std::vector<int> hidx(nidx);
+    int64_t io = 0;
+    for (int b = 0; b < nb; ++b) {
+      const int p = blocks[b].p;
+      ScreenBlock& t = tab[b];
+      t.S = S[p];
+      t.A = A[p];
+      t.W = want_w ? W[p] : nullptr;
+      t.ld = n[p];
+      t.idx = didx + io;
+      t.Sk = Sk + t.off;
+      t.Ak = Ak + t.off;
+      t.Wk = Wk + t.off;
+      std::copy(blocks[b].idx.begin(), blocks[b].idx.end(), hidx.begin() + io);
+      io += t.k;
+    }
+    HIP_TRY(hipMemcpyAsync(didx, hidx.data(), (size_t)nidx * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dtab, tab.data(), (size_t)nb * sizeof(ScreenBlock), hipMemcpyHostToDevice, st));
+    K_TRY(gather_blocks(st, dtab, nb, total, 0));
+    if (h->opt.warm_start) K_TRY(gather_blocks(st, dtab, nb, total, 1));
+    HIP_TRY(hipStreamSynchronize(st));  // the host staging arrays are released below
+
+    // small blocks in one persistent launch, the others batched
+    std::vector<const double*> sS, bS;
+    std::vector<int64_t> sn, bn;
+    std::vector<double> sl, bl;
+    std::vector<double*> sA, sW, bA, bW;
+    std::vector<int> sid, bid;
+    for (int b = 0; b < nb; ++b) {
+      const bool small = tab[b].k <= GLASSO_SMALL_MAX_N;
+      (small ? sS : bS).push_back(tab[b].Sk);
+      (small ? sn : bn).push_back(tab[b].k);
+      (small ? sl : bl).push_back(lambda[blocks[b].p]);
+      (small ? sA : bA).push_back(tab[b].Ak);
+      (small ? sW : bW).push_back(want_w ? tab[b].Wk : nullptr);
+      (small ? sid : bid).push_back(b);
+    }
+    std::vector<glasso_info> binfo(nb);
+    if (!sS.empty()) {
+      std::vector<glasso_info> si(sS.size());
+      e = small_with_handle(h, (int)sS.size(), sS.data(), sn.data(), sl.data(), tol, sA.data(), want_w ? sW.data() : nullptr,
+                            si.data(), st);
+      if (e) return e;
+      for (size_t q = 0; q < si.size(); ++q) binfo[sid[q]] = si[q];
+    }
+    if (!bS.empty()) {
+      std::vector<glasso_info> bi(bS.size());
+      e = solve_batched_plain(h, st, (int)bS.size(), bS.data(), bn.data(), bl.data(), tol, bA.data(),
+                              want_w ? bW.data() : nullptr, bi.data());
+      if (e) return e;
+      for (size_t q = 0; q < bi.size(); ++q) binfo[bid[q]] = bi[q];
+    }
+    // assemble: zeros between the blocks
+    for (int p = 0; p < count; ++p) {
+      if (ncomp[p] == 1) continue;
+      K_TRY(zero_fill(st, A[p], n[p] * n[p]));
+      if (want_w && W[p]) K_TRY(zero_fill(st, W[p], n[p] * n[p]));
+    }
+    K_TRY(scatter_blocks(st, dtab, nb, total, want_w ? 1 : 0));
+    K_TRY(block_abs_sums(st, dtab, nb, dsum));
+    std::vector<double> hsum(nb);
+    HIP_TRY(hipMemcpyAsync(hsum.data(), dsum, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (info) {
+      std::vector<double> z1(count, 0.0), a1(count, 0.0), fro2(count, 0.0);
+      for (int p = 0; p < count; ++p) {
+        if (ncomp[p] == 1) continue;
+        memset(&info[p], 0, sizeof(glasso_info));
+        info[p].status = GLASSO_CONVERGED;
+      }
+      for (int b = 0; b < nb; ++b) {
+        glasso_info& in = info[blocks[b].p];
+        const glasso_info& bi = binfo[b];
+        in.objective += bi.objective;
+        z1[blocks[b].p] += bi.kkt_rel1 * hsum[b];
+        a1[blocks[b].p] += hsum[b];
+        fro2[blocks[b].p] += bi.kkt_fro * bi.kkt_fro;
+        in.kkt_max = std::max(in.kkt_max, bi.kkt_max);
+        in.nnz += bi.nnz;
+        in.iterations = std::max(in.iterations, bi.iterations);
+        in.ls_trials += bi.ls_trials;
+        in.status = std::max(in.status, bi.status);
+        in.fallback_steps += bi.fallback_steps;
+        in.aza_gemm_products += bi.aza_gemm_products;
+        in.aza_sparse_products += bi.aza_sparse_products;
+        for (int i = 1; i < 8; ++i) in.time_ms[i] += bi.time_ms[i];
+      }
+      for (int p = 0; p < count; ++p) {
+        if (ncomp[p] == 1) continue;
+        info[p].kkt_rel1 = a1[p] > 0.0 ? z1[p] / a1[p] : 0.0;
+        info[p].kkt_fro = sqrt(fro2[p]);
+        // the stopping rule is the whole problem's: met when the assembled A meets it,
+        // even if a block stalled (status LS_FAILED) below its own share
+        if (info[p].kkt_rel1 <= tol) info[p].status = GLASSO_CONVERGED;
+      }
+    }
+  }
+  if (!direct.empty()) {
+    std::vector<const double*> dS;
+    std::vector<int64_t> dn;
+    std::vector<double> dl;
+    std::vector<double*> dA, dW;
+    for (int p : direct) {
+      dS.push_back(S[p]);
+      dn.push_back(n[p]);
+      dl.push_back(lambda[p]);
+      dA.push_back(A[p]);
+      dW.push_back(want_w ? W[p] : nullptr);
+    }
+    std::vector<glasso_info> di(direct.size());
+    e = solve_batched_plain(h, st, (int)direct.size(), dS.data(), dn.data(), dl.data(), tol, dA.data(),
+                            want_w ? dW.data() : nullptr, di.data());
+    if (e) return e;
+    if (info)
+      for (size_t q = 0; q < direct.size(); ++q) info[direct[q]] = di[q];
+  }
+  if (info) {
+    const double total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    for (int p = 0; p < count; ++p) {
+      info[p].components = ncomp[p];
+      info[p].largest_component = largest[p];
+      info[p].time_ms[0] = total_ms;
+    }
+  }
+  return GLASSO_OK;
+}
+
+}  // namespace
+
+glasso_err glasso_solve(glasso_handle h, const double* S, int64_t n, double lambda, double tol, double* A,
+                        double* W, glasso_info* info, void* stream) {
+  if (!h || !S || !A || n < 1 || !(lambda > 0.0) || !(tol > 0.0) || !isfinite(lambda) || n > (1 << 20))
+    return GLASSO_ERR_INVALID_ARG;
+  const double* Sp[1] = {S};
+  double* Ap[1] = {A};
+  double* Wp[1] = {W};
+  if (h->opt.screen) return run_screened(h, (hipStream_t)stream, 1, Sp, &n, &lambda, tol, Ap, Wp, info);
+  return run_engine(h, (hipStream_t)stream, 1, n, Sp, &lambda, tol, Ap, Wp, info);
+}
+
+glasso_err glasso_solve_batched(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                                const double* lambda, double tol, double* const* A, double* const* W,
+                                glasso_info* info, void* stream) {
+  if (!h || count < 1 || !S || !n || !lambda || !A || !(tol > 0.0)) return GLASSO_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!S[i] || !A[i] || n[i] < 1 || n[i] > (1 << 20) || !(lambda[i] > 0.0) || !isfinite(lambda[i]))
+      return GLASSO_ERR_INVALID_ARG;
+  if (h->opt.screen) return run_screened(h, (hipStream_t)stream, count, S, n, lambda, tol, A, W, info);
+  return solve_batched_plain(h, (hipStream_t)stream, count, S, n, lambda, tol, A, W, info);
 }
 
 glasso_err glasso_autotune(glasso_handle h, int64_t n, int count, int* policy, void* stream) {
@@ -1278,6 +1518,7 @@ glasso_err run_small(const glasso_options& o, int count, const double* const* S,
   p.shrink = o.shrink;
   p.t_floor = o.t_floor;
   p.t_min = o.t_min;
+  p.sigma = o.sigma;
   p.max_iter = o.max_iter;
   p.warm_start = o.warm_start;
   HIP_TRY(hipMemcpyAsync(dpr, pr, (size_t)count * sizeof(SmallProblem), hipMemcpyHostToDevice, st));
@@ -1303,6 +1544,8 @@ glasso_err run_small(const glasso_options& o, int count, const double* const* S,
       in.status = (glasso_status)out[i].status;
       in.fallback_steps = out[i].fallback_steps;
       in.time_ms[0] = total;
+      in.components = 1;
+      in.largest_component = (int)n[i];
     }
   }
   return err;
@@ -1310,10 +1553,12 @@ glasso_err run_small(const glasso_options& o, int count, const double* const* S,
 
 }  // namespace
 
-glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
-                              const double* lambda, double tol, double* const* A, double* const* W,
-                              glasso_info* info, void* stream) {
-  if (!h || !small_args_ok(count, S, n, lambda, tol, A)) return GLASSO_ERR_INVALID_ARG;
+namespace {
+
+// The persistent small-problem launch on the handle's own workspace (grown as needed).
+glasso_err small_with_handle(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                             const double* lambda, double tol, double* const* A, double* const* W, glasso_info* info,
+                             hipStream_t st) {
   const int grid = std::min(count, 512);
   const SmallLayout lay(grid, count);
   if (lay.total > h->small_bytes) {
@@ -1328,8 +1573,17 @@ glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S
   }
   std::vector<SmallProblem> pr(count);
   std::vector<SmallOut> out(count);
-  return run_small(h->opt, count, S, n, lambda, tol, A, W, info, (hipStream_t)stream,
-                   static_cast<char*>(h->small_base), grid, pr.data(), out.data());
+  return run_small(h->opt, count, S, n, lambda, tol, A, W, info, st, static_cast<char*>(h->small_base), grid,
+                   pr.data(), out.data());
+}
+
+}  // namespace
+
+glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
+                              const double* lambda, double tol, double* const* A, double* const* W,
+                              glasso_info* info, void* stream) {
+  if (!h || !small_args_ok(count, S, n, lambda, tol, A)) return GLASSO_ERR_INVALID_ARG;
+  return small_with_handle(h, count, S, n, lambda, tol, A, W, info, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------ allocation-free small solves

@@ -190,9 +190,12 @@ int pass_grad(hipStream_t stream, const double* S, const double* W, const double
               void* Zs = nullptr, int64_t sZs = 0);
 // info_reset[b] is set to 0 for the problems the pass handles and to -1 for the
 // skipped ones, so that the Cholesky that follows skips them too.
+// W (may be null): with it the pass also sums W (.) (At - A) for the predicted
+// change of the sufficient-decrease test (finish_trial writes SC_PRED)
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S,
                const int8_t* GM, int64_t n, int64_t np, double lam, double t, double* At,
-               double* Lt, double* part, int* info_reset, const PassBatch& pb = PassBatch());
+               double* Lt, double* part, int* info_reset, const PassBatch& pb = PassBatch(),
+               const double* W = nullptr);
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL,
                  const double* dLt, const int* info, int64_t n, double lam, double* scal,
                  const PassBatch& pb = PassBatch());
@@ -219,6 +222,32 @@ int copy_rect(hipStream_t stream, const double* src, int64_t lds, double* dst, i
 // *out = max_{j < i < n} |S_ij| of the padded S; part: 256 doubles of scratch
 int offdiag_absmax(hipStream_t stream, const double* S, int64_t n, int64_t np, double* part, double* out);
 
+// ---- block-diagonal screening (screen.hip)
+// One block (connected component of {|S_ij| > lambda}) of a problem: its k
+// variables idx[0..k) (device, ascending) of the full matrices S, A, W (ld), and
+// its packed k x k copies Sk, Ak, Wk; off = its first element in the packing.
+struct ScreenBlock {
+  const double* S;
+  double* A;
+  double* W;
+  int64_t ld;
+  const int* idx;
+  int k;
+  int64_t off;
+  double *Sk, *Ak, *Wk;
+};
+// parent[i] = the smallest index of i's component (n x n S, ld lds); *err |= 1 if a
+// union did not settle (never expected)
+int screen_components(hipStream_t stream, const double* S, int64_t n, int64_t lds, double lam, int* parent,
+                      int* err);
+// which = 0: Sk <- S on the block; 1: Ak <- A (a warm start)
+int gather_blocks(hipStream_t stream, const ScreenBlock* blk, int count, int64_t total, int which);
+// A (and W) on the block <- Ak (Wk)
+int scatter_blocks(hipStream_t stream, const ScreenBlock* blk, int count, int64_t total, int with_w);
+// out[b] = sum |Ak| of block b
+int block_abs_sums(hipStream_t stream, const ScreenBlock* blk, int count, double* out);
+int zero_fill(hipStream_t stream, double* X, int64_t count);
+
 // ---- persistent small-problem solver (n <= SMALL_MAX_N, one workgroup per problem)
 constexpr int SMALL_MAX_N = 64;
 constexpr int GLASSO_CONVERGED_DEV = 0, GLASSO_MAX_ITER_DEV = 1, GLASSO_LS_FAILED_DEV = 2;  // glasso_status
@@ -243,6 +272,7 @@ struct SmallParams {
   int8_t* gm;  // per workgroup: 64 x 64
   int* next;   // work queue: the next problem index to take (set to the grid size by solve_small)
   double tol, t0, shrink, t_floor, t_min;
+  double sigma;  // sufficient-decrease fraction (0: strict decrease)
   int max_iter, warm_start;
 };
 constexpr int64_t SMALL_WS_DOUBLES = 6 * 64 * 64;
@@ -276,11 +306,12 @@ enum ScalarSlot {
   SC_POWER_A,
   SC_POWER_W,
   SC_DENSE_PRODUCT,  // 1: the last product used the dense GEMM pair, 0: the sparse product
+  SC_PRED,           // predicted change <g, At - A> + lam (||At||_1 - ||A||_1) (with W given)
   SC_COUNT = 24
 };
 
 constexpr int GRAD_PARTS = 6;   // per-workgroup partials of pass_grad
-constexpr int TRIAL_PARTS = 3;  // per-workgroup partials of pass_trial
+constexpr int TRIAL_PARTS = 4;  // per-workgroup partials of pass_trial
 
 inline int64_t pass_tiles(int64_t np) {
   const int64_t T = np / 64;

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
                                                          const int8_t* __restrict__ GM, int64_t n, int64_t np,
                                                          double lam, double t, double* __restrict__ At,
                                                          double* __restrict__ Lt, double* part, int* info_reset,
-                                                         int T, PassBatch pb) {
+                                                         int T, PassBatch pb, const double* __restrict__ W) {
   __shared__ double tt[64][65];
   __shared__ double di[64], dj[64];
   __shared__ double sh[4];
@@ -181,6 +181,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
   P += prob * pb.sM;
   S += prob * pb.sS;
   GM += prob * pb.sM;
+  if (W) W += prob * pb.sM;
   At += pbi * pb.sM;
   Lt += pbi * pb.sM;
   part += (int64_t)pbi * gridDim.x * TRIAL_PARTS;
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
     dj[tid - 64] = A[(j0 + tid - 64) * (np + 1)];
   __syncthreads();
 
-  double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0;
+  double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0, s_w = 0.0;
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int r = rw + 4 * q;
@@ -216,6 +217,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
           s_tr += wgt * (s * (at - a));
           s_l1 += wgt * (fabs(at) - fabs(a));
           s_nnz += (at != 0.0) ? wgt : 0.0;
+          if (W) s_w += wgt * (W[off] * (at - a));
         }
       } else {
         at = (i == j) ? 1.0 : 0.0;
@@ -237,11 +239,13 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
   const double b0 = block_sum(s_tr, sh);
   const double b1 = block_sum(s_l1, sh);
   const double b2 = block_sum(s_nnz, sh);
+  const double b3 = block_sum(s_w, sh);
   if (tid == 0) {
     double* pp = part + (int64_t)blockIdx.x * TRIAL_PARTS;
     pp[0] = b0;
     pp[1] = b1;
     pp[2] = b2;
+    pp[3] = b3;
   }
 }
 
@@ -259,17 +263,19 @@ __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, i
   dLt += pbi * pb.sV;
   scal += (int64_t)pbi * SC_COUNT;
   const int inf = info[pbi];
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, tl = 0.0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, tl = 0.0;
   for (int b = tid; b < nparts; b += 256) {
     t0 += part[(int64_t)b * TRIAL_PARTS + 0];
     t1 += part[(int64_t)b * TRIAL_PARTS + 1];
     t2 += part[(int64_t)b * TRIAL_PARTS + 2];
+    t3 += part[(int64_t)b * TRIAL_PARTS + 3];
   }
   if (inf == 0)
     for (int64_t i = tid; i < n; i += 256) tl += log(dL[i] / dLt[i]);
   const double dtr = block_sum(t0, sh);
   const double dl1 = block_sum(t1, sh);
   const double nnz = block_sum(t2, sh);
+  const double dw = block_sum(t3, sh);
   const double dlog = 2.0 * block_sum(tl, sh);
   if (tid == 0) {
     scal[SC_DTR] = dtr;
@@ -278,6 +284,8 @@ __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, i
     scal[SC_DF] = dlog + dtr + lam * dl1;
     scal[SC_TRIAL_INFO] = (double)inf;
     scal[SC_NNZ_AT] = nnz;
+    // <g, At - A> = sum S (.) (At - A) - sum W (.) (At - A), g = S - W
+    scal[SC_PRED] = (dtr - dw) + lam * dl1;
   }
 }
 
@@ -633,11 +641,11 @@ int pass_grad(hipStream_t stream, const double* S, const double* W, const double
 
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S, const int8_t* GM, int64_t n,
                int64_t np, double lam, double t, double* At, double* Lt, double* part, int* info_reset,
-               const PassBatch& pb) {
+               const PassBatch& pb, const double* W) {
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
   hipLaunchKernelGGL(pass_trial_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, A, P, S, GM, n, np, lam, t, At,
-                     Lt, part, info_reset, T, pb);
+                     Lt, part, info_reset, T, pb, W);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
           ++o.fallback_steps;
         }
         if (t < p.t_min) break;
-        double s_tr = 0.0, s_l1 = 0.0;
+        double s_tr = 0.0, s_l1 = 0.0, s_w = 0.0;
         constexpr int CHT = 4;
 #pragma unroll 1
         for (int k0 = 0; k0 < SNN / 256; k0 += CHT) {
@@ -281,6 +281,7 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
                   const double wgt = (i == j) ? 1.0 : 2.0;
                   s_tr += wgt * (S[e] * (at - av));
                   s_l1 += wgt * (fabs(at) - fabs(av));
+                  if (p.sigma > 0.0) s_w += wgt * (W[e] * (at - av));
                 }
               } else {
                 at = (i == j) ? 1.0 : 0.0;
@@ -299,12 +300,14 @@ __global__ __launch_bounds__(256) void pista_small_kernel(SmallParams p) {
         }
         const double dtr = block_sum(s_tr, sh);
         const double dl1 = block_sum(s_l1, sh);
+        // sufficient decrease: sigma times <g, At - A> + lam (||At||_1 - ||A||_1), g = S - W
+        const double target = (p.sigma > 0.0) ? p.sigma * ((dtr - block_sum(s_w, sh)) + lam * dl1) : 0.0;
         ++o.ls_trials;
         const int fail = lds_potrf<SN>(a, tid);
         bool ok = false;
         if (fail < 0) {
           const double dlog = 2.0 * block_sum(tid < n ? log(dl[tid] / a[tid][tid]) : 0.0, sh);
-          ok = (dlog + dtr + lam * dl1) < 0.0;
+          ok = (dlog + dtr + lam * dl1) < target;
         }
         __syncthreads();
         if (ok) {

@@ -98,14 +98,16 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options),
          offsetof(glasso_options, warm_start),
          offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
          offsetof(glasso_options, ls_width), offsetof(glasso_options, dense_product),
          sizeof(glasso_info), offsetof(glasso_info, nnz), offsetof(glasso_info, status),
          offsetof(glasso_info, time_ms), offsetof(glasso_info, aza_gemm_products),
          offsetof(glasso_info, aza_sparse_products), offsetof(glasso_info, leaf_launches),
-         offsetof(glasso_info, leaf_ms), offsetof(glasso_info, leaf_flops));
+         offsetof(glasso_info, leaf_ms), offsetof(glasso_info, leaf_flops), offsetof(glasso_options, screen),
+         offsetof(glasso_options, sigma), offsetof(glasso_info, components),
+         offsetof(glasso_info, largest_component));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -119,5 +121,7 @@ int main(void) {
             g.GlassoOptions.dense_product.offset, ctypes.sizeof(g.GlassoInfo),
             g.GlassoInfo.nnz.offset, g.GlassoInfo.status.offset, g.GlassoInfo.time_ms.offset,
             g.GlassoInfo.aza_gemm_products.offset, g.GlassoInfo.aza_sparse_products.offset,
-            g.GlassoInfo.leaf_launches.offset, g.GlassoInfo.leaf_ms.offset, g.GlassoInfo.leaf_flops.offset]
+            g.GlassoInfo.leaf_launches.offset, g.GlassoInfo.leaf_ms.offset, g.GlassoInfo.leaf_flops.offset,
+            g.GlassoOptions.screen.offset, g.GlassoOptions.sigma.offset, g.GlassoInfo.components.offset,
+            g.GlassoInfo.largest_component.offset]
     assert [int(x) for x in out] == want

@@ -161,3 +161,41 @@ def test_deterministic(g):
     a = to_host(s.solve(to_dev(S), lam, 1e-7).A)
     b = to_host(s.solve(to_dev(S), lam, 1e-7).A)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,seed", [(130, 1), (300, 2)])
+def test_armijo_line_search(g, n, seed):
+    """sigma = 0.3: a trial point is accepted only when F falls by 0.3 times the
+    decrease the linear model predicts (the trial pass sums W (.) (At - A) for it).
+    The blocked engine, its batch and the persistent launch follow the oracle's
+    Armijo search step for step, and reach the minimiser of the plain solve."""
+    S, _ = synth.random_sparse_problem(n, n // 2, seed)
+    lam, tol = 0.3 * synth.lambda_max(S), 1e-8
+    ref = oracle.pista(S, lam, tol, sigma=0.3, max_iter=3000)
+    plain = oracle.pista(S, lam, tol, max_iter=3000)
+    assert ref.status == plain.status == oracle.CONVERGED
+    runs = [g.Solver(sigma=0.3).solve(to_dev(S), lam, tol),
+            g.Solver(sigma=0.3).solve_batched(to_dev(S), [lam, 0.9 * lam], tol)[0]]
+    if n <= g.SMALL_MAX_N:
+        runs.append(g.Solver(sigma=0.3).solve_small([to_dev(S)], [lam], tol)[0])
+    for r in runs:
+        assert r.status == g.CONVERGED
+        assert abs(r.iterations - ref.iterations) <= 1 and abs(r.ls_trials - ref.ls_trials) <= 2
+        A = to_host(r.A)
+        assert oracle.check_solution(S, A, lam)["kkt_rel1"] <= tol * 1.0001
+        assert abs(r.objective - plain.objective) <= 1e-8 * max(1.0, abs(plain.objective))
+        assert support_mismatch(A, plain.A, oracle.check_solution(S, plain.A, lam)["g"], lam) == 0
+
+
+def test_armijo_small_problems(g):
+    """The persistent launch with sigma = 0.3 against the oracle's Armijo solves."""
+    probs = []
+    for n, seed in [(20, 3), (48, 4), (64, 5)]:
+        S, _ = synth.random_sparse_problem(n, n // 2, seed)
+        probs.append((S, 0.25 * synth.lambda_max(S)))
+    res = g.Solver(sigma=0.3).solve_small([to_dev(S) for S, _ in probs], [lam for _, lam in probs], 1e-8)
+    for (S, lam), r in zip(probs, res):
+        ref = oracle.pista(S, lam, 1e-8, sigma=0.3, max_iter=3000)
+        assert r.status == ref.status == g.CONVERGED
+        assert abs(r.iterations - ref.iterations) <= 1
+        assert abs(r.objective - ref.objective) <= 1e-8 * max(1.0, abs(ref.objective))
