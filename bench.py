@@ -269,7 +269,7 @@ def bench_path(g, torch, dev):
     g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000)  # warmup (and tile tuning)
     g.lambda_path(St, lams, 1e-5, mode="independent", max_iter=5000, precision="bf16x3")
 
-    def run(name, mode, graphs, prec, tol):
+    def run(name, mode, graphs, prec, tol, screen=False):
         torch.cuda.synchronize()
         t = time.perf_counter()
         if mode == "one_by_one":
@@ -278,7 +278,8 @@ def bench_path(g, torch, dev):
             torch.cuda.synchronize()
             s1.close()
         else:
-            res = g.lambda_path(St, lams, tol, mode=mode, waves=4, max_iter=5000, graphs=graphs, precision=prec)
+            res = g.lambda_path(St, lams, tol, mode=mode, waves=4, max_iter=5000, graphs=graphs, precision=prec,
+                                screen=screen)
             torch.cuda.synchronize()
         dt = time.perf_counter() - t
         if any(r.status != g.CONVERGED for r in res):
@@ -301,6 +302,10 @@ def bench_path(g, torch, dev):
                                    ("waves", "waves", False), ("waves_graphs", "waves", True),
                                    ("sequential", "sequential", False), ("one_by_one", "one_by_one", False)):
             modes[name] = run(name, mode, graphs, "fp64", tol)
+        # with block-diagonal screening: the large-lambda end falls apart into small blocks
+        for name, mode, graphs in (("independent_screened", "independent", False),
+                                   ("waves_graphs_screened", "waves", True)):
+            modes[name] = run(name, mode, graphs, "fp64", tol, screen=True)
         mixed = {name: run(name, mode, graphs, "bf16x3", tol)
                  for name, mode, graphs in (("independent", "independent", False), ("waves_graphs", "waves", True))}
         for rec in mixed.values():
@@ -431,7 +436,7 @@ def bench_small(g, torch, dev, count=1024):
             "iterations": sum(r.iterations for r in res)}
 
 
-def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3"):
+def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3", screen=False):
     """Serving: a Poisson stream of independent requests, n log-uniform in [64, 4096];
     request i draws its random sparse precision and m = n/2 samples on the device
     (glasso_generate, from its own seed) and arrives with them resident in HBM;
@@ -456,9 +461,9 @@ def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3"):
         f"({sample_gib:.1f} GiB of samples)")
     slots = 4
     budget = 64 * 2**30
-    eng = GpuEngine(slots=slots, precision=precision, tol=1e-5, keep=False)
+    eng = GpuEngine(slots=slots, precision=precision, tol=1e-5, keep=False, screen=screen)
     fp = lambda n: gpu_buffers(n, n // 2, resident=True)  # noqa: E731
-    wsf = lambda n: gpu_workspace(n, precision, n // 2)  # noqa: E731
+    wsf = lambda n: gpu_workspace(n, precision, n // 2, screen=screen)  # noqa: E731
 
     def requests(rate, subset=None):
         arr = [a / rate for (a, _, _) in base] if rate else [0.0] * count
@@ -471,15 +476,16 @@ def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3"):
     st = srv.run(requests(None), realtime=False)
     st = srv.run(requests(None), realtime=False)
     capacity = st.solves_per_s
-    log(f"[bench] serving closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
+    tag = " (screened)" if screen else ""
+    log(f"[bench] serving{tag} closed loop: {capacity:.2f} solves/s, p50 {st.p50_ms:.1f} ms")
     one = min(count, 500)
     serial = Server(eng, slots=1, hbm_budget=budget, footprint=fp, workspace=wsf).run(requests(None, one),
                                                                                      realtime=False)
-    log(f"[bench] serving one slot ({one} requests): {serial.solves_per_s:.2f} solves/s")
+    log(f"[bench] serving{tag} one slot ({one} requests): {serial.solves_per_s:.2f} solves/s")
     out = {"workload": f"{count} Poisson requests, n log-uniform [64, 4096], random sparse precision and m=n/2 "
                        f"samples drawn on the device per request (resident in HBM on arrival; S formed by the "
                        f"slot), lambda=0.3 lambda_max, {precision} form, tol 1e-5, {slots} slots, HBM budget "
-                       f"{budget >> 30} GiB",
+                       f"{budget >> 30} GiB" + (", block-diagonal screening" if screen else ""),
            "requests": count, "closed_loop_solves_per_s": capacity,
            "one_slot_solves_per_s": serial.solves_per_s, "speedup_vs_one_slot": capacity / serial.solves_per_s,
            "rates": {}}
@@ -491,7 +497,8 @@ def bench_serve(g, torch, dev, count, seed=0, precision="bf16x3"):
         out["rates"][f"{frac:.1f}x"] = {"arrival_rate_per_s": rate, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
                                         "solves_per_s": st.solves_per_s, "mean_in_flight": st.mean_active,
                                         "peak_charged_gib": st.peak_bytes / 2**30, "not_converged": errs}
-        log(f"[bench] serving {frac:.1f}x: p50 {st.p50_ms:.1f} ms p99 {st.p99_ms:.1f} ms, {st.solves_per_s:.2f}/s")
+        log(f"[bench] serving{tag} {frac:.1f}x: p50 {st.p50_ms:.1f} ms p99 {st.p99_ms:.1f} ms, "
+            f"{st.solves_per_s:.2f}/s")
     eng.close()
     r08 = out["rates"]["0.8x"]
     out.update({"p50_ms": r08["p50_ms"], "p99_ms": r08["p99_ms"], "solves_per_s": r08["solves_per_s"]})
@@ -667,6 +674,7 @@ def main():
         line["batched"] = bench_path(g, torch, dev)
     if not args.no_serve:
         line["serving"] = bench_serve(g, torch, dev, args.serve_requests)
+        line["serving"]["screened"] = bench_serve(g, torch, dev, args.serve_requests, screen=True)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         line["cpu_baseline"] = cpu_baseline(S, lams, [r.iterations for r in results[-len(lams):]])

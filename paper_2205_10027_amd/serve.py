@@ -88,9 +88,12 @@ def gpu_buffers(n: int, m: int | None = None, resident: bool = False) -> int:
     return b
 
 
-def gpu_workspace(n: int, precision: str = "bf16x3", m: int | None = None) -> int:
+def gpu_workspace(n: int, precision: str = "bf16x3", m: int | None = None, screen: bool = False) -> int:
     """Device bytes a slot's handle keeps after serving a request of size n: the
-    solver workspace and, with m samples, the covariance workspace."""
+    solver workspace and, with m samples, the covariance workspace; with screening
+    also the packed blocks (at most 3 n^2 doubles and the labels) and the persistent
+    small-problem launch's workspace (512 workgroup slots and the descriptors of up
+    to n blocks)."""
     import paper_2205_10027_amd as g
 
     b = g.workspace_bytes(n, precision)
@@ -98,6 +101,9 @@ def gpu_workspace(n: int, precision: str = "bf16x3", m: int | None = None) -> in
         npad = -(-n // 128) * 128
         mpad = -(-m // 16) * 16
         b += (mpad * npad + npad * npad + npad) * 8
+    if screen:
+        b += 3 * n * n * 8 + 64 * n + (1 << 16)
+        b += 512 * (6 * 64 * 64 * 8 + 64 * 64) + 128 * n + 512
     return b
 
 
@@ -113,7 +119,7 @@ class GpuEngine:
     client that reads its answer and lets it go)."""
 
     def __init__(self, slots: int, precision: str = "bf16x3", tol: float = 1e-5, device: int = 0,
-                 keep: bool = True):
+                 keep: bool = True, screen: bool = False):
         import torch
 
         import paper_2205_10027_amd as g
@@ -122,9 +128,10 @@ class GpuEngine:
         self.tol = tol
         self.keep = keep
         self.precision = precision
+        self.screen = screen
         self.g = g
         self.device = torch.device("cuda", device)
-        self.solvers = [g.Solver(precision=precision) for _ in range(slots)]
+        self.solvers = [g.Solver(precision=precision, screen=screen) for _ in range(slots)]
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
 
     def __call__(self, slot: int, req: Request):
@@ -150,7 +157,7 @@ class GpuEngine:
     def release(self, slot: int):
         """Free what an idle slot's handle keeps (its workspaces): a new handle."""
         self.solvers[slot].close()
-        self.solvers[slot] = self.g.Solver(precision=self.precision)
+        self.solvers[slot] = self.g.Solver(precision=self.precision, screen=self.screen)
 
     def close(self):
         for s in self.solvers:
