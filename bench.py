@@ -224,6 +224,8 @@ def bench_config1(g, torch, dev, reps=3):
 
 def time_chain(g, St, lams, tol, precision, steps, warmup, torch, dense_product=False):
     solver = g.Solver(precision=precision, dense_product=dense_product)
+    # the FP64 GEMM tile policy the autotuner picks for this size (solves reuse it)
+    time_chain.tile_threshold = solver.autotune(St.shape[0])
     As = [torch.empty_like(St) for _ in lams]  # the last step's solution per lambda
 
     def step():
@@ -603,7 +605,10 @@ def main():
         aza["gemm_peak_tflops"] = PEAK_TFLOPS[args.precision]
     config = {"workload": f"chain n={n} m={m} seed={seed} lambdas={list(lams)} tol={tol}",
               "precision": args.precision,
-              "aza_form": "dense GEMM pair" if args.dense_product else "sparse where the rows are short, else GEMM pair",
+              "aza_form": ("dense GEMM pair" if args.dense_product else
+                           "sampled sparse product where the rows are short (FP64 arithmetic; Z from its two-part "
+                           "bf16 split in the BF16x3 form), else the GEMM pair"),
+              "tile_threshold": time_chain.tile_threshold,
               "iterations": [r.iterations for r in results[:len(lams)]],
               "ls_trials": [r.ls_trials for r in results[:len(lams)]],
               "solves_per_s": solves / elapsed}

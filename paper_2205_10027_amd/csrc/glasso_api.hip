@@ -507,9 +507,14 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int>, int> g_tune;
 
 // Times factor + inverse (+ the FP64 A Z A) of identity matrices in the handle's
-// workspace under each candidate; the workspace contents are overwritten.
+// workspace under each candidate; the workspace contents are overwritten.  The
+// factorisation runs without its zero-block map, so that every update tile does
+// its whole K range (with the map, every tile of an identity returns at once and
+// the timing would only rank launch overheads).
 glasso_err tune_tiles(glasso_handle h, hipStream_t st, int precision, int* chosen) {
   Workspace& w = h->ws;
+  FactorBatch dense = factor_batch(w);
+  dense.nz = nullptr;
   float best = 0.f;
   int best_thr = TUNE_CANDIDATES[0];
   bool have = false;
@@ -526,7 +531,7 @@ glasso_err tune_tiles(glasso_handle h, hipStream_t st, int precision, int* chose
       glasso_err e = push_ints(st, w.info, h->hm.info, w.count);
       if (e) return e;
       HIP_TRY(hipEventRecord(h->ev[0], st));
-      K_TRY(potrf_lower(st, w.L, w.np, (int)w.np, w.dL, w.Dinv, w.info, factor_batch(w)));
+      K_TRY(potrf_lower(st, w.L, w.np, (int)w.np, w.dL, w.Dinv, w.info, dense));
       e = inverse_from_factor(w, st, nullptr);
       if (e) return e;
       if (precision == GLASSO_FP64) {
