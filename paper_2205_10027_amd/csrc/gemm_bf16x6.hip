@@ -313,12 +313,17 @@ __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __re
                                                              int64_t sL, int64_t sD, int64_t sT, int64_t sTt,
                                                              const int* skip) {
   if (skip && skip[blockIdx.z]) return;
+  const int bi = blockIdx.x, bj = blockIdx.y;  // tile rows i, columns j of T
+  // Tiles of T above the 128x128 diagonal blocks (and their transposes in Tt) are
+  // zero and never read: every later product clips its K range at 128-tile
+  // granularity to the triangle (the doubling products, V^T V), so only the zeros
+  // inside the diagonal blocks are read.  They are not written.
+  if ((bj >> 1) > (bi >> 1)) return;
   L += blockIdx.z * sL;
   Dinv += blockIdx.z * sD;
   T += blockIdx.z * sT;
   Tt += blockIdx.z * sTt;
   __shared__ float t[64][65];
-  const int bi = blockIdx.x, bj = blockIdx.y;  // tile rows i, columns j of T
   const int tid = threadIdx.x, c = tid & 63, r0 = tid >> 6;
   const int64_t i0 = (int64_t)bi * 64, j0 = (int64_t)bj * 64;
   const bool same_block = (bi >> 1) == (bj >> 1);  // inside one 128x128 diagonal block
