@@ -7,7 +7,7 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import it.  The product path never calls it and shares no code with it.
 
 Every function is pinned by tests under tests/ (closed forms, KKT invariants,
-an independent G-ISTA solve, brute force on tiny inputs, equivariances and
+an independent proximal-gradient solve, brute force on tiny inputs, equivariances and
 mutation tests).  The trajectory after the line-search fallback (cond-based t,
 Sec. 6) is parity unpinned: the GPU estimates cond(A) by power iteration while
 this oracle computes it exactly; the final solution stays pinned by KKT.
@@ -35,6 +35,10 @@ from .reference import (  # noqa: F401
     predicted_change,
     cond_fallback_step,
     pista,
+    gista_trial_point,
+    quadratic_bound_excess,
+    bb_step,
+    gista,
     PistaResult,
     check_solution,
     CONVERGED,

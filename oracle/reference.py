@@ -276,6 +276,101 @@ def pista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 500,
         k += 1
 
 
+# --------------------------------------------------------------------------- G-ISTA (Sec. 3.2)
+def gista_trial_point(A: np.ndarray, g: np.ndarray, lam: float, t: float) -> np.ndarray:
+    """A + D with D the minimiser of eq. proximal_gen for H = I scaled by 1/t (the
+    proximal-gradient step): <g, D> + ||D||_F^2 / (2t) + lam ||A + D||_1 separates
+    into scalar problems whose minimiser is SoftThreshold(A - t g, t lam)."""
+    return soft_threshold(A - t * g, t * lam)
+
+
+def quadratic_bound_excess(A, At, L, Lt, W, t) -> float:
+    """f(At) - f(A) - <g, At - A> - ||At - A||_F^2 / (2t), f = -log det + tr(S .), in
+    difference form: f(At) - f(A) - <S - W, At - A> = 2 sum_i log(L_ii / Lt_ii) +
+    sum W (.) (At - A).  The proximal-gradient step is accepted when this is <= 0,
+    i.e. when the quadratic model behind the step bounds f at the trial point."""
+    dA = At - A
+    dlog = 2.0 * float(np.sum(np.log(np.diag(L) / np.diag(Lt))))
+    return dlog + float(np.sum(W * dA)) - float(np.sum(dA * dA)) / (2.0 * t)
+
+
+def bb_step(dA: np.ndarray, W_old: np.ndarray, W_new: np.ndarray) -> float:
+    """Barzilai-Borwein step <dA, dA> / <dA, grad f(A_new) - grad f(A_old)> with
+    grad f = S - W, i.e. <dA, dA> / <dA, W_old - W_new>: the first step size G-ISTA
+    tries in the next iteration.  The denominator is positive for dA != 0 (f is
+    strictly convex); otherwise the caller keeps its previous step."""
+    num = float(np.sum(dA * dA))
+    den = float(np.sum(dA * (W_old - W_new)))
+    return num / den if den > 0.0 and num > 0.0 else np.nan
+
+
+def gista(S: np.ndarray, lam: float, tol: float, A0=None, max_iter: int = 5000,
+          t0: float = 1.0, shrink: float = 0.5, t_min: float = 1e-12) -> PistaResult:
+    """G-ISTA: proximal gradient descent on F, the H = I case of eq. proximal_gen
+    (Sec. 3.2), the paper's first-order comparison method (Sec. 6).  Same start
+    (Sec. 6), same stopping rule and measures as pista.  Step sizes follow the
+    G-ISTA authors' recommendation: the first trial of an iteration takes the
+    Barzilai-Borwein step of the previous accepted step (t0 in the first
+    iteration), and backtracking multiplies t by `shrink` until the trial point is
+    PD and quadratic_bound_excess <= 0; the search fails below t_min, or when the
+    trial point no longer differs from A (rounding has swallowed the step)."""
+    S = np.asarray(S, dtype=np.float64)
+    A = initial_iterate(S, lam) if A0 is None else np.array(A0, dtype=np.float64)
+    L = cholesky_or_none(A)
+    if L is None:
+        raise ValueError("initial iterate is not positive definite")
+    F = objective(S, A, lam, L)
+    history = []
+    total_trials = 0
+    k = 0
+    t_next = t0
+    W_prev = dA_prev = None
+    while True:
+        W = inverse_from_cholesky(L)
+        if dA_prev is not None:
+            bb = bb_step(dA_prev, W_prev, W)
+            if np.isfinite(bb):
+                t_next = bb
+        g = gradient(S, W)
+        M = free_set_mask(A, g, lam)
+        G = sign_guess(A, g)
+        Z = min_norm_subgradient(g, G, M, lam)
+        km = kkt_measures(Z, A)
+        rec = {"F": F, "kkt_rel1": km["kkt_rel1"]}
+        if km["kkt_rel1"] <= tol or k >= max_iter:
+            history.append(rec)
+            status = CONVERGED if km["kkt_rel1"] <= tol else MAX_ITER
+            return PistaResult(A, W, F, k, status, km["kkt_rel1"], km["kkt_fro"],
+                               km["kkt_max"], total_trials, history)
+        t = t_next
+        accepted = None
+        trials = 0
+        while t >= t_min:
+            At = gista_trial_point(A, g, lam, t)
+            if np.array_equal(At, A):
+                break  # the step has shrunk below the resolution of A: no progress left
+            Lt = cholesky_or_none(At)
+            trials += 1
+            if Lt is not None and quadratic_bound_excess(A, At, L, Lt, W, t) <= 0.0:
+                accepted = (At, Lt)
+                break
+            t *= shrink
+        total_trials += trials
+        rec.update({"t": t, "trials": trials})
+        history.append(rec)
+        if accepted is None:
+            return PistaResult(A, W, F, k, LS_FAILED, km["kkt_rel1"], km["kkt_fro"],
+                               km["kkt_max"], total_trials, history)
+        At, Lt = accepted
+        dF = objective_change(S, A, At, L, Lt, lam)
+        rec["dF"] = dF
+        W_prev, dA_prev = W, At - A
+        A, L = At, Lt
+        F = F + dF
+        t_next = t
+        k += 1
+
+
 # --------------------------------------------------------------------------- certificate
 def check_solution(S: np.ndarray, A: np.ndarray, lam: float) -> dict:
     """Optimality measures of any candidate A, independent of how it was found:

@@ -214,6 +214,74 @@ def check_armijo(orc, seed=9):
     return all(h["pred"] < 0 and h["dF"] < 0.3 * h["pred"] for h in steps)
 
 
+def check_gista(orc, seed=11):
+    """G-ISTA (H = I in eq. proximal_gen) pinned to the mathematics:
+      * its step minimises <g, D> + D^2/(2t) + lam |A + D| entry by entry (brute
+        force on a fine grid);
+      * the minimiser is a fixed point of the step for any t (gradient from
+        numpy.linalg.inv of an independently certified A*);
+      * the Barzilai-Borwein step of two multiples of the identity, a I -> b I, is
+        a b (closed form);
+      * quadratic_bound_excess equals f(At) - f(A) - <grad f(A), At - A> -
+        ||At - A||^2/(2t) with f from slogdet and the gradient from inv;
+      * a solve reaches the minimiser of the independent proximal-gradient solver
+        (KKT conditions checked on inv(A)), the n = 2 closed form and the
+        closed-form diagonal solution (0 iterations), decreasing F at every step."""
+    rng = np.random.default_rng(seed)
+    for _ in range(40):
+        a, g = rng.normal(scale=2.0, size=2)
+        lam = rng.uniform(0.01, 1.5)
+        t = rng.uniform(0.05, 2.0)
+        x = float(orc.gista_trial_point(np.array([[a]]), np.array([[g]]), lam, t)[0, 0])
+        grid = np.linspace(x - 3.0, x + 3.0, 60001)
+        h = g * (grid - a) + (grid - a) ** 2 / (2 * t) + lam * np.abs(grid)
+        hx = g * (x - a) + (x - a) ** 2 / (2 * t) + lam * abs(x)
+        if hx > h.min() + 1e-9 or abs(grid[np.argmin(h)] - x) > 2e-4:
+            return False
+    S = random_psd(10, 6, seed)
+    lam = 0.12
+    A_ind = gista(S, lam)
+    if kkt_violation(S, A_ind, lam) > 1e-7:
+        return False
+    W_ind = np.linalg.inv(A_ind)
+    for t in (0.05, 0.4, 1.0):
+        if np.abs(orc.gista_trial_point(A_ind, S - W_ind, lam, t) - A_ind).max() > 1e-7:
+            return False
+    for a, b in ((0.5, 0.8), (2.0, 1.25)):
+        n = 4
+        bb = orc.bb_step((b - a) * np.eye(n), np.eye(n) / a, np.eye(n) / b)
+        if abs(bb - a * b) > 1e-12 * a * b:
+            return False
+    X = rng.normal(size=(6, 6))
+    A = X @ X.T + 0.5 * np.eye(6)
+    E = rng.normal(size=(6, 6))
+    At = A + 0.05 * (E + E.T)
+    S6 = random_psd(6, 9, seed + 1)
+    for t in (0.01, 0.3):
+        d = At - A
+        direct = (f_direct(S6, At, 0.0) - f_direct(S6, A, 0.0) - np.sum((S6 - np.linalg.inv(A)) * d)
+                  - np.sum(d * d) / (2 * t))
+        got = orc.quadratic_bound_excess(A, At, np.linalg.cholesky(A), np.linalg.cholesky(At),
+                                         np.linalg.inv(A), t)
+        if abs(got - direct) > 1e-9 * (1.0 + abs(direct)):
+            return False
+    r = orc.gista(S, lam, 1e-8, max_iter=20000)
+    if r.status != orc.CONVERGED or np.abs(r.A - A_ind).max() > 1e-6:
+        return False
+    if abs(f_direct(S, r.A, lam) - f_direct(S, A_ind, lam)) > 1e-9 * abs(f_direct(S, A_ind, lam)):
+        return False
+    if not all(h["dF"] < 0 for h in r.history if "dF" in h):
+        return False
+    S2 = random_psd(2, 3, seed)
+    r2 = orc.gista(S2, 0.2, 1e-10, max_iter=20000)
+    if not np.allclose(r2.A, n2_closed_form(S2, 0.2), rtol=1e-7, atol=1e-9):
+        return False
+    Sd = random_psd(8, 24, seed + 2)
+    lam_d = np.abs(Sd - np.diag(np.diag(Sd))).max() * 1.01
+    rd = orc.gista(Sd, lam_d, 1e-12)
+    return rd.iterations == 0 and np.allclose(rd.A, np.diag(1.0 / (np.diag(Sd) + lam_d)), rtol=1e-14, atol=0)
+
+
 def all_pins(orc):
     return {
         "armijo": check_armijo(orc),
@@ -223,4 +291,5 @@ def all_pins(orc):
         "kkt_invariants": check_kkt_invariants(orc),
         "against_gista": check_against_gista(orc),
         "diagonal": check_diagonal_solution(orc),
+        "gista": check_gista(orc),
     }

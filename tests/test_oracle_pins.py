@@ -278,6 +278,26 @@ def test_armijo_line_search():
     assert pins.check_armijo(oracle)
 
 
+def test_gista_pins():
+    """G-ISTA (H = I in eq. proximal_gen, Sec. 3.2): prox step by brute force, fixed
+    point, Barzilai-Borwein closed form, quadratic-bound excess against slogdet, and
+    solves against the independent solver and the closed forms."""
+    assert pins.check_gista(oracle)
+
+
+def test_gista_reaches_the_pista_minimiser_chain_config0():
+    """Both methods minimise the same strictly convex F: on the chain workload at
+    n = 100 G-ISTA's solution has pISTA's objective and support."""
+    S, _ = synth.chain_problem(100, 50, seed=0)
+    r = oracle.pista(S, 0.2, 1e-9)
+    g = oracle.gista(S, 0.2, 1e-7)
+    assert g.status == oracle.CONVERGED
+    assert abs(g.objective - r.objective) <= 1e-9 * abs(r.objective)
+    chk = oracle.check_solution(S, g.A, 0.2)
+    assert chk["kkt_rel1"] <= 1e-7
+    assert np.array_equal(g.A != 0, r.A != 0)
+
+
 def test_iteration_cap_status():
     S, _ = synth.chain_problem(50, 25, 0)
     r = oracle.pista(S, 0.2, 1e-12, max_iter=2)
@@ -349,6 +369,15 @@ MUTANTS = {
     "predicted_change_drops_l1": dict(predicted_change=lambda g, A, At, lam: float(np.sum(g * (At - A)))),
     "cond_fallback_unsquared": dict(cond_fallback_step=lambda A, factor=0.9:
                                     factor * np.linalg.eigvalsh(A)[0] / np.linalg.eigvalsh(A)[-1]),
+    "gista_step_wrong_sign": dict(gista_trial_point=lambda A, g, lam, t: opista.soft_threshold(A + t * g, t * lam)),
+    "gista_threshold_unscaled": dict(gista_trial_point=lambda A, g, lam, t: opista.soft_threshold(A - t * g, lam)),
+    "bb_step_reciprocal": dict(bb_step=lambda dA, Wo, Wn: 1.0 / opista.bb_step(dA, Wo, Wn)),
+    "quadratic_bound_drops_quadratic": dict(quadratic_bound_excess=lambda A, At, L, Lt, W, t:
+                                            opista.quadratic_bound_excess(A, At, L, Lt, W, t)
+                                            + float(np.sum((At - A) ** 2)) / (2.0 * t)),
+    "quadratic_bound_gradient_sign": dict(quadratic_bound_excess=lambda A, At, L, Lt, W, t:
+                                          opista.quadratic_bound_excess(A, At, L, Lt, W, t)
+                                          - 2.0 * float(np.sum(W * (At - A)))),
 }
 
 
@@ -358,7 +387,7 @@ def test_mutant_is_caught(name):
     caught = False
     for check in (pins.check_scalar_lemma, pins.check_diagonal_solution, pins.check_n2_closed_form,
                   pins.check_kkt_invariants, pins.check_against_gista, pins.check_cond_fallback,
-                  pins.check_armijo):
+                  pins.check_armijo, pins.check_gista):
         try:
             ok = check(m) if check is not pins.check_scalar_lemma else check(m, trials=40)
         except Exception:
