@@ -20,6 +20,8 @@ Extra objects on the same line:
   config.vs_oracle, chain_n100, random_n2000
                 every result's error against the oracle's stored solution; the chain
                 n = 100 and random n = 2000 workloads (FP64 / FP32 / BF16x3) timed
+  gista         G-ISTA (proximal gradient, the paper's first-order comparison method)
+                on the same engine: chain n = 10^4 and random n = 2000 time-to-KKT beside pISTA
   batched       regularisation path (random sparse n=1000, m=500, 32 lambdas
                 from lambda_max to lambda_max/100, tol 1e-5 and 1e-8): solves/s and
                 error against the oracle per mode
@@ -31,7 +33,8 @@ Extra objects on the same line:
                 lambda scaled by the GPU's iteration count
 
     python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
-                    [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline] [--dense-product]
+                    [--no-path] [--no-serve] [--no-fp64-ref] [--no-cpu-baseline] [--no-gista]
+                    [--dense-product]
 """
 from __future__ import annotations
 
@@ -253,6 +256,58 @@ def time_chain(g, St, lams, tol, precision, steps, warmup, torch, dense_product=
     elapsed = time.perf_counter() - t0
     solver.close()
     return elapsed, results, As
+
+
+def bench_gista(g, torch, dev, St10k, lams, tol, pista_s):
+    """G-ISTA (proximal gradient, the H = I case of eq. proximal_gen; the paper's
+    first-order comparison method) on the same engine and workloads: time-to-KKT of
+    the chain n = 10^4 solves (the default mixed form: W with FP32 accuracy while
+    iterating) and of the random sparse n = 2000 workload, iterations and trials
+    beside pISTA's, every result against the oracle's stored solution."""
+    import json as _json
+
+    import synth
+
+    out = {"method": "G-ISTA: trial point ST(A - t g, t lambda), Barzilai-Borwein first step, backtracking "
+                     "until PD with f below its quadratic model", "chain_n10000": {}, "random_n2000": {}}
+    for prec in ("bf16x3", "fp64"):
+        s = g.Solver(method="gista", precision=prec, max_iter=5000)
+        s.autotune(St10k.shape[0])
+        per = []
+        t0 = time.perf_counter()
+        for lam in lams:
+            r = s.solve(St10k, lam, tol, want_W=False)
+            torch.cuda.synchronize()
+            err = golden_error(f"chain10k_lam{lam}", [r])
+            per.append({"lambda": lam, "s": r.time_ms[0] / 1000.0, "iterations": r.iterations,
+                        "ls_trials": r.ls_trials, "status": r.status_name, "kkt_rel1": r.kkt_rel1,
+                        "objective_rel_err_vs_oracle": err["worst_objective_rel_err"] if err else None,
+                        "support_mismatch_vs_oracle": err["support_mismatch"] if err else None})
+            log(f"[bench] gista {prec} chain n=10^4 lambda={lam}: {r.time_ms[0] / 1000:.2f}s, "
+                f"{r.iterations} iterations, {r.ls_trials} trials")
+        dt = (time.perf_counter() - t0) / len(lams)
+        s.close()
+        out["chain_n10000"][prec] = {"s_per_solve": dt, "per_lambda": per}
+    out["chain_n10000"]["pista_bf16x3_s_per_solve"] = pista_s
+    out["chain_n10000"]["pista_speedup_over_gista_bf16x3"] = out["chain_n10000"]["bf16x3"]["s_per_solve"] / pista_s
+    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
+        w = _json.load(f)["random_sparse_n2000"]
+    S = torch.from_numpy(synth.random_sparse_problem(w["n"], w["m"], w["seed"])[0]).to(dev)
+    for method in ("gista", "pista"):
+        s = g.Solver(method=method, precision="bf16x3", max_iter=5000)
+        s.solve(S, w["lambda"], w["tol"])  # warmup
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = s.solve(S, w["lambda"], w["tol"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        s.close()
+        err = golden_error("random2000", [r])
+        out["random_n2000"][method] = {"s_per_solve": dt, "iterations": r.iterations, "ls_trials": r.ls_trials,
+                                       "status": r.status_name,
+                                       "objective_rel_err_vs_oracle": err["worst_objective_rel_err"] if err else None}
+        log(f"[bench] {method} random n=2000 bf16x3: {dt * 1e3:.1f} ms, {r.iterations} iterations")
+    return out
 
 
 def bench_path(g, torch, dev):
@@ -521,6 +576,7 @@ def main():
     ap.add_argument("--support", action="store_true",
                     help="also run the support-recovery sweep (about a minute of GPU time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gista", action="store_true")
     ap.add_argument("--dense-product", action="store_true",
                     help="form every A Z A with the dense GEMM pair (the paper's design)")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -673,6 +729,8 @@ def main():
     line["chain_n100"] = bench_config0(g, torch, dev)
     line["random_n2000"] = bench_config1(g, torch, dev)
     line["covariance"] = bench_covariance(g, torch, dev)
+    if not args.no_gista:
+        line["gista"] = bench_gista(g, torch, dev, St, lams, tol, value)
     if args.support:
         line["support_recovery"] = bench_support(g, torch, dev)
     if not args.no_path:

@@ -43,7 +43,7 @@ typedef enum {
 typedef enum {
   GLASSO_CONVERGED = 0, /* ||Z||_1 <= tol * ||A||_1 (stopping rule, Sec. 6) */
   GLASSO_MAX_ITER = 1,  /* max_iter accepted steps without meeting tol */
-  GLASSO_LS_FAILED = 2  /* no step size down to t_min was PD with a strict decrease */
+  GLASSO_LS_FAILED = 2  /* no step size down to t_min passed the line search's test */
 } glasso_status;
 
 typedef enum {
@@ -110,7 +110,25 @@ typedef struct {
                       ||A||_1)), the decrease that the linear model of f plus the l1 term
                       predicts (an Armijo rule); 0 (default): strict decrease, the paper's
                       condition t_cond_min.  0 <= sigma < 1. */
+  int method;      /* glasso_method; default GLASSO_PISTA.  GLASSO_GISTA solves the same problem
+                      by proximal gradient descent (the H = I case of eq. proximal_gen, Sec. 3.2;
+                      the paper's first-order comparison method, Sec. 6): trial point
+                      ST(A - t (S - W), t lambda); accepted when positive definite with
+                      f(At) <= f(A) + <g, At - A> + ||At - A||_F^2 / (2t), f = -log det + tr(S .),
+                      evaluated in difference form; the first step of each iteration is the
+                      Barzilai-Borwein step <dA, dA> / <dA, W_prev - W> of the last accepted step
+                      dA (t0 in the first iteration), then t *= shrink down to t_min (t_floor and
+                      sigma do not apply); a trial point equal to A (the step lost in rounding)
+                      ends the search with GLASSO_LS_FAILED.  Same start, stopping rule,
+                      precisions (no product: precision only sets the W ladder) and outputs as
+                      pISTA.  glasso_solve_small and glasso_solve_small_static accept
+                      GLASSO_PISTA only; with screen, every block goes to the batched engine. */
 } glasso_options;
+
+typedef enum {
+  GLASSO_PISTA = 0, /* Alg. 1 (preconditioned ISTA) */
+  GLASSO_GISTA = 1  /* proximal gradient (G-ISTA), see glasso_options.method */
+} glasso_method;
 
 #define GLASSO_TILES_AUTO (-1)
 
@@ -320,6 +338,18 @@ glasso_err glasso_precond_product(glasso_handle h, const double* A, const double
 glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P, const double* S,
                               const int8_t* GM, int64_t n, double lambda, double t, double* At,
                               double* sums, void* stream);
+
+/* Trial point of a G-ISTA step (eq. proximal_gen with H = I, Sec. 3.2):
+ * g = S - W, At = SoftThreshold(A - t g, t lambda) on the free set M = (GM != 0)
+ * (zero elsewhere, where the step gives exactly zero), n x n full symmetric.
+ * sums (host, 4 doubles, may be NULL) receive sum S (.) (At - A), sum (|At| - |A|),
+ * sum W (.) (At - A) and ||At - A||_F^2.  A, S, W (n x n, symmetric, lower
+ * triangles read) and GM (n x n int8, from glasso_gradient_pass) are device
+ * buffers; At is a device buffer the caller owns.
+ * Errors: INVALID_ARG for a null handle or buffer, n < 1, lambda <= 0 or t <= 0. */
+glasso_err glasso_gista_trial_point(glasso_handle h, const double* A, const double* S, const double* W,
+                                    const int8_t* GM, int64_t n, double lambda, double t, double* At,
+                                    double* sums, void* stream);
 
 /* The preconditioned product as a solve forms it when dense_product is 0 (the
  * sampled sparse form; the paper's design forms A Z A densely, Sec. 4.3.3): P_ij =

@@ -20,6 +20,8 @@ _lib = _native.load()
 FP64, MIXED_FP32, MIXED_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3}
 CONVERGED, MAX_ITER, LS_FAILED = 0, 1, 2
+PISTA, GISTA = 0, 1  # glasso_method
+METHODS = {"pista": PISTA, "gista": GISTA}
 TILES_AUTO = -1  # tile policy chosen by the autotuner (GLASSO_TILES_AUTO)
 SMALL_MAX_N = 64  # largest n of glasso_solve_small (GLASSO_SMALL_MAX_N)
 SMALL_STATIC_MAX_COUNT = 16384  # problems per glasso_solve_small_static call
@@ -94,7 +96,7 @@ class Solver:
                  shrink: float = 0.5, t_floor: float = 1e-4, t_min: float = 1e-12,
                  warm_start: bool = False, tile_policy: int = TILES_AUTO, graphs: bool = False,
                  w_mixed: int = -1, ls_width: int = 0, dense_product: bool = False, screen: bool = False,
-                 sigma: float = 0.0):
+                 sigma: float = 0.0, method: str | int = "pista"):
         opt = GlassoOptions()
         _check(_lib.glasso_default_options(ctypes.byref(opt)), "glasso_default_options")
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -111,6 +113,7 @@ class Solver:
         opt.dense_product = int(bool(dense_product))
         opt.screen = int(bool(screen))
         opt.sigma = float(sigma)
+        opt.method = METHODS[method] if isinstance(method, str) else int(method)
         self.options = opt
         h = ctypes.c_void_p()
         _check(_lib.glasso_create(ctypes.byref(h), ctypes.byref(opt)), "glasso_create")
@@ -292,6 +295,20 @@ class Solver:
                                           P.data_ptr(), ctypes.byref(used), _stream(stream)),
                "glasso_sparse_product")
         return P, bool(used.value)
+
+    def gista_trial_point(self, A, S, W, GM, lam: float, t: float, stream=None):
+        """G-ISTA trial point ST(A - t (S - W), t lam) on the free set
+        (glasso_gista_trial_point); returns (At, sums[4])."""
+        n = _square(A, "A")
+        for name, x in (("S", S), ("W", W)):
+            if tuple(x.shape) != (n, n):
+                raise ValueError(f"{name} must be n x n")
+        At = torch.empty_like(A)
+        sums = (ctypes.c_double * 4)()
+        _check(_lib.glasso_gista_trial_point(self._h, _dev(A, "A"), _dev(S, "S"), _dev(W, "W"),
+                                             _dev(GM, "GM", torch.int8), n, float(lam), float(t), At.data_ptr(),
+                                             sums, _stream(stream)), "glasso_gista_trial_point")
+        return At, list(sums)
 
     def trial_point(self, A, P, S, GM, lam: float, t: float, stream=None):
         n = _square(A, "A")

@@ -26,6 +26,7 @@ class GlassoOptions(ctypes.Structure):
         ("dense_product", ctypes.c_int),
         ("screen", ctypes.c_int),
         ("sigma", ctypes.c_double),
+        ("method", ctypes.c_int),
     ]
 
 
@@ -78,6 +79,7 @@ SIGNATURES = {
     "glasso_gradient_pass": (_INT, [_VP, _VP, _VP, _VP, _I64, _D, _VP, _VP, c_double_p, _VP]),
     "glasso_precond_product": (_INT, [_VP, _VP, _VP, _I64, _INT, _VP, _VP]),
     "glasso_trial_point": (_INT, [_VP, _VP, _VP, _VP, _VP, _I64, _D, _D, _VP, c_double_p, _VP]),
+    "glasso_gista_trial_point": (_INT, [_VP, _VP, _VP, _VP, _VP, _I64, _D, _D, _VP, c_double_p, _VP]),
     "glasso_sparse_product": (_INT, [_VP, _VP, _VP, _VP, _I64, _VP, ctypes.POINTER(_INT), _VP]),
 }
 

@@ -73,6 +73,17 @@ __device__ __forceinline__ double trial_element(double a, double p, double Cij, 
   return sign_of(x) * m;
 }
 
+// G-ISTA trial element (eq. proximal_gen with H = I, the proximal-gradient step):
+// At = ST(A - t g, t lam) with g = S - W.  Off the free set (A = 0, |g| <= lam) it is
+// exactly 0, so the pass visits only the free set, as for the pISTA step.
+__device__ __forceinline__ double gista_element(double a, double s, double w, double lam, double t) {
+  const double g = s - w;
+  const double x = a - t * g;
+  const double tau = t * lam;
+  const double m = fmax(fabs(x) - tau, 0.0);
+  return sign_of(x) * m;
+}
+
 }  // namespace
 
 }  // namespace glasso

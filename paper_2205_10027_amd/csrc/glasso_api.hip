@@ -329,6 +329,7 @@ glasso_err check_options(const glasso_options* o) {
   if (o->ls_width < 0 || o->ls_width > LS_WIDTH_MAX) return GLASSO_ERR_INVALID_ARG;
   if (o->dense_product < 0 || o->dense_product > 1) return GLASSO_ERR_INVALID_ARG;
   if (o->screen < 0 || o->screen > 1 || !(o->sigma >= 0.0 && o->sigma < 1.0)) return GLASSO_ERR_INVALID_ARG;
+  if (o->method != GLASSO_PISTA && o->method != GLASSO_GISTA) return GLASSO_ERR_INVALID_ARG;
   if (!(o->t0 > 0.0) || !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->t_floor >= 0.0) || !(o->t_min > 0.0))
     return GLASSO_ERR_INVALID_ARG;
   return GLASSO_OK;
@@ -652,6 +653,14 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       prod_b(count, 0), ncand(count, 0),
       last_trials(count, 1), since(count, 0);
   std::vector<double> tb(count, o.t0);  // next step size of each problem's backtracking sequence
+  // G-ISTA (eq. proximal_gen with H = I): no preconditioned product; the trial point
+  // is ST(A - t g, t lam), accepted when PD with f below its quadratic model; the
+  // first step of an iteration is the Barzilai-Borwein step of the last accepted
+  // one (bb_num / (bb_dw - SC_DW_NEW), the gradient pass summing W (.) (A - A_prev)
+  // against the replaced iterate, which the accept step leaves in P)
+  const bool gista = o.method == GLASSO_GISTA;
+  std::vector<double> t_next(count, o.t0), bb_num(count, 0.0), bb_dw(count, 0.0);
+  std::vector<int> bb_have(count, 0);
   const bool sparse_on = o.dense_product == 0;
   // this iteration's product tries the sparse form (eager launches skip it when every
   // active problem has more than SPARSE_KA nonzeros per row on average, so some row
@@ -692,6 +701,10 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   double* const z_f64 = (o.precision == GLASSO_MIXED_BF16X3) ? nullptr : w.Z;
   void* const z_split = (o.precision == GLASSO_MIXED_BF16X3) ? (void*)(reinterpret_cast<uint8_t*>(w.X) + 4 * nn)
                                                              : nullptr;
+  // the replaced iterate of the last accepted step (G-ISTA): the trial buffer that
+  // held the old iterate after an exchange, else P, where the accept step saves it
+  const bool swap_accept = !o.graphs && count == 1 && K == 1;
+  auto a_prev = [&]() -> const double* { return gista ? (swap_accept ? w.At : w.P) : nullptr; };
   auto head = [&](hipStream_t s, bool timed) -> glasso_err {  // a1, a2
     glasso_err e2 = push_ints(s, w.skip, hm.skip, count);
     if (e2) return e2;
@@ -711,7 +724,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (e2) return e2;
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
-    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn,
+                    a_prev()));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], s));
     return fetch_async(h, s);
   };
@@ -731,7 +745,8 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     if (e2) return e2;
     K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
     K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
-    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pr, z_split, 8 * nn));
+    K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pr, z_split, 8 * nn,
+                    a_prev()));
     return fetch_async(h, s);
   };
   auto prod = [&](hipStream_t s, bool timed) -> glasso_err {  // a3
@@ -759,7 +774,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     e2 = push_doubles(s, w.t, hm.t, slots);
     if (e2) return e2;
     K_TRY(pass_trial(s, w.A, w.P, w.S, w.GM, n, np, 0.0, 0.0, w.At, w.Lt, w.part, w.info, pt,
-                     o.sigma > 0.0 ? w.W : nullptr));
+                     (o.sigma > 0.0 || gista) ? w.W : nullptr, gista ? 1 : 0));
     // the trial's factor is finished (diagonal blocks placed and inverted) only if
     // it is accepted, at the next head
     if (timed) HIP_TRY(hipEventRecord(h->ev[8], s));
@@ -782,7 +797,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
   auto accept = [&](hipStream_t s, bool) -> glasso_err {  // a7
     glasso_err e2 = push_ints(s, w.accept, hm.accept, count);
     if (e2) return e2;
-    K_TRY(accept_trials(s, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, np));
+    K_TRY(accept_trials(s, w.accept, count, w.A, w.At, w.L, w.Lt, w.dL, w.dLt, np, gista ? w.P : nullptr));
     return GLASSO_OK;
   };
   const bool graphs = o.graphs != 0;
@@ -804,7 +819,6 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       if (parity) flip();
     }
   } swapped{w, 0};
-  const bool swap_accept = !graphs && count == 1 && K == 1;
   if (graphs) {
     GraphKey key;
     key.base = w.base;
@@ -884,6 +898,14 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       e = run_recheck(mark);
       if (e) return e;
     }
+    if (gista)
+      for (int b = 0; b < count; ++b) {
+        if (!active[b] || !bb_have[b]) continue;
+        const double den = bb_dw[b] - hscal(h, b, SC_DW_NEW);
+        const double bb = bb_num[b] / den;
+        if (den > 0.0 && bb_num[b] > 0.0 && std::isfinite(bb)) t_next[b] = bb;
+        bb_have[b] = 0;
+      }
     int nact = 0;
     for (int b = 0; b < count; ++b) {
       if (!active[b]) continue;
@@ -901,7 +923,9 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     for (int b = 0; b < count; ++b) hm.skip[b] = !active[b];
     // a3: P = A Z A; with A still the diagonal A^(0) it is D Z D, formed elementwise
     HIP_TRY(hipEventRecord(h->ev[2], st));
-    if (exact_w) {
+    if (gista) {
+      // no preconditioned product
+    } else if (exact_w) {
       HIP_TRY(hipEventRecord(h->ev[5], st));
       e = push_ints(st, w.skip, hm.skip, count);
       if (e) return e;
@@ -930,7 +954,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     for (int b = 0; b < count; ++b) {
       ls[b] = active[b];
       fb_used[b] = 0;
-      tb[b] = o.t0;
+      tb[b] = gista ? t_next[b] : o.t0;
     }
     // acceptance: a strict decrease (sigma = 0, condition t_cond_min) or sigma times
     // the decrease the linear model predicts (the trial pass read W for it)
@@ -940,7 +964,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       int nls = 0;
       for (int b = 0; b < count; ++b) {
         if (!ls[b]) continue;
-        if (tb[b] < o.t_floor && !fb_used[b]) {
+        if (!gista && tb[b] < o.t_floor && !fb_used[b]) {
           double tf = 0.0;
           e = cond_fallback_step(h, st, b, n, &tf);
           if (e) return e;
@@ -968,7 +992,7 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
           hm.lsskip[b * K + ncand[b]] = 0;
           if (++ncand[b] == want) break;
           c *= o.shrink;
-          if (c < o.t_min || (c < o.t_floor && !fb_used[b])) break;
+          if (c < o.t_min || (!gista && c < o.t_floor && !fb_used[b])) break;
         }
       }
       first_round = false;
@@ -991,10 +1015,34 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
       for (int b = 0; b < count; ++b) {
         hm.accept[b] = 0;
         if (!ls[b]) continue;
-        int got = -1;
-        for (int i = 0; i < ncand[b] && got < 0; ++i)
-          if (hm.info[b * K + i] == 0 && hscal_t(h, b * K + i, SC_DF) < decrease_target(b * K + i)) got = i;
+        int got = -1, stalled = -1;
+        for (int i = 0; i < ncand[b] && got < 0 && stalled < 0; ++i) {
+          const int j = b * K + i;
+          if (gista) {
+            // a trial point equal to A: the step is below the resolution of A
+            if (hscal_t(h, j, SC_D2) == 0.0)
+              stalled = i;
+            else if (hm.info[j] == 0 && hscal_t(h, j, SC_QB) <= 0.0)
+              got = i;
+          } else if (hm.info[j] == 0 && hscal_t(h, j, SC_DF) < decrease_target(j)) {
+            got = i;
+          }
+        }
+        if (stalled >= 0) {
+          trials[b] += stalled;
+          ls[b] = 0;
+          active[b] = 0;
+          status[b] = GLASSO_LS_FAILED;
+          continue;
+        }
         if (got >= 0) {
+          if (gista) {
+            const int j = b * K + got;
+            t_next[b] = hm.t[j];
+            bb_num[b] = hscal_t(h, j, SC_D2);
+            bb_dw[b] = hscal_t(h, j, SC_DW);
+            bb_have[b] = 1;
+          }
           trials[b] += got + 1;
           since[b] += got + 1;
           last_trials[b] = since[b];
@@ -1104,6 +1152,7 @@ glasso_err glasso_default_options(glasso_options* opt) {
   opt->t_floor = 1e-4;
   opt->t_min = 1e-12;
   opt->warm_start = 0;
+  opt->method = GLASSO_PISTA;
   return GLASSO_OK;
 }
 
@@ -1331,7 +1380,8 @@ glasso_err run_screened(glasso_handle h, hipStream_t st, int count, const double
     std::vector<double*> sA, sW, bA, bW;
     std::vector<int> sid, bid;
     for (int b = 0; b < nb; ++b) {
-      const bool small = tab[b].k <= GLASSO_SMALL_MAX_N;
+      // the persistent small solver runs pISTA only
+      const bool small = tab[b].k <= GLASSO_SMALL_MAX_N && h->opt.method == GLASSO_PISTA;
       (small ? sS : bS).push_back(tab[b].Sk);
       (small ? sn : bn).push_back(tab[b].k);
       (small ? sl : bl).push_back(lambda[blocks[b].p]);
@@ -1587,7 +1637,7 @@ glasso_err small_with_handle(glasso_handle h, int count, const double* const* S,
 glasso_err glasso_solve_small(glasso_handle h, int count, const double* const* S, const int64_t* n,
                               const double* lambda, double tol, double* const* A, double* const* W,
                               glasso_info* info, void* stream) {
-  if (!h || !small_args_ok(count, S, n, lambda, tol, A)) return GLASSO_ERR_INVALID_ARG;
+  if (!h || !small_args_ok(count, S, n, lambda, tol, A) || h->opt.method != GLASSO_PISTA) return GLASSO_ERR_INVALID_ARG;
   return small_with_handle(h, count, S, n, lambda, tol, A, W, info, (hipStream_t)stream);
 }
 
@@ -1627,7 +1677,7 @@ glasso_err glasso_solve_small_static(const glasso_options* opt, int count, const
   glasso_options o;
   glasso_default_options(&o);
   if (opt) {
-    if (check_options(opt)) return GLASSO_ERR_INVALID_ARG;
+    if (check_options(opt) || opt->method != GLASSO_PISTA) return GLASSO_ERR_INVALID_ARG;
     o = *opt;
   }
   std::lock_guard<std::mutex> lock(g_static_mu);
@@ -1866,6 +1916,34 @@ glasso_err glasso_trial_point(glasso_handle h, const double* A, const double* P,
   if (sums) {
     sums[0] = hscal(h, 0, SC_DTR);
     sums[1] = hscal(h, 0, SC_DL1);
+  }
+  return GLASSO_OK;
+}
+
+glasso_err glasso_gista_trial_point(glasso_handle h, const double* A, const double* S, const double* W,
+                                    const int8_t* GM, int64_t n, double lambda, double t, double* At, double* sums,
+                                    void* stream) {
+  if (!h || !A || !S || !W || !GM || !At || n < 1 || !(lambda > 0.0) || !(t > 0.0)) return GLASSO_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t np = pad_to_tile(n);
+  glasso_err e = ensure_workspace(h, 1, np, st);
+  if (e) return e;
+  Workspace& w = h->ws;
+  K_TRY(pad_copy_f64(st, A, n, np, w.A, nullptr, 1));
+  K_TRY(pad_copy_f64(st, S, n, np, w.S, nullptr, 0));
+  K_TRY(pad_copy_f64(st, W, n, np, w.W, nullptr, 0));
+  K_TRY(pad_copy_i8(st, GM, n, np, w.GM));
+  K_TRY(pass_trial(st, w.A, w.P, w.S, w.GM, n, np, lambda, t, w.At, w.Lt, w.part, w.info, PassBatch(), w.W, 1));
+  // no factor: the log-ratio term reads the same diagonal twice and vanishes
+  K_TRY(finish_trial(st, w.part, (int)pass_tiles(np), w.dL, w.dL, w.info, 0, lambda, w.scal, PassBatch(), t));
+  K_TRY(sym_copy_out(st, w.At, np, At, n, 0));
+  e = fetch(h, st);
+  if (e) return e;
+  if (sums) {
+    sums[0] = hscal(h, 0, SC_DTR);
+    sums[1] = hscal(h, 0, SC_DL1);
+    sums[2] = hscal(h, 0, SC_DW);
+    sums[3] = hscal(h, 0, SC_D2);
   }
   return GLASSO_OK;
 }

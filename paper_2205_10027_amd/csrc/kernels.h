@@ -184,26 +184,34 @@ struct PassBatch {
 
 // Z (FP64, may be null) and/or Zs, its two-part bf16 split (4 bytes per element,
 // per-problem byte stride sZs; may be null).
+// Aprev (may be null; per-problem stride pb.sM): the previous iterate, for
+// SC_DW_NEW = sum W (.) (A - Aprev), the second half of the Barzilai-Borwein
+// denominator of G-ISTA.
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A,
               const double* dL, int64_t n, int64_t nlog, int64_t np, double lam, double* Z,
               int8_t* GM, double* part, double* scal, const PassBatch& pb = PassBatch(),
-              void* Zs = nullptr, int64_t sZs = 0);
+              void* Zs = nullptr, int64_t sZs = 0, const double* Aprev = nullptr);
 // info_reset[b] is set to 0 for the problems the pass handles and to -1 for the
 // skipped ones, so that the Cholesky that follows skips them too.
 // W (may be null): with it the pass also sums W (.) (At - A) for the predicted
-// change of the sufficient-decrease test (finish_trial writes SC_PRED)
+// change of the sufficient-decrease test (finish_trial writes SC_PRED, SC_DW).
+// gista != 0: the trial point is the G-ISTA step ST(A - t (S - W), t lam) instead
+// of eq. d_sol (W required, P unread); finish_trial then writes SC_QB.
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S,
                const int8_t* GM, int64_t n, int64_t np, double lam, double t, double* At,
                double* Lt, double* part, int* info_reset, const PassBatch& pb = PassBatch(),
-               const double* W = nullptr);
+               const double* W = nullptr, int gista = 0);
+// t: the step size when pb.t is null (for SC_QB)
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL,
                  const double* dLt, const int* info, int64_t n, double lam, double* scal,
-                 const PassBatch& pb = PassBatch());
+                 const PassBatch& pb = PassBatch(), double t = 1.0);
 // for every problem b with accept[b] = j + 1 != 0 copy trial slot j's point, its
 // (unfinished) factor and diagonal over problem b's current ones; the diagonal-block
 // inverses are formed when the factor is finished
+// (Aprev, may be null: receives problem b's replaced iterate first)
 int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At,
-                  double* L, const double* Lt, double* dL, const double* dLt, int64_t np);
+                  double* L, const double* Lt, double* dL, const double* dLt, int64_t np,
+                  double* Aprev = nullptr);
 int sym_copy_out(hipStream_t stream, const double* src, int64_t np, double* dst, int64_t n,
                  int mode);
 // sample covariance (eq. empirical_cov): column means of Y (m x n row-major) into mu;
@@ -307,11 +315,15 @@ enum ScalarSlot {
   SC_POWER_W,
   SC_DENSE_PRODUCT,  // 1: the last product used the dense GEMM pair, 0: the sparse product
   SC_PRED,           // predicted change <g, At - A> + lam (||At||_1 - ||A||_1) (with W given)
+  SC_DW,             // sum W (.) (At - A) (with W given)
+  SC_D2,             // ||At - A||_F^2
+  SC_QB,             // G-ISTA: f(At) - f(A) - <g, At - A> - ||At - A||_F^2 / (2t) (with W given)
+  SC_DW_NEW,         // gradient pass with the previous iterate: sum W (.) (A - A_prev)
   SC_COUNT = 24
 };
 
-constexpr int GRAD_PARTS = 6;   // per-workgroup partials of pass_grad
-constexpr int TRIAL_PARTS = 4;  // per-workgroup partials of pass_trial
+constexpr int GRAD_PARTS = 7;   // per-workgroup partials of pass_grad
+constexpr int TRIAL_PARTS = 5;  // per-workgroup partials of pass_trial
 
 inline int64_t pass_tiles(int64_t np) {
   const int64_t T = np / 64;

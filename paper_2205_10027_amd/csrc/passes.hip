@@ -10,6 +10,8 @@
 //   C_ij = lam (A_ii A_jj + A_ij^2) (i != j), lam A_ii^2 (i = j);
 //   B = P - C (.) GM with P = A Z A;  At = M (.) ST(A - tB, tC);
 //   sums of S (.) (At - A) and |At| - |A| for the difference-form decrease.
+//   G-ISTA mode (eq. proximal_gen with H = I): At = ST(A - t (S - W), t lam), with
+//   sums of W (.) (At - A) and (At - A)^2 for its quadratic-bound test.
 //
 // Both passes visit only the tiles on or below the diagonal (64x64 tiles of the
 // padded matrix), read lower triangles, and write symmetric outputs through an
@@ -36,7 +38,8 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
                                                         const double* __restrict__ dL, int64_t n,
                                                         int64_t np, double lam, double* __restrict__ Z,
                                                         uint8_t* __restrict__ Zs, int64_t sZs,
-                                                        int8_t* __restrict__ GM, double* part, int T, PassBatch pb) {
+                                                        int8_t* __restrict__ GM, double* part, int T, PassBatch pb,
+                                                        const double* __restrict__ Aprev) {
   __shared__ double zt[64][65];
   __shared__ int8_t gt[64][68];
   __shared__ double sh[4];
@@ -49,6 +52,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
   if (Z) Z += pbi * pb.sM;
   if (Zs) Zs += pbi * sZs;
   GM += pbi * pb.sM;
+  if (Aprev) Aprev += pbi * pb.sM;
   part += (int64_t)pbi * gridDim.x * GRAD_PARTS;
   int ti, tj;
   lower_tile(xcd_remap(blockIdx.x, gridDim.x), T, ti, tj);
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
   const int64_t i0 = (int64_t)ti * 64, j0 = (int64_t)tj * 64;
   const bool diag = (ti == tj);
 
-  double s_absz = 0.0, s_z2 = 0.0, m_absz = 0.0, s_absa = 0.0, s_nnz = 0.0, s_sa = 0.0;
+  double s_absz = 0.0, s_z2 = 0.0, m_absz = 0.0, s_absa = 0.0, s_nnz = 0.0, s_sa = 0.0, s_dw = 0.0;
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int r = rw + 4 * q;
@@ -76,6 +80,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
         s_absa += wgt * fabs(a);
         s_nnz += nz ? wgt : 0.0;
         s_sa += wgt * (s * a);
+        if (Aprev) s_dw += wgt * (w * (a - Aprev[off]));
       }
       if (Z) Z[off] = z;
       if (Zs) store_split2(Zs, np, i, j, z);
@@ -105,6 +110,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
   const double b3 = block_sum(s_absa, sh);
   const double b4 = block_sum(s_nnz, sh);
   const double b5 = block_sum(s_sa, sh);
+  const double b6 = block_sum(s_dw, sh);
   if (tid == 0) {
     double* pp = part + (int64_t)blockIdx.x * GRAD_PARTS;
     pp[0] = b0;
@@ -113,6 +119,7 @@ __global__ __launch_bounds__(256) void pass_grad_kernel(const double* __restrict
     pp[3] = b3;
     pp[4] = b4;
     pp[5] = b5;
+    pp[6] = b6;
   }
 }
 
@@ -127,7 +134,7 @@ __global__ __launch_bounds__(256) void finish_grad_kernel(const double* part, in
   part += (int64_t)pbi * nparts * GRAD_PARTS;
   dL += pbi * pb.sV;
   scal += (int64_t)pbi * SC_COUNT;
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t5 = 0.0, t6 = 0.0;
   for (int b = tid; b < nparts; b += 256) {
     const double* pp = part + (int64_t)b * GRAD_PARTS;
     t0 += pp[0];
@@ -136,6 +143,7 @@ __global__ __launch_bounds__(256) void finish_grad_kernel(const double* part, in
     t3 += pp[3];
     t4 += pp[4];
     t5 += pp[5];
+    t6 += pp[6];
   }
   double tl = 0.0;
   for (int64_t i = tid; i < nlog; i += 256) tl += log(dL[i]);
@@ -145,8 +153,10 @@ __global__ __launch_bounds__(256) void finish_grad_kernel(const double* part, in
   const double sa = block_sum(t3, sh);
   const double nnz = block_sum(t4, sh);
   const double ssa = block_sum(t5, sh);
+  const double dwn = block_sum(t6, sh);
   const double ld = 2.0 * block_sum(tl, sh);
   if (tid == 0) {
+    scal[SC_DW_NEW] = dwn;
     scal[SC_SUM_ABS_Z] = sz;
     scal[SC_SUM_Z2] = sz2;
     scal[SC_MAX_ABS_Z] = mz;
@@ -167,7 +177,8 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
                                                          const int8_t* __restrict__ GM, int64_t n, int64_t np,
                                                          double lam, double t, double* __restrict__ At,
                                                          double* __restrict__ Lt, double* part, int* info_reset,
-                                                         int T, PassBatch pb, const double* __restrict__ W) {
+                                                         int T, PassBatch pb, const double* __restrict__ W,
+                                                         int gista) {
   __shared__ double tt[64][65];
   __shared__ double di[64], dj[64];
   __shared__ double sh[4];
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
     dj[tid - 64] = A[(j0 + tid - 64) * (np + 1)];
   __syncthreads();
 
-  double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0, s_w = 0.0;
+  double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0, s_w = 0.0, s_d2 = 0.0;
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int r = rw + 4 * q;
@@ -209,15 +220,21 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
         const int8_t gm = GM[off];
         if (gm != 0) {
           const double a = A[off];
-          const double p = P[off];
-          const double Cij = c_element(i == j, di[r], dj[c], a, lam);
-          at = trial_element(a, p, Cij, (double)gm, t);
           const double s = S[off];
+          if (gista) {
+            at = gista_element(a, s, W[off], lam, t);
+          } else {
+            const double p = P[off];
+            const double Cij = c_element(i == j, di[r], dj[c], a, lam);
+            at = trial_element(a, p, Cij, (double)gm, t);
+          }
           const double wgt = (i == j) ? 1.0 : 2.0;
-          s_tr += wgt * (s * (at - a));
+          const double d = at - a;
+          s_tr += wgt * (s * d);
           s_l1 += wgt * (fabs(at) - fabs(a));
           s_nnz += (at != 0.0) ? wgt : 0.0;
-          if (W) s_w += wgt * (W[off] * (at - a));
+          s_d2 += wgt * (d * d);
+          if (W) s_w += wgt * (W[off] * d);
         }
       } else {
         at = (i == j) ? 1.0 : 0.0;
@@ -240,35 +257,40 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
   const double b1 = block_sum(s_l1, sh);
   const double b2 = block_sum(s_nnz, sh);
   const double b3 = block_sum(s_w, sh);
+  const double b4 = block_sum(s_d2, sh);
   if (tid == 0) {
     double* pp = part + (int64_t)blockIdx.x * TRIAL_PARTS;
     pp[0] = b0;
     pp[1] = b1;
     pp[2] = b2;
     pp[3] = b3;
+    pp[4] = b4;
   }
 }
 
-// After the trial's Cholesky: dF = 2 sum log(L_ii / Lt_ii) + sum S(At-A) + lam sum(|At|-|A|).
+// After the trial's Cholesky: dF = 2 sum log(L_ii / Lt_ii) + sum S(At-A) + lam sum(|At|-|A|),
+// and the G-ISTA bound excess 2 sum log(L_ii / Lt_ii) + sum W(At-A) - ||At-A||^2 / (2t).
 __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, int nparts, const double* dL,
                                                            const double* dLt, const int* info, int64_t n,
-                                                           double lam, double* scal, PassBatch pb) {
+                                                           double lam, double* scal, PassBatch pb, double t) {
   __shared__ double sh[4];
   const int tid = threadIdx.x;
   const int pbi = blockIdx.x, prob = pbi / pb.div;  // trial slot, its problem
   if (pb.skip && pb.skip[pbi]) return;
   if (pb.lam) lam = pb.lam[prob];
+  if (pb.t) t = pb.t[pbi];
   part += (int64_t)pbi * nparts * TRIAL_PARTS;
   dL += prob * pb.sV;
   dLt += pbi * pb.sV;
   scal += (int64_t)pbi * SC_COUNT;
   const int inf = info[pbi];
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, tl = 0.0;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, tl = 0.0;
   for (int b = tid; b < nparts; b += 256) {
     t0 += part[(int64_t)b * TRIAL_PARTS + 0];
     t1 += part[(int64_t)b * TRIAL_PARTS + 1];
     t2 += part[(int64_t)b * TRIAL_PARTS + 2];
     t3 += part[(int64_t)b * TRIAL_PARTS + 3];
+    t4 += part[(int64_t)b * TRIAL_PARTS + 4];
   }
   if (inf == 0)
     for (int64_t i = tid; i < n; i += 256) tl += log(dL[i] / dLt[i]);
@@ -276,8 +298,12 @@ __global__ __launch_bounds__(256) void finish_trial_kernel(const double* part, i
   const double dl1 = block_sum(t1, sh);
   const double nnz = block_sum(t2, sh);
   const double dw = block_sum(t3, sh);
+  const double d2 = block_sum(t4, sh);
   const double dlog = 2.0 * block_sum(tl, sh);
   if (tid == 0) {
+    scal[SC_DW] = dw;
+    scal[SC_D2] = d2;
+    scal[SC_QB] = (dlog + dw) - d2 / (2.0 * t);
     scal[SC_DTR] = dtr;
     scal[SC_DL1] = dl1;
     scal[SC_DLOG] = dlog;
@@ -536,7 +562,7 @@ __global__ __launch_bounds__(256) void center_pad_kernel(const double* __restric
 // Accept trial slot j = accept[b] - 1 of every problem b with accept[b] != 0:
 // A_b <- At_j, L_b <- Lt_j (np x np each), dL_b <- dLt_j (np).
 __global__ void accept_kernel(const int* accept, double* A, const double* At, double* L, const double* Lt,
-                              double* dL, const double* dLt, int64_t nn, int64_t np) {
+                              double* dL, const double* dLt, int64_t nn, int64_t np, double* Aprev) {
   const int b = blockIdx.y;
   const int j = accept[b] - 1;  // trial slot to take, or none
   if (j < 0) return;
@@ -544,6 +570,7 @@ __global__ void accept_kernel(const int* accept, double* A, const double* At, do
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t dst = (int64_t)b * nn, src = (int64_t)j * nn;
   for (int64_t e = i0; e < nn; e += stride) {
+    if (Aprev) Aprev[dst + e] = A[dst + e];
     A[dst + e] = At[src + e];
     L[dst + e] = Lt[src + e];
   }
@@ -565,10 +592,11 @@ int center_pad(hipStream_t stream, const double* Y, int64_t m, int64_t n, const 
 }
 
 int accept_trials(hipStream_t stream, const int* accept, int count, double* A, const double* At, double* L,
-                  const double* Lt, double* dL, const double* dLt, int64_t np) {
+                  const double* Lt, double* dL, const double* dLt, int64_t np, double* Aprev) {
   const int64_t nn = np * np;
   const int blocks = (int)std::min<int64_t>((nn + 255) / 256, 4096);
-  hipLaunchKernelGGL(accept_kernel, dim3(blocks, count), dim3(256), 0, stream, accept, A, At, L, Lt, dL, dLt, nn, np);
+  hipLaunchKernelGGL(accept_kernel, dim3(blocks, count), dim3(256), 0, stream, accept, A, At, L, Lt, dL, dLt, nn, np,
+                     Aprev);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -630,29 +658,30 @@ int sum_log(hipStream_t stream, const double* d, int64_t n, double* out) {
 
 int pass_grad(hipStream_t stream, const double* S, const double* W, const double* A, const double* dL, int64_t n,
               int64_t nlog, int64_t np, double lam, double* Z, int8_t* GM, double* part, double* scal,
-              const PassBatch& pb, void* Zs, int64_t sZs) {
+              const PassBatch& pb, void* Zs, int64_t sZs, const double* Aprev) {
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
   hipLaunchKernelGGL(pass_grad_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, S, W, A, dL, n, np, lam, Z,
-                     static_cast<uint8_t*>(Zs), sZs, GM, part, T, pb);
+                     static_cast<uint8_t*>(Zs), sZs, GM, part, T, pb, Aprev);
   hipLaunchKernelGGL(finish_grad_kernel, dim3(pb.count), dim3(256), 0, stream, part, tiles, dL, nlog, lam, scal, pb);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int pass_trial(hipStream_t stream, const double* A, const double* P, const double* S, const int8_t* GM, int64_t n,
                int64_t np, double lam, double t, double* At, double* Lt, double* part, int* info_reset,
-               const PassBatch& pb, const double* W) {
+               const PassBatch& pb, const double* W, int gista) {
+  if (gista && !W) return -1;
   const int T = (int)(np / 64);
   const int tiles = T * (T + 1) / 2;
   hipLaunchKernelGGL(pass_trial_kernel, dim3(tiles, pb.count), dim3(256), 0, stream, A, P, S, GM, n, np, lam, t, At,
-                     Lt, part, info_reset, T, pb, W);
+                     Lt, part, info_reset, T, pb, W, gista);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 int finish_trial(hipStream_t stream, const double* part, int nparts, const double* dL, const double* dLt,
-                 const int* info, int64_t n, double lam, double* scal, const PassBatch& pb) {
+                 const int* info, int64_t n, double lam, double* scal, const PassBatch& pb, double t) {
   hipLaunchKernelGGL(finish_trial_kernel, dim3(pb.count), dim3(256), 0, stream, part, nparts, dL, dLt, info, n, lam,
-                     scal, pb);
+                     scal, pb, t);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

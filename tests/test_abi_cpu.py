@@ -98,7 +98,7 @@ def test_struct_layout_matches_c():
 #include <stddef.h>
 #include "glasso.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(glasso_options),
          offsetof(glasso_options, warm_start),
          offsetof(glasso_options, tile_policy), offsetof(glasso_options, graphs), offsetof(glasso_options, w_mixed),
          offsetof(glasso_options, ls_width), offsetof(glasso_options, dense_product),
@@ -107,7 +107,7 @@ int main(void) {
          offsetof(glasso_info, aza_sparse_products), offsetof(glasso_info, leaf_launches),
          offsetof(glasso_info, leaf_ms), offsetof(glasso_info, leaf_flops), offsetof(glasso_options, screen),
          offsetof(glasso_options, sigma), offsetof(glasso_info, components),
-         offsetof(glasso_info, largest_component));
+         offsetof(glasso_info, largest_component), offsetof(glasso_options, method));
   return 0;
 }'''
     with tempfile.TemporaryDirectory() as d:
@@ -123,5 +123,5 @@ int main(void) {
             g.GlassoInfo.aza_gemm_products.offset, g.GlassoInfo.aza_sparse_products.offset,
             g.GlassoInfo.leaf_launches.offset, g.GlassoInfo.leaf_ms.offset, g.GlassoInfo.leaf_flops.offset,
             g.GlassoOptions.screen.offset, g.GlassoOptions.sigma.offset, g.GlassoInfo.components.offset,
-            g.GlassoInfo.largest_component.offset]
+            g.GlassoInfo.largest_component.offset, g.GlassoOptions.method.offset]
     assert [int(x) for x in out] == want
