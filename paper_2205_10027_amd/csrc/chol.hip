@@ -117,6 +117,10 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
+    // a block Y_q^T that is zero in the whole wave gives X_q = 0 and changes no later
+    // block (banded factors: the rows below reach only the last columns of L11)
+    const bool live = __ballot((x[q][0] != 0.0) || (x[q][1] != 0.0) || (x[q][2] != 0.0) || (x[q][3] != 0.0)) != 0;
+    if (!live) continue;
     // X_q^T = inv(L_qq) Y_q^T
     const int r0 = (q < 7) ? 16 * q : 0, c0 = (q < 7) ? 112 : 96;
     v4d xq = {0.0, 0.0, 0.0, 0.0};

@@ -145,24 +145,33 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
     grouped_tile(L, p.tiles_m, p.tiles_n, ti, tj);
   }
   const int m0 = ti * T, n0 = tj * T;
+  // 128-wide K chunks the tile multiplies: all of them, or with a zero-block map
+  // those panels of the K range that have a nonzero block in both the tile's A rows
+  // and its B rows (the others add exact zeros).  No chunk: C stays as it is.
+  uint64_t kmask = ~0ull;
   if (p.nz) {
-    // the tile adds A B^T only if some panel of its K range has a nonzero block in
-    // both its A rows and its B rows; otherwise C stays as it is
-    // one thread per panel of the K range, all loads independent
-    const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
-    const int ca = (p.nz_row0 + m0) >> 6, cb = (p.nz_col0 + n0) >> 6;
-    int any = 0;
-    for (int s = (p.nz_k0 >> 7) + tid; s < (p.nz_k0 + p.K) >> 7; s += 256) {
-      const uint8_t* fs = f + (int64_t)s * p.nz_chunks;
-      int a = 0, b = 0;
+    __shared__ unsigned long long kmask_sh;
+    if (wave == 0) {
+      // lane c looks at panel c of the K range (at most 64 panels)
+      const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
+      const int ca = (p.nz_row0 + m0) >> 6, cb = (p.nz_col0 + n0) >> 6;
+      int on = 0;
+      if (lane < (p.K >> 7)) {
+        const uint8_t* fs = f + (int64_t)((p.nz_k0 >> 7) + lane) * p.nz_chunks;
+        int a = 0, b = 0;
 #pragma unroll
-      for (int c = 0; c < T / 64; ++c) {
-        a |= fs[ca + c];
-        b |= fs[cb + c];
+        for (int c = 0; c < T / 64; ++c) {
+          a |= fs[ca + c];
+          b |= fs[cb + c];
+        }
+        on = a && b;
       }
-      any |= a && b;
+      const unsigned long long bal = __ballot(on);
+      if (lane == 0) kmask_sh = bal;
     }
-    if (!__syncthreads_or(any)) return;
+    __syncthreads();
+    kmask = kmask_sh;
+    if (!kmask) return;
   }
 
   const double* A = p.A + (int64_t)blockIdx.y * p.sA + (int64_t)blockIdx.z * p.zA;
@@ -174,6 +183,17 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
   if (p.a_tri == 2) kbeg = max(kbeg, m0);
   if (p.b_tri == 1) kbeg = max(kbeg, n0);
   if (p.b_tri == 2) kend = min(kend, n0 + T);
+  kbeg = max(kbeg, __builtin_ctzll(kmask) << 7);
+  // the slice after kt: the next one of its chunk, else the first of the next chunk
+  // in kmask (kend when there is none); without a map simply the next one (K may
+  // exceed the 64 chunks a mask holds)
+  auto next_k = [&](int kt) -> int {
+    const int nk = kt + BK;
+    if (!p.nz || (nk & 127)) return nk;
+    const int c = kt >> 7;
+    const uint64_t later = (c >= 63) ? 0ull : (kmask & (~0ull << (c + 1)));
+    return later ? (int)(__builtin_ctzll(later) << 7) : kend;
+  };
   // op(B) is indexed [k][n]: its "lower" (zero for k < n) is the staged row's k < row
   const int btri = p.b_tri == 1 ? 2 : (p.b_tri == 2 ? 1 : 0);
 
@@ -183,22 +203,41 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
 #pragma unroll
     for (int j = 0; j < NBLK; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
+  // With a zero-block map (sparse factors) a BK slice whose op(A) or op(B) part is
+  // all zero adds exact zeros: its MFMAs are skipped, decided at the barrier that
+  // publishes the slice.  Dense launches use plain barriers.
+  const bool sparse = p.nz != nullptr;
+  auto nonzero = [&](const double (&r)[R]) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < R; ++i) any = any || r[i] != 0.0;
+    return any;
+  };
   if (kbeg < kend) {
     double ra[R], rb[R];
     load_slice<TA, T>(A, p.lda, m0, kbeg, tid, p.a_tri, ra);
     load_slice<TB, T>(B, p.ldb, n0, kbeg, tid, btri, rb);
     store_slice<TA, T>(As[0], tid, ra);
     store_slice<TB, T>(Bs[0], tid, rb);
-    __syncthreads();
+    bool live = true;  // the slice in As[cur], Bs[cur] has a nonzero product
+    if (sparse) {
+      const bool za = __syncthreads_or(nonzero(ra));
+      const bool zb = __syncthreads_or(nonzero(rb));
+      live = za && zb;
+    } else {
+      __syncthreads();
+    }
     int cur = 0;
-    for (int kt = kbeg; kt < kend; kt += BK) {
-      const bool more = kt + BK < kend;
+    for (int kt = kbeg; kt < kend;) {
+      const int nk = next_k(kt);
+      const bool more = nk < kend;
       if (more) {
-        load_slice<TA, T>(A, p.lda, m0, kt + BK, tid, p.a_tri, ra);
-        load_slice<TB, T>(B, p.ldb, n0, kt + BK, tid, btri, rb);
+        load_slice<TA, T>(A, p.lda, m0, nk, tid, p.a_tri, ra);
+        load_slice<TB, T>(B, p.ldb, n0, nk, tid, btri, rb);
       }
 #pragma unroll
       for (int kk = 0; kk < BK / 4; ++kk) {
+        if (!live) break;
         double af[NBLK], bf[NBLK];
         const int kc = kk * 4 + (lane >> 4);
 #pragma unroll
@@ -215,8 +254,15 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
         store_slice<TA, T>(As[cur ^ 1], tid, ra);
         store_slice<TB, T>(Bs[cur ^ 1], tid, rb);
       }
-      __syncthreads();
+      if (sparse) {
+        const bool za = __syncthreads_or(more && nonzero(ra));
+        const bool zb = __syncthreads_or(more && nonzero(rb));
+        live = za && zb;
+      } else {
+        __syncthreads();
+      }
       cur ^= 1;
+      kt = nk;
     }
   }
 
@@ -299,7 +345,8 @@ int gemm_f64(hipStream_t stream, int ta, int tb, int M, int N, int K, double alp
   p.nz_row0 = zb.nz_row0;
   p.nz_col0 = zb.nz_col0;
   p.nz_k0 = zb.nz_k0;
-  if (zb.nz && (ta || tb || K % 128 || zb.nz_k0 % 128 || zb.nz_row0 % 64 || zb.nz_col0 % 64)) return -1;
+  if (zb.nz && (ta || tb || K % 128 || K > 64 * 128 || zb.nz_k0 % 128 || zb.nz_row0 % 64 || zb.nz_col0 % 64))
+    return -1;
   // 128x128 tiles unless the launch has too few of them to fill the chip; both
   // tile edges accumulate every output in the same k order (bitwise equal results).
   // An in-place product (C aliases A, N = 128) keeps 128-wide tiles: one workgroup

@@ -44,7 +44,7 @@ def test_precond_product_fp64(solver, n):
     assert np.array_equal(P, P.T)
 
 
-@pytest.mark.parametrize("n", [5, 300, 1024])
+@pytest.mark.parametrize("n", [5, 300, 1024, 8320])
 def test_precond_product_fp64_diagonal_A(solver, n):
     """For a diagonal A every entry of the FP64 GEMM pair is one rounded product per
     GEMM, (A_ii Z_ij) A_jj, the other terms being exact zeros: the elementwise D Z D
@@ -256,3 +256,61 @@ def test_trial_point_bit_exact(solver, n, t):
     dl1 = float(np.sum(np.abs(ref) - np.abs(A)))
     assert abs(sums["dtr"] - dtr) <= 1e-12 * max(1.0, np.sum(np.abs(S * (ref - A))))
     assert abs(sums["dl1"] - dl1) <= 1e-12 * max(1.0, np.sum(np.abs(ref)) + np.sum(np.abs(A)))
+
+
+# ------------------------------------------------------------------ G-ISTA trial point
+@pytest.mark.parametrize("n", [1, 5, 64, 130, 300])
+@pytest.mark.parametrize("t", [1.0, 0.37, 1e-3])
+def test_gista_trial_point_bit_exact(solver, n, t):
+    """The proximal-gradient step ST(A - t (S - W), t lam) (eq. proximal_gen, H = I):
+    the same IEEE operations as the oracle -> bit-exact on the free set and exact
+    zeros off it (there |g| <= lam, so the step is exactly zero); sums in another
+    order -> relative 1e-12."""
+    lam = 0.2
+    rng = np.random.default_rng(n + 11)
+    A = sparse_sym(n, n + 4, density=0.2)
+    S = sym(rng.standard_normal((n, n)))
+    W = sym(S - 0.4 * rng.standard_normal((n, n)))
+    # planted ties |g| = lam off the support
+    g = oracle.gradient(S, W)
+    if n >= 5:
+        W[3, 1] = W[1, 3] = S[3, 1] - lam
+        W[4, 0] = W[0, 4] = S[4, 0] + lam
+        A[3, 1] = A[1, 3] = A[4, 0] = A[0, 4] = 0.0
+        g = oracle.gradient(S, W)
+    M = oracle.free_set_mask(A, g, lam)
+    G = oracle.sign_guess(A, g)
+    GM = np.where(M, G, 0.0).astype(np.int8)
+    At, sums = solver.gista_trial_point(to_dev(A), to_dev(S), to_dev(W), to_dev(GM, torch.int8), lam, t)
+    At = to_host(At)
+    ref = oracle.gista_trial_point(A, g, lam, t)
+    assert np.array_equal(At, ref)
+    d = ref - A
+    for got, want, scale in ((sums[0], np.sum(S * d), np.sum(np.abs(S * d))),
+                             (sums[1], np.sum(np.abs(ref) - np.abs(A)), np.sum(np.abs(ref)) + np.sum(np.abs(A))),
+                             (sums[2], np.sum(W * d), np.sum(np.abs(W * d))),
+                             (sums[3], np.sum(d * d), np.sum(d * d))):
+        assert abs(got - want) <= 1e-12 * max(1.0, scale)
+
+
+def test_inverse_fp64_beyond_64_k_chunks(solver):
+    """n = 8320: the products of the FP64 triangular inverse and LAUUM run K ranges
+    longer than 64 chunks of 128; W A = I on 64 sampled rows (banded SPD A, whose
+    inverse is dense), within the inverse's bound."""
+    n = 8320
+    rng = np.random.default_rng(12)
+    A = np.zeros((n, n))
+    idx = np.arange(n)
+    A[idx, idx] = 2.5
+    off = -0.5 + 0.2 * rng.random(n - 1)
+    A[idx[1:], idx[:-1]] = off
+    A[idx[:-1], idx[1:]] = off
+    W = to_host(solver.inverse(to_dev(A)))
+    rows = rng.choice(n, 64, replace=False)
+    R = W[rows] @ A
+    E = np.zeros_like(R)
+    E[np.arange(64), rows] = 1.0
+    # residual bound 4 n eps cond(A) max|W| |A|_inf; cond(A) <= 3.5 / 1.5 (Gershgorin)
+    bound = 4 * n * EPS * (3.5 / 1.5) * np.max(np.abs(W)) * 3.5
+    assert np.max(np.abs(R - E)) <= bound, (np.max(np.abs(R - E)), bound)
+    assert np.array_equal(W, W.T)
