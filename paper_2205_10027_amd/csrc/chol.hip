@@ -19,7 +19,8 @@ namespace {
 constexpr int NB = 128;        // leaf block (= GEMM tile)
 constexpr int LDL = NB + 1;    // LDS row stride of the leaf
 constexpr int OUTER = 1024;    // outer panel width of the blocked Cholesky
-constexpr int MID = 512;       // middle panel width: K = 128 updates stay inside it
+constexpr int MID = 512;       // middle panel width: its blocks update each other first
+constexpr int LEFT_MIN_N = 2048;  // left-looking leaf steps above this padded size
 
 // One step of the blocked Cholesky: the 128-column block whose diagonal block is at
 // A, with `rest` rows of the panel below it (a multiple of 64).
@@ -39,8 +40,17 @@ constexpr int MID = 512;       // middle panel width: K = 128 updates stay insid
 // v_mfma_f64_16x16x4f64 layouts the output block X_q^T (element (i, j) in lane
 // j + 16 (i%4), register i/4) is exactly the B operand of the k-steps over its
 // 16 rows, so every X_q stays in registers until the store.
-__global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda, int k0, int rest, double* dL,
-                                                         int* info, FactorBatch fb) {
+//
+// Left-looking inside a middle panel: the block column first receives the products
+// of the kl panels to its left in the same middle panel (columns k0 - 128 kl ..
+// k0), A_kk -= L_kp L_kp^T and, in each solving workgroup, R -= L_rp L_kp^T for its
+// rows, panel by panel in 64-column halves staged through LDS.  Products of 16x16
+// blocks that are zero are skipped, and with a zero-block map so are whole panels
+// whose block-column rows (or the workgroup's rows) are zero: for banded factors
+// only the adjacent panel's corner remains.  (Earlier middle panels reach the block
+// through the right-looking updates of potrf_lower.)
+__global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda, int k0, int rest, int kl,
+                                                         double* dL, int* info, FactorBatch fb) {
   // problem blockIdx.y of the batch
   A += blockIdx.y * fb.sA;
   dL += blockIdx.y * fb.sdL;
@@ -73,7 +83,102 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
       for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
   }
 
-  const int fail = lds_potrf<NB>(a, tid);
+  const int li = lane & 15, lk = lane >> 4;
+  const uint8_t* nzf = fb.nz ? fb.nz + blockIdx.y * fb.snz : nullptr;
+  const int own_chunk = (k0 + NB) / 64 + (int)blockIdx.x - 1;
+  // nonzero 16x16 blocks (b, q) of a staged 128 x 64 half panel, bit 4b + q; two
+  // masks used in turn, the next one cleared while the current one is in use
+  __shared__ unsigned int dmask[2];
+  auto left_updates = [&](v4d(&acc)[9], const int(&bi)[9], const int(&bj)[9]) {
+    int phase = 0;
+    for (int kp = kl; kp >= 1; --kp) {
+      const int P = k0 / NB - kp;  // global panel index
+      // map bits of panel P: bit h = a nonzero in columns 64h .. 64h + 63
+      int m0 = 3, m1 = 3, mr = solver ? 3 : 0;
+      if (nzf) {
+        const uint8_t* f = nzf + (int64_t)P * fb.nz_chunks;
+        m0 = f[k0 / 64];
+        m1 = f[k0 / 64 + 1];
+        if (solver) mr = f[own_chunk];
+      }
+      if (!(m0 | m1)) continue;  // L_kp = 0: nothing to subtract
+      const double* D = A - NB * kp;  // L_kp: rows k0.., columns of panel P
+      const double* Rr = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + li) * lda - NB * kp;
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        const bool d0 = (m0 >> h) & 1, d1 = (m1 >> h) & 1;
+        if (!(d0 || d1)) continue;
+        const bool rows_h = (mr >> h) & 1;
+        unsigned int* const mcur = &dmask[phase & 1];
+        if (tid == 0) dmask[(phase + 1) & 1] = 0u;
+        // stage L_kp[:, 64h .. 64h + 63] (a zero 64-row chunk is written without
+        // loading it) and collect the nonzero 16x16 blocks: thread t holds columns
+        // 2t mod 64 and 2t mod 64 + 1 of rows t/32 + 8i
+        unsigned int bits = 0u;
+        const int c = (2 * tid) & 63, r0 = tid >> 5;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int r = r0 + 8 * i;
+          double2 v = make_double2(0.0, 0.0);
+          if (i < 8 ? d0 : d1) v = *reinterpret_cast<const double2*>(D + (int64_t)r * lda + 64 * h + c);
+          a[r][c] = v.x;
+          a[r][c + 1] = v.y;
+          if (v.x != 0.0 || v.y != 0.0) bits |= 1u << (4 * (r >> 4) + (c >> 4));
+        }
+        if (bits) atomicOr(mcur, bits);
+        // this wave's 16 rows of L_rp, in the B layout: rp[q][s] = row li, column 16q + 4s + lk
+        double rp[4][4];
+        if (rows_h) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) rp[q][s2] = Rr[64 * h + 16 * q + 4 * s2 + lk];
+        }
+        __syncthreads();
+        const unsigned int dm = *mcur;
+        // A_kk -= L_kp L_kp^T on this wave's blocks of the lower triangle, the nine
+        // accumulators in turn between dependent MFMAs
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bool on[9];
+#pragma unroll
+          for (int sl = 0; sl < 9; ++sl)
+            on[sl] = bj[sl] >= 0 && ((dm >> (4 * bi[sl] + q)) & 1u) && ((dm >> (4 * bj[sl] + q)) & 1u);
+#pragma unroll
+          for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+            for (int sl = 0; sl < 9; ++sl)
+              if (on[sl])
+                acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * bi[sl] + li][16 * q + 4 * s2 + lk],
+                                                             a[16 * bj[sl] + li][16 * q + 4 * s2 + lk], acc[sl], 0,
+                                                             0, 0);
+        }
+        // R^T -= L_kp L_rp^T: block b of Y^T from block (b, q) of L_kp and slice q of rp
+        if (rows_h) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool rq = __ballot((rp[q][0] != 0.0) || (rp[q][1] != 0.0) || (rp[q][2] != 0.0) ||
+                                     (rp[q][3] != 0.0)) != 0;
+            if (!rq) continue;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+              for (int b = 0; b < 8; ++b)
+                if ((dm >> (4 * b + q)) & 1u)
+                  x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + li][16 * q + 4 * s2 + lk], rp[q][s2],
+                                                              x[b], 0, 0, 0);
+          }
+        }
+        ++phase;
+        __syncthreads();  // before the next half overwrites the staging
+      }
+    }
+  };
+  if (tid == 0) {
+    dmask[0] = 0u;
+    dmask[1] = 0u;
+  }
+  const int fail = kl > 0 ? lds_potrf<NB>(a, tid, left_updates) : lds_potrf<NB>(a, tid);
   if (fail >= 0) {
     if (blockIdx.x == 0 && tid == 0) *info = k0 + fail + 1;
     return;
@@ -114,7 +219,6 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   }
   __syncthreads();
 
-  const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     // a block Y_q^T that is zero in the whole wave gives X_q = 0 and changes no later
@@ -148,15 +252,23 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   for (int r = 0; r < 16; ++r)
     *reinterpret_cast<double2*>(Rw + (int64_t)r * lda) = make_double2(a[16 * wave + r][2 * lane], a[16 * wave + r][2 * lane + 1]);
   if (fb.nz) {
-    // whether these 64 solved rows hold a nonzero (the updates skip zero blocks)
-    bool nzl = false;
+    // which halves of these 64 solved rows hold a nonzero (the updates skip zero
+    // blocks): bit 0 columns 0..63, bit 1 columns 64..127
+    bool nz0 = false, nz1 = false;
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) nzl = nzl || x[b][s] != 0.0;
-    nzl = __syncthreads_or(nzl);
+      for (int s = 0; s < 4; ++s) {
+        if (b < 4)
+          nz0 = nz0 || x[b][s] != 0.0;
+        else
+          nz1 = nz1 || x[b][s] != 0.0;
+      }
+    nz0 = __syncthreads_or(nz0);
+    nz1 = __syncthreads_or(nz1);
     if (tid == 0)
-      fb.nz[blockIdx.y * fb.snz + (int64_t)(k0 / NB) * fb.nz_chunks + (k0 + NB) / 64 + (int)blockIdx.x - 1] = nzl ? 1 : 0;
+      fb.nz[blockIdx.y * fb.snz + (int64_t)(k0 / NB) * fb.nz_chunks + (k0 + NB) / 64 + (int)blockIdx.x - 1] =
+          (uint8_t)((nz0 ? 1 : 0) | (nz1 ? 2 : 0));
   }
 }
 
@@ -240,6 +352,11 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
     z.nz_k0 = c;
     return z;
   };
+  // Inside a middle panel the blocks update each other left-looking, in the leaf
+  // steps, above LEFT_MIN_N: there a leaf launch has enough workgroups (one per 64
+  // rows below the block) that its own K <= 384 update costs less than a separate
+  // K = 128 launch per step.  Below it the middle panel is updated right-looking.
+  const bool left_looking = n > LEFT_MIN_N;
   int rc = 0;
   for (int K0 = 0; K0 < n && rc == 0; K0 += OUTER) {
     const int K1 = min(K0 + OUTER, n);
@@ -251,8 +368,10 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
         const int rest = n - k - NB;
         const bool timed = timer && timer->used + 2 <= timer->cap && k < timer->n;
         if (timed && hipEventRecord(timer->ev[timer->used], stream) != hipSuccess) return -2;
+        // panels to the left in this middle panel, applied inside the leaf step
+        const int kl = left_looking ? (k - M0) / NB : 0;
         hipLaunchKernelGGL(leaf_potrf_kernel, dim3(1 + rest / 64, fb.count), dim3(256), 0, stream, Akk, lda, k,
-                           rest, dL + k, info, fb);
+                           rest, kl, dL + k, info, fb);
         if (hipGetLastError() != hipSuccess) return -2;
         if (timed) {
           if (hipEventRecord(timer->ev[timer->used + 1], stream) != hipSuccess) return -2;
@@ -260,10 +379,13 @@ int potrf_lower(hipStream_t stream, double* A, int64_t lda, int n, double* dL, d
           const int64_t left = timer->n - k;
           const double nb = (double)(left < NB ? left : NB);
           const double below = (double)(left > NB ? left - NB : 0);
-          timer->flops += timer->active * (nb * nb * nb / 3.0 + below * nb * nb);
+          // the block's left-looking update (K = 128 kl: the rows below, and the lower
+          // half of the diagonal block), its factor and the panel solve
+          const double kk = (double)(NB * kl);
+          timer->flops += timer->active * (nb * nb * nb / 3.0 + below * nb * nb + 2.0 * below * nb * kk + nb * nb * kk);
         }
-        if (k + NB < M1) {
-          // update of the remaining columns of the middle panel (K = 128)
+        if (!left_looking && k + NB < M1) {
+          // right-looking: update of the remaining columns of the middle panel (K = 128)
           const double* Pk = A + (int64_t)(k + NB) * lda + k;
           rc = gemm_f64(stream, 0, 0, rest, M1 - k - NB, NB, -1.0, Pk, lda, Pk, lda, 1.0,
                         A + (int64_t)(k + NB) * lda + (k + NB), lda, 0, 0, 0, info, 1, 0, 0, 0, 0, rows(k + NB, k));

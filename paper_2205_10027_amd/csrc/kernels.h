@@ -16,7 +16,8 @@ struct ZBatch {
   int64_t sA = 0, sB = 0, sC = 0;
   // Optional zero-block skipping for the Cholesky updates C -= A B^T, where A and
   // B are rows of the factor's finished panels: nz[z * snz + s * nz_chunks + c]
-  // says whether rows 64c..64c+63 of 128-column panel s hold a nonzero.  A tile
+  // says whether rows 64c..64c+63 of 128-column panel s hold a nonzero (bit 0 in
+  // the panel's columns 0..63, bit 1 in 64..127; nonzero = either).  A tile
   // whose operand rows (global rows nz_row0 + m0.., nz_col0 + n0..) meet a zero
   // block in every panel of its K range (global columns nz_k0..) adds nothing and
   // leaves C untouched.  nz == nullptr: no skipping.

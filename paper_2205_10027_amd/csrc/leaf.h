@@ -148,10 +148,20 @@ __device__ void lds_trtri(double (*a)[NB + 1], int tid) {
 // The broadcasts grow with the square of the panel width, the update rounds only
 // linearly with the number of panels, which is why the panels are narrow.
 // Elements above the diagonal are never read as data.
+// `pre` (optional) runs after the blocks are in the accumulators and before the
+// first panel, with the LDS block free for its own staging: it may subtract further
+// products from the accumulators (the leaf step's left-looking updates); block
+// column 0 then goes back to LDS from the accumulators like every later one.
 constexpr int PF = 16;
 
-template <int NB>
-__device__ int lds_potrf(double (*a)[NB + 1], int tid) {
+struct NoPre {
+  template <int SL>
+  __device__ void operator()(v4d (&)[SL], const int (&)[SL], const int (&)[SL]) const {}
+};
+
+template <int NB, typename Pre = NoPre>
+__device__ int lds_potrf(double (*a)[NB + 1], int tid, Pre pre = Pre()) {
+  constexpr bool kPre = !__is_same(Pre, NoPre);
   constexpr int NBB = NB / 16;               // 16x16 blocks per edge
   constexpr int NBLK = NBB * (NBB + 1) / 2;  // blocks of the lower triangle
   constexpr int SLOTS = (NBLK + 3) / 4;      // blocks per wave
@@ -175,11 +185,15 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid) {
       for (int r = 0; r < 4; ++r) acc[s][r] = a[16 * bi[s] + 4 * r + lk][16 * bj[s] + li];
     }
   }
+  if (kPre) {
+    __syncthreads();  // every wave has its blocks: the LDS block is free
+    pre(acc, bi, bj);
+  }
   int fail = -1;
 #pragma unroll 1
   for (int p = 0; p < NBB; ++p) {
     const int c0 = PF * p;
-    if (p > 0) {
+    if (p > 0 || kPre) {
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s)
         if (bj[s] == p) for_block(acc[s], lane, [&](int r, int c, double v) { a[16 * bi[s] + r][c0 + c] = v; });

@@ -124,6 +124,23 @@ def test_cholesky(solver, n):
     assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
 
 
+@pytest.mark.parametrize("n", [2300, 3000])
+def test_cholesky_left_looking_dense(solver, n):
+    """Dense SPD above a padded size of 2048: the blocks of each 512-wide middle
+    panel update each other inside the leaf steps (left-looking, K up to 384);
+    backward error bound as for test_cholesky."""
+    A = random_spd(n, n)
+    L, info, logdet = solver.cholesky(to_dev(A))
+    L = to_host(L)
+    assert info == 0
+    assert np.all(np.triu(L, 1) == 0)
+    back = np.abs(L @ L.T - A)
+    bound = 4 * n * EPS * (np.abs(L) @ np.abs(L.T)) + 1e-300
+    assert np.all(back <= bound), np.max(back / bound)
+    sign, ld = np.linalg.slogdet(A)
+    assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
+
+
 def banded_spd(n, seed, band):
     rng = np.random.default_rng(seed)
     A = np.zeros((n, n))
@@ -164,6 +181,28 @@ def test_cholesky_zero_blocks(solver, n, kind):
     assert np.max(np.abs(L - ref)) <= 1e-12 * np.max(np.abs(ref))
     if kind.startswith("band"):
         assert np.all(np.tril(L, -int(kind[4:]) - 1) == 0)  # no fill outside the band
+    sign, ld = np.linalg.slogdet(A)
+    assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
+
+
+@pytest.mark.parametrize("n", [300, 520, 1100, 2300, 4500])
+def test_cholesky_scattered_sparse(solver, n):
+    """A scattered sparse SPD matrix (random off-diagonal pattern, diagonally
+    dominant, like the solver's iterates): the update tiles and, above a padded size
+    of 2048 (n = 2300, 4500), the leaf steps' left-looking updates skip the 16x16
+    blocks that are zero and keep the others, wherever in a block the nonzeros sit.
+    Factor against numpy."""
+    rng = np.random.default_rng(n + 3)
+    A = np.zeros((n, n))
+    i, j = rng.integers(0, n, 6 * n), rng.integers(0, n, 6 * n)
+    A[i, j] = rng.uniform(-1.0, 1.0, 6 * n)
+    A = sym(np.tril(A, -1))
+    A[np.arange(n), np.arange(n)] = np.abs(A).sum(axis=1) + 0.1
+    L, info, logdet = solver.cholesky(to_dev(A))
+    L = to_host(L)
+    assert info == 0
+    ref = np.linalg.cholesky(A)
+    assert np.max(np.abs(L - ref)) <= 1e-12 * np.max(np.abs(ref))
     sign, ld = np.linalg.slogdet(A)
     assert abs(logdet - ld) <= 1e-12 * max(1.0, abs(ld)) * n
 
