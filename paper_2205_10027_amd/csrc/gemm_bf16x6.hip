@@ -63,25 +63,40 @@ __device__ __forceinline__ void store6(uint8_t* S, int tid, const v4u (&r)[6]) {
 
 // acc += A[m0.., kbeg..kend) B[n0.., kbeg..kend)^T for the 4 wave64 of a 128x128
 // tile (wave (wm, wn) owns rows wm*64.., columns wn*64..): 32-k stages through one
-// LDS buffer per operand, the next stage prefetched in registers.
+// LDS buffer per operand, the next stage prefetched in registers.  kmask (when
+// `masked`): the 128-wide K chunks to multiply (bit c: k in [128c, 128c + 128));
+// the others contribute exact zeros and are not read.
 __device__ __forceinline__ void tile_product(const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb, int m0,
                                              int n0, int kbeg, int kend, uint8_t* As, uint8_t* Bs, v4f (&acc)[4][4],
-                                             int tid) {
+                                             int tid, bool masked = false, uint64_t kmask = ~0ull) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  if (masked) {
+    if (!kmask) return;
+    kbeg = max(kbeg, (int)(__builtin_ctzll(kmask) << 7));
+  }
   if (kbeg >= kend) return;
+  // the stage after kt: the next one, or with a mask the first of the next chunk in it
+  auto next_k = [&](int kt) -> int {
+    const int nk = kt + BK6;
+    if (!masked || (nk & 127)) return nk;
+    const int c = kt >> 7;
+    const uint64_t later = (c >= 63) ? 0ull : (kmask & (~0ull << (c + 1)));
+    return later ? (int)(__builtin_ctzll(later) << 7) : kend;
+  };
   v4u ra[6], rb[6];
   load6(A, lda, m0, kbeg, tid, ra);
   load6(B, ldb, n0, kbeg, tid, rb);
   // lane's fragment: row (lane & 15) of a 16-row block, run (lane >> 4) of the stage
   const int frag = (lane & 15) * ROW6 + (lane >> 4) * RUN6;
-  for (int kt = kbeg; kt < kend; kt += BK6) {
+  for (int kt = kbeg; kt < kend;) {
     store6(As, tid, ra);
     store6(Bs, tid, rb);
     __syncthreads();
-    if (kt + BK6 < kend) {
-      load6(A, lda, m0, kt + BK6, tid, ra);
-      load6(B, ldb, n0, kt + BK6, tid, rb);
+    const int nk = next_k(kt);
+    if (nk < kend) {
+      load6(A, lda, m0, nk, tid, ra);
+      load6(B, ldb, n0, nk, tid, rb);
     }
     v8bf a1[4], a2[4], a3[4];
 #pragma unroll
@@ -111,6 +126,7 @@ __device__ __forceinline__ void tile_product(const uint8_t* A, int64_t lda, cons
       }
     }
     __syncthreads();
+    kt = nk;
   }
 }
 
@@ -157,24 +173,23 @@ __device__ __forceinline__ void split3(float x, uint32_t& h1, uint32_t& h2, uint
   h2 = bf16_bits(r1);
   h3 = bf16_bits(r1 - bf16_value(h2));  // exact
 }
-// element (row, col) of a split matrix with ld elements per row
-__device__ __forceinline__ void store_split(uint8_t* M, int64_t ld, int64_t row, int col, float x) {
-  uint32_t h1, h2, h3;
-  split3(x, h1, h2, h3);
-  uint16_t* q = reinterpret_cast<uint16_t*>(M + row * ld * 6 + (col >> 3) * RUN6 + (col & 7) * 2);
-  q[0] = (uint16_t)h1;
-  q[8] = (uint16_t)h2;
-  q[16] = (uint16_t)h3;
-}
-// elements (row, col0 .. col0 + 3), col0 a multiple of 4: one 8-byte store per part
-__device__ __forceinline__ void store_split4(uint8_t* M, int64_t ld, int64_t row, int col0, v4f x) {
-  uint32_t h1[4], h2[4], h3[4];
+// a run of 8 consecutive elements (row, col0 .. col0 + 7), col0 a multiple of 8:
+// three 16-byte stores
+__device__ __forceinline__ void store_run(uint8_t* M, int64_t ld, int64_t row, int64_t col0, const float (&x)[8]) {
+  uint32_t p1[4], p2[4], p3[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) split3(x[e], h1[e], h2[e], h3[e]);
-  uint8_t* q = M + row * ld * 6 + (col0 >> 3) * RUN6 + (col0 & 7) * 2;
-  *reinterpret_cast<uint2*>(q) = make_uint2(h1[0] | (h1[1] << 16), h1[2] | (h1[3] << 16));
-  *reinterpret_cast<uint2*>(q + 16) = make_uint2(h2[0] | (h2[1] << 16), h2[2] | (h2[3] << 16));
-  *reinterpret_cast<uint2*>(q + 32) = make_uint2(h3[0] | (h3[1] << 16), h3[2] | (h3[3] << 16));
+  for (int q = 0; q < 4; ++q) {
+    uint32_t a1, a2, a3, b1, b2, b3;
+    split3(x[2 * q], a1, a2, a3);
+    split3(x[2 * q + 1], b1, b2, b3);
+    p1[q] = a1 | (b1 << 16);
+    p2[q] = a2 | (b2 << 16);
+    p3[q] = a3 | (b3 << 16);
+  }
+  v4u* d = reinterpret_cast<v4u*>(M + (row * ld + col0) * 6);
+  d[0] = (v4u){p1[0], p1[1], p1[2], p1[3]};
+  d[1] = (v4u){p2[0], p2[1], p2[2], p2[3]};
+  d[2] = (v4u){p3[0], p3[1], p3[2], p3[3]};
 }
 
 // ---- triangular inverse on the split copies (the mixed-W iterations)
@@ -210,13 +225,18 @@ struct TriBf6Params {
   int nz_chunks, nz_row0, nz_col0, nz_gstep, nz_w;
 };
 
+// rows of the output tile staged as FP32 in LDS for whole-run stores (64 rows at a time)
+constexpr int STG_LD = T6 + 4;
+static_assert(64 * STG_LD * 4 <= 2 * T6 * ROW6, "staging fits in the operand buffers");
+
 template <int KCLIP>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p) {
   if (p.skip && p.skip[blockIdx.z]) return;
   const uint8_t* A = p.A + blockIdx.y * p.sA + blockIdx.z * p.zA;
   const uint8_t* B = p.B + blockIdx.y * p.sB + blockIdx.z * p.zB;
-  __shared__ __attribute__((aligned(16))) uint8_t As[T6 * ROW6];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[T6 * ROW6];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * T6 * ROW6];
+  uint8_t* const As = lds;
+  uint8_t* const Bs = lds + T6 * ROW6;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   // longest K range first: KCLIP 1 shortens with the column tile, 2 lengthens with the row tile
@@ -233,13 +253,32 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p)
   const int m0 = ti * T6, n0 = tj * T6;
   const int kbeg = (KCLIP == 1) ? n0 : 0;
   int kend = (KCLIP == 2) ? min(p.K, m0 + T6) : p.K;
+  bool masked = false;
+  uint64_t kmask = ~0ull;
   if (p.nz) {
     const uint8_t* f = p.nz + (int64_t)blockIdx.z * p.snz;
     const int r0 = p.nz_row0 + (int)blockIdx.y * p.nz_gstep;  // global row of T21's row 0
     const int c0 = p.nz_col0 + (int)blockIdx.y * p.nz_gstep;  // global column of T21's column 0
-    // every thread reads its share of the (panel, 64-row block) entries, all loads
-    // independent, then one workgroup-wide reduction
-    if (KCLIP == 1) {
+    if (KCLIP == 1 && (p.K >> 7) <= 64) {
+      // K chunk c (128 columns of T21, panel (c0 >> 7) + c of L) is multiplied only
+      // if the tile's 128 rows of T21 have a nonzero block in it: lane c of wave 0
+      // looks it up
+      __shared__ unsigned long long kmask_sh;
+      if (wave == 0) {
+        int on = 0;
+        if (lane < (p.K >> 7) && 128 * lane + 128 > kbeg && 128 * lane < kend) {
+          const uint8_t* fs = f + (int64_t)((c0 >> 7) + lane) * p.nz_chunks + ((r0 + m0) >> 6);
+          on = fs[0] | fs[1];
+        }
+        const unsigned long long bal = __ballot(on);
+        if (lane == 0) kmask_sh = bal;
+      }
+      __syncthreads();
+      kmask = kmask_sh;
+      masked = true;
+    } else if (KCLIP == 1) {
+      // every thread reads its share of the (panel, 64-row block) entries, all loads
+      // independent, then one workgroup-wide reduction
       const int q0 = (c0 + kbeg) >> 7, nq = ((c0 + kend - 1) >> 7) - q0 + 1;
       int any = 0;
       for (int e = tid; e < 2 * nq; e += 256)
@@ -266,52 +305,67 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p)
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
-  tile_product(A, p.lda, B, p.ldb, m0, n0, kbeg, kend, As, Bs, acc, tid);
+  tile_product(A, p.lda, B, p.ldb, m0, n0, kbeg, kend, As, Bs, acc, tid, masked, kmask);
   uint8_t* C = p.C ? p.C + blockIdx.y * p.sC + blockIdx.z * p.zC : nullptr;
   uint8_t* CT = p.CT ? p.CT + blockIdx.y * p.sCT + blockIdx.z * p.zCT : nullptr;
-  // D[r][c] of a 16x16 block sits in lane (c + 16*(r/4)), element r%4
+  // The tile leaves through LDS in two halves of 64 rows (tile_product ends with a
+  // barrier, so the operand buffers are free): every store is a whole run of 8
+  // consecutive elements (three 16-byte stores), of C's rows and of CT's rows.
+  // D[r][c] of a 16x16 block sits in lane (c + 16*(r/4)), element r%4.
+  float(*st)[STG_LD] = reinterpret_cast<float(*)[STG_LD]>(lds);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int h = 0; h < 2; ++h) {
+    if (wm == h) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = n0 + wn * 64 + j * 16 + (lane & 15);
-      const int row0 = m0 + wm * 64 + i * 16 + 4 * (lane >> 4);
-      const v4f v = acc[i][j] * p.alpha;
-      if (C) {
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) store_split(C, p.ldc, row0 + r, col, v[r]);
-      }
-      if (CT) store_split4(CT, p.ldct, col, row0, v);
+        for (int j = 0; j < 4; ++j) {
+          const v4f v = acc[i][j] * p.alpha;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) st[i * 16 + 4 * (lane >> 4) + r][wn * 64 + j * 16 + (lane & 15)] = v[r];
+        }
     }
-}
-
-// a run of 8 consecutive elements (row, col0 .. col0 + 7), col0 a multiple of 8:
-// three 16-byte stores
-__device__ __forceinline__ void store_run(uint8_t* M, int64_t ld, int64_t row, int64_t col0, const float (&x)[8]) {
-  uint32_t p1[4], p2[4], p3[4];
+    __syncthreads();
+    if (C) {
+      // 64 rows x 16 runs
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    uint32_t a1, a2, a3, b1, b2, b3;
-    split3(x[2 * q], a1, a2, a3);
-    split3(x[2 * q + 1], b1, b2, b3);
-    p1[q] = a1 | (b1 << 16);
-    p2[q] = a2 | (b2 << 16);
-    p3[q] = a3 | (b3 << 16);
+      for (int q = 0; q < 4; ++q) {
+        const int g = tid + 256 * q, r = g >> 4, run = g & 15;
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = st[r][8 * run + e];
+        store_run(C, p.ldc, m0 + 64 * h + r, n0 + 8 * run, x);
+      }
+    }
+    if (CT) {
+      // 128 rows of CT (the tile's columns) x 8 runs of this half's 64 rows
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int g = tid + 256 * q, col = g & 127, run = g >> 7;
+        float y[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) y[e] = st[8 * run + e][col];
+        store_run(CT, p.ldct, n0 + col, m0 + 64 * h + 8 * run, y);
+      }
+    }
+    __syncthreads();
   }
-  v4u* d = reinterpret_cast<v4u*>(M + (row * ld + col0) * 6);
-  d[0] = (v4u){p1[0], p1[1], p1[2], p1[3]};
-  d[1] = (v4u){p2[0], p2[1], p2[2], p2[3]};
-  d[2] = (v4u){p3[0], p3[1], p3[2], p3[3]};
 }
 
 // T and Tt (split) from the factor L (lower, FP64) and its diagonal-block inverses
 // Dinv (np x 128, ld 128): a 64x64 tile of T goes through LDS, then every thread
 // writes whole runs of T's rows and of Tt's rows.
+// With the factor's zero-block map (nz, every first doubling product masked by it):
+// a tile below the diagonal blocks is read only as T21 of its level, and only when
+// its 128-row block has a nonzero block in its panel; tri<2> overwrites it (and its
+// transpose in Tt) before anything else reads it.  So only those tiles of T, and
+// the diagonal blocks of both copies, are written.
 __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __restrict__ L,
                                                              const double* __restrict__ Dinv, int64_t np,
                                                              uint8_t* __restrict__ T, uint8_t* __restrict__ Tt,
                                                              int64_t sL, int64_t sD, int64_t sT, int64_t sTt,
-                                                             const int* skip) {
+                                                             const int* skip, const uint8_t* nz, int64_t snz,
+                                                             int nz_chunks) {
   if (skip && skip[blockIdx.z]) return;
   const int bi = blockIdx.x, bj = blockIdx.y;  // tile rows i, columns j of T
   // Tiles of T above the 128x128 diagonal blocks (and their transposes in Tt) are
@@ -319,6 +373,12 @@ __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __re
   // granularity to the triangle (the doubling products, V^T V), so only the zeros
   // inside the diagonal blocks are read.  They are not written.
   if ((bj >> 1) > (bi >> 1)) return;
+  const bool off_block = (bj >> 1) < (bi >> 1);
+  if (nz && off_block) {
+    const uint8_t* f = nz + (int64_t)blockIdx.z * snz + (int64_t)(bj >> 1) * nz_chunks;
+    if (!(f[bi & ~1] | f[bi | 1])) return;
+  }
+  const bool write_tt = !(nz && off_block);
   L += blockIdx.z * sL;
   Dinv += blockIdx.z * sD;
   T += blockIdx.z * sT;
@@ -345,7 +405,7 @@ __global__ __launch_bounds__(256) void tri_init_bf16x6_kernel(const double* __re
       y[e] = t[8 * q + e][r];
     }
     store_run(T, np, i0 + r, j0 + 8 * q, x);
-    store_run(Tt, np, j0 + r, i0 + 8 * q, y);
+    if (write_tt) store_run(Tt, np, j0 + r, i0 + 8 * q, y);
   }
 }
 
@@ -439,8 +499,11 @@ int trtri_bf16x6(hipStream_t stream, const double* L, const double* Dinv, int64_
   uint8_t* Tt = static_cast<uint8_t*>(Ttv);
   uint8_t* tmp = static_cast<uint8_t*>(tmpv);
   const int T64 = (int)(np / 64);
+  // the init may leave tiles unwritten only when every first product is masked by the
+  // map (masks hold 64 chunks of 128: K = s <= 8192)
+  const uint8_t* init_nz = (nz && np <= 16384) ? nz : nullptr;
   hipLaunchKernelGGL(tri_init_bf16x6_kernel, dim3(T64, T64, count), dim3(256), 0, stream, L, Dinv, np, T, Tt, sL,
-                     sD, sT, sTt, skip);
+                     sD, sT, sTt, skip, init_nz, snz, (int)(np / 64));
   if (hipGetLastError() != hipSuccess) return -2;
   // element offsets inside the split copies: sub-matrices start at multiples of 128
   // columns, so byte offset = 6 x element offset
