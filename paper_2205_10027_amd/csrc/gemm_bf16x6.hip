@@ -284,6 +284,22 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x6_tri_kernel(TriBf6Params p)
       for (int e = tid; e < 2 * nq; e += 256)
         any |= f[(int64_t)(q0 + (e >> 1)) * p.nz_chunks + ((r0 + m0) >> 6) + (e & 1)];
       if (!__syncthreads_or(any)) kend = kbeg;
+    } else if ((p.K >> 7) <= 64) {
+      // tmp's row chunk c (128 rows: tmp = T21 V11) is nonzero only where T21's rows
+      // are: bit c of the mask when any panel of T21 has a nonzero block in them
+      __shared__ unsigned long long kmask2_sh;
+      if (tid == 0) kmask2_sh = 0ull;
+      __syncthreads();
+      const int q0 = c0 >> 7, nq = p.nz_w >> 7, nch = p.K >> 6;
+      unsigned long long mine = 0ull;
+      for (int e = tid; e < nch * nq; e += 256) {
+        const int c = e / nq, q = q0 + e - (e / nq) * nq;
+        if (f[(int64_t)q * p.nz_chunks + (r0 >> 6) + c]) mine |= 1ull << (c >> 1);
+      }
+      if (mine) atomicOr(&kmask2_sh, mine);
+      __syncthreads();
+      kmask = kmask2_sh;
+      masked = true;
     } else {
       __shared__ int last[4];
       const int q0 = c0 >> 7, nq = p.nz_w >> 7, nch = p.K >> 6;

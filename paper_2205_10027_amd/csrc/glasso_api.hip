@@ -716,12 +716,23 @@ glasso_err run_engine(glasso_handle h, hipStream_t st, int count, int64_t n, con
     // the accepted trial's factor: place and invert its diagonal blocks
     K_TRY(finish_factor(s, w.L, np, (int)np, w.dL, w.Dinv, w.skip, fbw));
     // FP64-W problems: V = inv(L) in place, W = V^T V; the others keep L intact
-    // (their FP64 re-check starts from it)
-    K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
-    K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
-    if (w_mixed) {
+    // (their FP64 re-check starts from it).  Eager launches leave out the kernels
+    // every problem would skip (a captured graph holds them all).
+    bool any64 = o.graphs != 0, any32 = o.graphs != 0;
+    for (int b = 0; b < count; ++b) {
+      any64 = any64 || !hm.skip64[b];
+      any32 = any32 || !hm.skip32[b];
+    }
+    if (any64) {
+      K_TRY(trtri_lower(s, w.L, np, (int)np, w.Dinv, w.X, w.skip64, fbw, nn));
+      K_TRY(lauum_lower(s, w.L, np, w.W, np, (int)np, w.skip64, fbw, nn));
+    }
+    if (w_mixed && any32) {
       e2 = inverse_f32(w, s, w.skip32, timed ? h->ev + 10 : nullptr);
       if (e2) return e2;
+    } else if (w_mixed && timed) {
+      HIP_TRY(hipEventRecord(h->ev[10], s));
+      HIP_TRY(hipEventRecord(h->ev[11], s));
     }
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], s));
     K_TRY(pass_grad(s, w.S, w.W, w.A, w.dL, n, n, np, 0.0, z_f64, w.GM, w.part, w.scal, pb, z_split, 8 * nn,
