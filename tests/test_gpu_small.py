@@ -99,10 +99,11 @@ def test_small_status_and_errors(g):
     assert r.status == g.MAX_ITER and r.iterations == 1
     r = g.Solver(t0=1e-13, t_min=1e-12, t_floor=0.0).solve_small([Sd], [0.2], 1e-9)[0]
     assert r.status == g.LS_FAILED and r.iterations == 0
-    # warm start from a neighbouring solution
+    # warm start from a neighbouring solution (at tol 1e-7: from this start the oracle
+    # itself stalls near KKT 1.3e-8 and does not reach 1e-8 in 500 iterations)
     first = g.Solver().solve_small([Sd], [0.25], 1e-8)[0]
-    warm = g.Solver(warm_start=True).solve_small([Sd], [0.2], 1e-8, A_list=[first.A.clone()])[0]
-    cold = g.Solver().solve_small([Sd], [0.2], 1e-8)[0]
+    warm = g.Solver(warm_start=True).solve_small([Sd], [0.2], 1e-7, A_list=[first.A.clone()])[0]
+    cold = g.Solver().solve_small([Sd], [0.2], 1e-7)[0]
     assert warm.status == g.CONVERGED and abs(warm.objective - cold.objective) <= 1e-9 * abs(cold.objective)
     with pytest.raises(g.GlassoError) as e:
         g.Solver(warm_start=True).solve_small([Sd], [0.2], 1e-6, A_list=[to_dev(-np.eye(40))])
