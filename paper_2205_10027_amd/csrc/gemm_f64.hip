@@ -65,16 +65,13 @@ struct GemmF64Params {
 
 // Stage one T x BK slice of op(X) (rows r0.., k from kt) into registers.
 // TX = 0: X[row * ld + k] (k contiguous); TX = 1: X[k * ld + row] (one LDS row per
-// thread: coalesced loads along the rows, 16-byte LDS stores).  tri: 1 zeroes
-// k > row, 2 zeroes k < row; for the B operand the caller passes the mirrored code.
+// thread: coalesced loads along the rows, 16-byte LDS stores).
 template <int TX, int T>
-__device__ __forceinline__ void load_slice(const double* X, int64_t ld, int r0, int kt, int tid, int tri,
+__device__ __forceinline__ void load_slice(const double* X, int64_t ld, int r0, int kt, int tid,
                                            double (&r)[Tile<T>::R]) {
   constexpr int R = Tile<T>::R, TPR = Tile<T>::TPR;
-  int row, k0;
   if (TX == 0) {
-    row = tid / TPR;
-    k0 = (tid % TPR) * R;
+    const int row = tid / TPR, k0 = (tid % TPR) * R;
     const double2* src = reinterpret_cast<const double2*>(X + (int64_t)(r0 + row) * ld + kt + k0);
 #pragma unroll
     for (int i = 0; i < R / 2; ++i) {
@@ -83,19 +80,26 @@ __device__ __forceinline__ void load_slice(const double* X, int64_t ld, int r0, 
       r[2 * i + 1] = v.y;
     }
   } else {
-    row = tid % T;
-    k0 = (tid / T) * R;
+    const int row = tid % T, k0 = (tid / T) * R;
     const double* src = X + (int64_t)(kt + k0) * ld + r0 + row;
 #pragma unroll
     for (int i = 0; i < R; ++i) r[i] = src[(int64_t)i * ld];
   }
-  if (tri) {
-    const int m = r0 + row;
+}
+// Triangular mask of a staged slice (rows r0.., k from kt), applied when the slice
+// goes to LDS (so the loads need not have arrived before): tri 1 zeroes k > row,
+// 2 zeroes k < row; for the B operand the caller passes the mirrored code.
+template <int TX, int T>
+__device__ __forceinline__ void mask_slice(int r0, int kt, int tid, int tri, double (&r)[Tile<T>::R]) {
+  constexpr int R = Tile<T>::R, TPR = Tile<T>::TPR;
+  if (!tri) return;
+  const int row = TX == 0 ? tid / TPR : tid % T;
+  const int k0 = TX == 0 ? (tid % TPR) * R : (tid / T) * R;
+  const int m = r0 + row;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int k = kt + k0 + i;
-      if ((tri == 1 && k > m) || (tri == 2 && k < m)) r[i] = 0.0;
-    }
+  for (int i = 0; i < R; ++i) {
+    const int k = kt + k0 + i;
+    if ((tri == 1 && k > m) || (tri == 2 && k < m)) r[i] = 0.0;
   }
 }
 
@@ -213,77 +217,139 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
     for (int i = 0; i < R; ++i) any = any || r[i] != 0.0;
     return any;
   };
+  // The slice in LDS buffer `cur` is multiplied while the next one is stored to the
+  // other buffer from one of PD register sets, each holding a slice whose loads were
+  // issued PD slices earlier.  PD > 1 for 64x64 tiles: a long K range on few tiles
+  // (the updates of a sparse factorisation past a few dense rows) then waits on
+  // global-load latency once per PD slices instead of once per slice.
+  constexpr int PD = T == 64 ? 3 : 1;
   if (kbeg < kend) {
-    double ra[R], rb[R];
-    load_slice<TA, T>(A, p.lda, m0, kbeg, tid, p.a_tri, ra);
-    load_slice<TB, T>(B, p.ldb, n0, kbeg, tid, btri, rb);
-    store_slice<TA, T>(As[0], tid, ra);
-    store_slice<TB, T>(Bs[0], tid, rb);
+    double ra[PD][R], rb[PD][R];
+    load_slice<TA, T>(A, p.lda, m0, kbeg, tid, ra[0]);
+    load_slice<TB, T>(B, p.ldb, n0, kbeg, tid, rb[0]);
+    mask_slice<TA, T>(m0, kbeg, tid, p.a_tri, ra[0]);
+    mask_slice<TB, T>(n0, kbeg, tid, btri, rb[0]);
+    store_slice<TA, T>(As[0], tid, ra[0]);
+    store_slice<TB, T>(Bs[0], tid, rb[0]);
     bool live = true;  // the slice in As[cur], Bs[cur] has a nonzero product
     if (sparse) {
-      const bool za = __syncthreads_or(nonzero(ra));
-      const bool zb = __syncthreads_or(nonzero(rb));
+      const bool za = __syncthreads_or(nonzero(ra[0]));
+      const bool zb = __syncthreads_or(nonzero(rb[0]));
       live = za && zb;
     } else {
       __syncthreads();
     }
+    // kq[s]: the slice register set s holds (kend: none); klast: the last one issued.
+    // Past the last slice a set is loaded with the last valid one and never used: the
+    // loads stay unconditional, so the compiler waits for each only where it is used.
+    int kq[PD];
+    int klast = kbeg;
+#pragma unroll
+    for (int s = 0; s < PD; ++s) {
+      klast = (klast < kend) ? next_k(klast) : kend;
+      kq[s] = klast;
+      const int kl = min(klast, kend - BK);
+      load_slice<TA, T>(A, p.lda, m0, kl, tid, ra[s]);
+      load_slice<TB, T>(B, p.ldb, n0, kl, tid, rb[s]);
+    }
     int cur = 0;
-    for (int kt = kbeg; kt < kend;) {
-      const int nk = next_k(kt);
-      const bool more = nk < kend;
-      if (more) {
-        load_slice<TA, T>(A, p.lda, m0, nk, tid, p.a_tri, ra);
-        load_slice<TB, T>(B, p.ldb, n0, nk, tid, btri, rb);
+    bool more = true;
+    while (more) {
+#pragma unroll
+      for (int s = 0; s < PD; ++s) {
+        if (!more) break;
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+          if (!live) break;
+          double af[NBLK], bf[NBLK];
+          const int kc = kk * 4 + (lane >> 4);
+#pragma unroll
+          for (int i = 0; i < NBLK; ++i) af[i] = As[cur][wm * WT + i * 16 + (lane & 15)][kc];
+#pragma unroll
+          for (int j = 0; j < NBLK; ++j) bf[j] = Bs[cur][wn * WT + j * 16 + (lane & 15)][kc];
+          // a 16x4 operand block that is zero in the whole wave adds exact zeros to its
+          // row (or column) of output blocks: past a sparse factor's dense rows most
+          // of a tile's rows are zero (launches with a zero-block map only)
+          unsigned int la = (1u << NBLK) - 1u, lb = (1u << NBLK) - 1u;
+          if (sparse) {
+#pragma unroll
+            for (int i = 0; i < NBLK; ++i) {
+              const uint64_t b = __ballot(af[i] != 0.0);
+              if (!b) la &= ~(1u << i);
+            }
+#pragma unroll
+            for (int j = 0; j < NBLK; ++j) {
+              const uint64_t b = __ballot(bf[j] != 0.0);
+              if (!b) lb &= ~(1u << j);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+            for (int j = 0; j < NBLK; ++j)
+              if (((la >> i) & 1u) && ((lb >> j) & 1u))
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        // the slices are consumed in k order: set s holds the next one
+        more = kq[s] < kend;
+        if (more) {
+          mask_slice<TA, T>(m0, kq[s], tid, p.a_tri, ra[s]);
+          mask_slice<TB, T>(n0, kq[s], tid, btri, rb[s]);
+          store_slice<TA, T>(As[cur ^ 1], tid, ra[s]);
+          store_slice<TB, T>(Bs[cur ^ 1], tid, rb[s]);
+        }
+        if (sparse) {
+          const bool za = __syncthreads_or(more && nonzero(ra[s]));
+          const bool zb = __syncthreads_or(more && nonzero(rb[s]));
+          live = za && zb;
+        } else {
+          __syncthreads();
+        }
+        if (more) {
+          // refill set s with the slice PD places further on
+          klast = (klast < kend) ? next_k(klast) : kend;
+          kq[s] = klast;
+          const int kl = min(klast, kend - BK);
+          load_slice<TA, T>(A, p.lda, m0, kl, tid, ra[s]);
+          load_slice<TB, T>(B, p.ldb, n0, kl, tid, rb[s]);
+          cur ^= 1;
+        }
       }
-#pragma unroll
-      for (int kk = 0; kk < BK / 4; ++kk) {
-        if (!live) break;
-        double af[NBLK], bf[NBLK];
-        const int kc = kk * 4 + (lane >> 4);
-#pragma unroll
-        for (int i = 0; i < NBLK; ++i) af[i] = As[cur][wm * WT + i * 16 + (lane & 15)][kc];
-#pragma unroll
-        for (int j = 0; j < NBLK; ++j) bf[j] = Bs[cur][wn * WT + j * 16 + (lane & 15)][kc];
-#pragma unroll
-        for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-          for (int j = 0; j < NBLK; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
-      if (more) {
-        store_slice<TA, T>(As[cur ^ 1], tid, ra);
-        store_slice<TB, T>(Bs[cur ^ 1], tid, rb);
-      }
-      if (sparse) {
-        const bool za = __syncthreads_or(more && nonzero(ra));
-        const bool zb = __syncthreads_or(more && nonzero(rb));
-        live = za && zb;
-      } else {
-        __syncthreads();
-      }
-      cur ^= 1;
-      kt = nk;
     }
   }
 
   // D[r][c] of a 16x16 block sits in lane (c + 16*(r%4)), element r/4
   // (v_mfma_f64_16x16x4f64 output layout, checked on gfx950).
+  // With beta != 0 every old value of the tile is loaded before the first store:
+  // loads interleaved with stores to C, which the compiler must assume may alias,
+  // would each wait for the one before.
   const double alpha = p.alpha, beta = p.beta;
+  double* const Cw = C + (int64_t)(m0 + wm * WT + (lane >> 4)) * p.ldc + n0 + wn * WT + (lane & 15);
+  double old[NBLK][NBLK][4];
 #pragma unroll
-  for (int i = 0; i < NBLK; ++i) {
+  for (int i = 0; i < NBLK; ++i)
 #pragma unroll
-    for (int j = 0; j < NBLK; ++j) {
-      const int col = n0 + wn * WT + j * 16 + (lane & 15);
+    for (int j = 0; j < NBLK; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) old[i][j][r] = 0.0;
+  if (beta != 0.0) {
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+      for (int j = 0; j < NBLK; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) old[i][j][r] = Cw[(int64_t)(i * 16 + 4 * r) * p.ldc + j * 16];
+  }
+#pragma unroll
+  for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WT + i * 16 + 4 * r + (lane >> 4);
-        double* dst = C + (int64_t)row * p.ldc + col;
         double v = alpha * acc[i][j][r];
-        if (beta != 0.0) v += beta * (*dst);
-        *dst = v;
+        if (beta != 0.0) v += beta * old[i][j][r];
+        Cw[(int64_t)(i * 16 + 4 * r) * p.ldc + j * 16] = v;
       }
-    }
-  }
 }
 
 template <int T>
