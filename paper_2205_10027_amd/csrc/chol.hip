@@ -60,8 +60,24 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool solver = blockIdx.x > 0 && rest > 0;
 
-  // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB)
-#pragma unroll 8
+  // zero-block map bytes of the kl (at most MID / NB - 1) panels to the left: lane
+  // 3 (kp - 1) + w of each wave loads byte w of panel k0 / NB - kp (w = 0, 1: the
+  // block's two 64-row chunks; 2: this workgroup's rows), in one load issued with
+  // the block's; combined into bits 2kp - 2 and 2kp - 1 (a bit per 64-column half)
+  // of mA0, mA1 and mR
+  const uint8_t* nzf = fb.nz ? fb.nz + blockIdx.y * fb.snz : nullptr;
+  constexpr int KLMAX = MID / NB - 1;
+  const bool use_map = nzf != nullptr && kl > 0;
+  unsigned int mbv = 0u;
+  if (use_map && lane < 3 * KLMAX) {
+    const int kp = lane / 3 + 1, w = lane % 3;
+    const int chunk = (w == 2 && solver) ? (k0 + NB) / 64 + (int)blockIdx.x - 1 : k0 / 64 + (w == 1 ? 1 : 0);
+    mbv = nzf[(int64_t)max(k0 / NB - kp, 0) * fb.nz_chunks + chunk];
+  }
+
+  // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB), all in
+  // flight together
+#pragma unroll
   for (int i = 0; i < NB * NB / 512; ++i) {
     const int e = 2 * (tid + 256 * i);
     const int r = e >> 7, c = e & 127;
@@ -70,6 +86,17 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
     a[r][c + 1] = (c + 1 <= r) ? v.y : 0.0;
   }
   __syncthreads();
+  unsigned int mA0 = 0xffu, mA1 = 0xffu, mR = solver ? 0xffu : 0u;
+  if (use_map) {
+    mA0 = mA1 = mR = 0u;
+#pragma unroll
+    for (int kp = 1; kp <= KLMAX; ++kp) {
+      const unsigned int on = kp <= kl ? 3u : 0u;
+      mA0 |= ((unsigned int)__builtin_amdgcn_readlane((int)mbv, 3 * kp - 3) & on) << (2 * kp - 2);
+      mA1 |= ((unsigned int)__builtin_amdgcn_readlane((int)mbv, 3 * kp - 2) & on) << (2 * kp - 2);
+      mR |= ((unsigned int)__builtin_amdgcn_readlane((int)mbv, 3 * kp - 1) & (solver ? on : 0u)) << (2 * kp - 2);
+    }
+  }
 
   // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
   // (register s of lane l: R[l%16][16b + 4s + l/16]); issued after the block is in
@@ -84,23 +111,14 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   }
 
   const int li = lane & 15, lk = lane >> 4;
-  const uint8_t* nzf = fb.nz ? fb.nz + blockIdx.y * fb.snz : nullptr;
-  const int own_chunk = (k0 + NB) / 64 + (int)blockIdx.x - 1;
   // nonzero 16x16 blocks (b, q) of a staged 128 x 64 half panel, bit 4b + q; two
   // masks used in turn, the next one cleared while the current one is in use
   __shared__ unsigned int dmask[2];
   auto left_updates = [&](v4d(&acc)[9], const int(&bi)[9], const int(&bj)[9]) {
     int phase = 0;
     for (int kp = kl; kp >= 1; --kp) {
-      const int P = k0 / NB - kp;  // global panel index
-      // map bits of panel P: bit h = a nonzero in columns 64h .. 64h + 63
-      int m0 = 3, m1 = 3, mr = solver ? 3 : 0;
-      if (nzf) {
-        const uint8_t* f = nzf + (int64_t)P * fb.nz_chunks;
-        m0 = f[k0 / 64];
-        m1 = f[k0 / 64 + 1];
-        if (solver) mr = f[own_chunk];
-      }
+      // map bits of panel k0 / NB - kp: bit h = a nonzero in columns 64h .. 64h + 63
+      const int m0 = (mA0 >> (2 * kp - 2)) & 3, m1 = (mA1 >> (2 * kp - 2)) & 3, mr = (mR >> (2 * kp - 2)) & 3;
       if (!(m0 | m1)) continue;  // L_kp = 0: nothing to subtract
       const double* D = A - NB * kp;  // L_kp: rows k0.., columns of panel P
       const double* Rr = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + li) * lda - NB * kp;
@@ -111,16 +129,21 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
         const bool rows_h = (mr >> h) & 1;
         unsigned int* const mcur = &dmask[phase & 1];
         if (tid == 0) dmask[(phase + 1) & 1] = 0u;
-        // stage L_kp[:, 64h .. 64h + 63] (a zero 64-row chunk is written without
-        // loading it) and collect the nonzero 16x16 blocks: thread t holds columns
-        // 2t mod 64 and 2t mod 64 + 1 of rows t/32 + 8i
+        // stage L_kp[:, 64h .. 64h + 63] (a 64-row chunk that the map shows zero is
+        // staged as zeros) and collect the nonzero 16x16 blocks: thread t holds
+        // columns 2t mod 64 and 2t mod 64 + 1 of rows t/32 + 8i.  The loads are
+        // unconditional (every row is inside the matrix), so all sixteen are in
+        // flight together.
         unsigned int bits = 0u;
         const int c = (2 * tid) & 63, r0 = tid >> 5;
+        double2 vv[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) vv[i] = *reinterpret_cast<const double2*>(D + (int64_t)(r0 + 8 * i) * lda + 64 * h + c);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const int r = r0 + 8 * i;
-          double2 v = make_double2(0.0, 0.0);
-          if (i < 8 ? d0 : d1) v = *reinterpret_cast<const double2*>(D + (int64_t)r * lda + 64 * h + c);
+          const bool keep = i < 8 ? d0 : d1;
+          const double2 v = keep ? vv[i] : make_double2(0.0, 0.0);
           a[r][c] = v.x;
           a[r][c + 1] = v.y;
           if (v.x != 0.0 || v.y != 0.0) bits |= 1u << (4 * (r >> 4) + (c >> 4));
