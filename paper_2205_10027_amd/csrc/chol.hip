@@ -75,6 +75,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
     mbv = nzf[(int64_t)max(k0 / NB - kp, 0) * fb.nz_chunks + chunk];
   }
 
+  // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
+  // (register s of lane l: R[l%16][16b + 4s + l/16]); issued first, they arrive
+  // while the block is loaded and factored
+  const double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
+  v4d x[8];
+  if (solver) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
+  }
+
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB), all in
   // flight together
 #pragma unroll
@@ -96,18 +108,6 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
       mA1 |= ((unsigned int)__builtin_amdgcn_readlane((int)mbv, 3 * kp - 2) & on) << (2 * kp - 2);
       mR |= ((unsigned int)__builtin_amdgcn_readlane((int)mbv, 3 * kp - 1) & (solver ? on : 0u)) << (2 * kp - 2);
     }
-  }
-
-  // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
-  // (register s of lane l: R[l%16][16b + 4s + l/16]); issued after the block is in
-  // LDS, they arrive while it is being factored
-  const double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
-  v4d x[8];
-  if (solver) {
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
   }
 
   const int li = lane & 15, lk = lane >> 4;

@@ -215,10 +215,9 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid, Pre pre = Pre()) {
       double u[PF];
 #pragma unroll
       for (int c = j; c < PF; ++c) u[c] = lane_bcast(v[j], c);
+      // a pivot that is not positive and finite gives garbage from here on (at
+      // least a diagonal entry that is not either); the panel is checked below
       const double piv = u[j];
-      const bool ok = (piv > 0.0) && (piv <= DBL_MAX);
-      if (!ok && fail < 0) fail = c0 + j;
-      // a failed pivot gives garbage here, and the panel is abandoned below
       const double r = rsqrt_pos(piv);
       // L[row][j] L[c][j] = v[j] u[c] / piv
       const double y = v[j] * (r * r);
@@ -226,12 +225,22 @@ __device__ int lds_potrf(double (*a)[NB + 1], int tid, Pre pre = Pre()) {
 #pragma unroll
       for (int c = j + 1; c < PF; ++c) v[c] -= y * u[c];
     }
-    if (fail >= 0) break;
     if (valid && (lane >= PF || wave == 0)) {
 #pragma unroll
       for (int q = 0; q < PF; ++q) a[row][c0 + q] = v[q];
     }
     __syncthreads();
+    {
+      // the panel's first pivot that is not positive and finite is the first of its
+      // diagonal entries sqrt(piv) that is not (rsqrt of a negative, zero, infinite
+      // or NaN pivot gives NaN): one check per panel, not a branch in every step
+      const double d = a[c0 + (lane & 15)][c0 + (lane & 15)];
+      const uint64_t bad = __ballot(!(d > 0.0 && d <= DBL_MAX));
+      if (bad) {
+        fail = c0 + __builtin_ctzll(bad);
+        break;
+      }
+    }
     // blocks right of the panel: acc -= L[bi rows][panel] L[bj rows][panel]^T
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
