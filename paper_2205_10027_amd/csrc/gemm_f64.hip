@@ -252,70 +252,70 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
       load_slice<TA, T>(A, p.lda, m0, kl, tid, ra[s]);
       load_slice<TB, T>(B, p.ldb, n0, kl, tid, rb[s]);
     }
+    // Straight-line groups of PD steps (no exit inside a group, every load, store and
+    // barrier unconditional) let the compiler wait, before storing set s, only for
+    // that set's loads.  `have` says whether LDS buffer `cur` holds a slice; past the
+    // last one a group finishes with steps that multiply nothing.
     int cur = 0;
-    bool more = true;
-    while (more) {
+    bool have = true;
+    do {
 #pragma unroll
       for (int s = 0; s < PD; ++s) {
-        if (!more) break;
+        if (have && live) {
 #pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-          if (!live) break;
-          double af[NBLK], bf[NBLK];
-          const int kc = kk * 4 + (lane >> 4);
+          for (int kk = 0; kk < BK / 4; ++kk) {
+            double af[NBLK], bf[NBLK];
+            const int kc = kk * 4 + (lane >> 4);
 #pragma unroll
-          for (int i = 0; i < NBLK; ++i) af[i] = As[cur][wm * WT + i * 16 + (lane & 15)][kc];
+            for (int i = 0; i < NBLK; ++i) af[i] = As[cur][wm * WT + i * 16 + (lane & 15)][kc];
 #pragma unroll
-          for (int j = 0; j < NBLK; ++j) bf[j] = Bs[cur][wn * WT + j * 16 + (lane & 15)][kc];
-          // a 16x4 operand block that is zero in the whole wave adds exact zeros to its
-          // row (or column) of output blocks: past a sparse factor's dense rows most
-          // of a tile's rows are zero (launches with a zero-block map only)
-          unsigned int la = (1u << NBLK) - 1u, lb = (1u << NBLK) - 1u;
-          if (sparse) {
+            for (int j = 0; j < NBLK; ++j) bf[j] = Bs[cur][wn * WT + j * 16 + (lane & 15)][kc];
+            // a 16x4 operand block that is zero in the whole wave adds exact zeros to
+            // its row (or column) of output blocks: past a sparse factor's dense rows
+            // most of a tile's rows are zero (launches with a zero-block map only)
+            unsigned int la = (1u << NBLK) - 1u, lb = (1u << NBLK) - 1u;
+            if (sparse) {
 #pragma unroll
-            for (int i = 0; i < NBLK; ++i) {
-              const uint64_t b = __ballot(af[i] != 0.0);
-              if (!b) la &= ~(1u << i);
+              for (int i = 0; i < NBLK; ++i) {
+                const uint64_t b = __ballot(af[i] != 0.0);
+                if (!b) la &= ~(1u << i);
+              }
+#pragma unroll
+              for (int j = 0; j < NBLK; ++j) {
+                const uint64_t b = __ballot(bf[j] != 0.0);
+                if (!b) lb &= ~(1u << j);
+              }
             }
 #pragma unroll
-            for (int j = 0; j < NBLK; ++j) {
-              const uint64_t b = __ballot(bf[j] != 0.0);
-              if (!b) lb &= ~(1u << j);
-            }
+            for (int i = 0; i < NBLK; ++i)
+#pragma unroll
+              for (int j = 0; j < NBLK; ++j)
+                if (((la >> i) & 1u) && ((lb >> j) & 1u))
+                  acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
           }
-#pragma unroll
-          for (int i = 0; i < NBLK; ++i)
-#pragma unroll
-            for (int j = 0; j < NBLK; ++j)
-              if (((la >> i) & 1u) && ((lb >> j) & 1u))
-                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
-        // the slices are consumed in k order: set s holds the next one
-        more = kq[s] < kend;
-        if (more) {
-          mask_slice<TA, T>(m0, kq[s], tid, p.a_tri, ra[s]);
-          mask_slice<TB, T>(n0, kq[s], tid, btri, rb[s]);
-          store_slice<TA, T>(As[cur ^ 1], tid, ra[s]);
-          store_slice<TB, T>(Bs[cur ^ 1], tid, rb[s]);
-        }
+        // the slices are consumed in k order: set s holds the next one (if any)
+        have = have && kq[s] < kend;
+        mask_slice<TA, T>(m0, kq[s], tid, p.a_tri, ra[s]);
+        mask_slice<TB, T>(n0, kq[s], tid, btri, rb[s]);
+        store_slice<TA, T>(As[cur ^ 1], tid, ra[s]);
+        store_slice<TB, T>(Bs[cur ^ 1], tid, rb[s]);
         if (sparse) {
-          const bool za = __syncthreads_or(more && nonzero(ra[s]));
-          const bool zb = __syncthreads_or(more && nonzero(rb[s]));
+          const bool za = __syncthreads_or(nonzero(ra[s]));
+          const bool zb = __syncthreads_or(nonzero(rb[s]));
           live = za && zb;
         } else {
           __syncthreads();
         }
-        if (more) {
-          // refill set s with the slice PD places further on
-          klast = (klast < kend) ? next_k(klast) : kend;
-          kq[s] = klast;
-          const int kl = min(klast, kend - BK);
-          load_slice<TA, T>(A, p.lda, m0, kl, tid, ra[s]);
-          load_slice<TB, T>(B, p.ldb, n0, kl, tid, rb[s]);
-          cur ^= 1;
-        }
+        // refill set s with the slice PD places further on
+        klast = (klast < kend) ? next_k(klast) : kend;
+        kq[s] = klast;
+        const int kl = min(klast, kend - BK);
+        load_slice<TA, T>(A, p.lda, m0, kl, tid, ra[s]);
+        load_slice<TB, T>(B, p.ldb, n0, kl, tid, rb[s]);
+        cur ^= 1;
       }
-    }
+    } while (have);
   }
 
   // D[r][c] of a 16x16 block sits in lane (c + 16*(r%4)), element r/4
