@@ -220,20 +220,29 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
 
   // inverses of the 16x16 diagonal blocks: wave w inverts block 2w in lanes 0..15
   // and block 2w + 1 in lanes 32..47, lane c computing column c by forward
-  // substitution.  They go to the free strict upper triangle: block b < 7 at tile
-  // (b, 7), block 7 at tile (0, 6) (16x16 tiles).
+  // substitution, column-oriented: once x_k is known it is subtracted from every
+  // later row (each row still sums its terms in k order), so the dependent chain is
+  // one step per row, not one per term.  1/L_ii: the hardware reciprocal refined by
+  // one third-order step.  The inverses go to the free strict upper triangle: block
+  // b < 7 at tile (b, 7), block 7 at tile (0, 6) (16x16 tiles).
   {
     const int c = lane & 31, b = 2 * wave + (lane >> 5), o = 16 * b;
     if (c < 16) {
       double rd[16], xv[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) rd[i] = 1.0 / a[o + i][o + i];
-#pragma unroll
       for (int i = 0; i < 16; ++i) {
-        double s = (i == c) ? 1.0 : 0.0;
+        const double d = a[o + i][o + i];
+        const double q0 = __builtin_amdgcn_rcp(d);
+        const double e = fma(-d, q0, 1.0);
+        rd[i] = fma(q0, fma(e, e, e), q0);
+      }
 #pragma unroll
-        for (int k = 0; k < i; ++k) s -= a[o + i][o + k] * xv[k];
-        xv[i] = s * rd[i];
+      for (int i = 0; i < 16; ++i) xv[i] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        xv[k] = xv[k] * rd[k];
+#pragma unroll
+        for (int i = k + 1; i < 16; ++i) xv[i] -= a[o + i][o + k] * xv[k];
       }
       const int r0 = (b < 7) ? o : 0, c0 = (b < 7) ? 112 : 96;
 #pragma unroll
