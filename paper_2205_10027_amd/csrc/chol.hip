@@ -76,15 +76,18 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   }
 
   // rows of the panel owned by this wave: R[16 wave + i][.] in the layout of Y_b^T
-  // (register s of lane l: R[l%16][16b + 4s + l/16]); issued first, they arrive
-  // while the block is loaded and factored
-  const double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + (lane >> 4);
+  // with the in-block index permuted (register s of lane l: R[l%16][16b + 4(l/16) + s],
+  // four consecutive columns per lane: two 16-byte loads per block, whole 128-byte
+  // lines per row); issued first, they arrive while the block is loaded and factored
+  const double* R = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave + (lane & 15)) * lda + 4 * (lane >> 4);
   v4d x[8];
   if (solver) {
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[b][s] = R[16 * b + 4 * s];
+    for (int b = 0; b < 8; ++b) {
+      const double2 lo = *reinterpret_cast<const double2*>(R + 16 * b);
+      const double2 hi = *reinterpret_cast<const double2*>(R + 16 * b + 2);
+      x[b] = (v4d){lo.x, lo.y, hi.x, hi.y};
+    }
   }
 
   // 32 independent 16-byte loads per thread (a wave reads 4 rows of 1 KB), all in
@@ -111,6 +114,12 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
   }
 
   const int li = lane & 15, lk = lane >> 4;
+  // The solve's MFMA products run with the index inside every 16-block permuted,
+  // t -> pt(t) = 4 (t mod 4) + t / 4, for the L11 rows (A operand) and the X^T rows
+  // (B operand and result): result register r of lane l then holds original row
+  // 4 (l/16) + r, so each lane keeps four consecutive columns of its row of X.  The
+  // products are the same sums in the same k order.
+  const int pli = 4 * (li & 3) + (li >> 2);
   // nonzero 16x16 blocks (b, q) of a staged 128 x 64 half panel, bit 4b + q; two
   // masks used in turn, the next one cleared while the current one is in use
   __shared__ unsigned int dmask[2];
@@ -188,7 +197,7 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
 #pragma unroll
               for (int b = 0; b < 8; ++b)
                 if ((dm >> (4 * b + q)) & 1u)
-                  x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + li][16 * q + 4 * s2 + lk], rp[q][s2],
+                  x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + pli][16 * q + 4 * s2 + lk], rp[q][s2],
                                                               x[b], 0, 0, 0);
           }
         }
@@ -262,14 +271,14 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
     v4d xq = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      xq = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + li][c0 + 4 * s + lk], x[q][s], xq, 0, 0, 0);
+      xq = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r0 + pli][c0 + 4 * lk + s], x[q][s], xq, 0, 0, 0);
     x[q] = xq;
     // Y_b^T -= L_bq X_q^T for the later blocks
 #pragma unroll
     for (int b = q + 1; b < 8; ++b)
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + li][16 * q + 4 * s + lk], x[q][s], x[b], 0, 0, 0);
+        x[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[16 * b + pli][16 * q + 4 * lk + s], x[q][s], x[b], 0, 0, 0);
   }
   // the solved rows go out through LDS so that each store writes a whole row
   // (1 KB per instruction) instead of 32 bytes in each of 16 rows
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
 #pragma unroll
   for (int b = 0; b < 8; ++b)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[16 * wave + li][16 * b + 4 * s + lk] = x[b][s];
+    for (int s = 0; s < 4; ++s) a[16 * wave + li][16 * b + 4 * lk + s] = x[b][s];
   __syncthreads();
   double* const Rw = A + (int64_t)(NB + 64 * ((int)blockIdx.x - 1) + 16 * wave) * lda + 2 * lane;
 #pragma unroll
