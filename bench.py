@@ -54,8 +54,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3}
 # WRITE_SIZE counter runs scaled by a 1 GiB plain-copy calibration
 # (profiles/traffic_w_bf16x6_chain10k.md)
 VTV_TRAFFIC_BYTES = 11511834624
-# HBM bytes per leaf_potrf_kernel launch: not yet taken from counters for the current kernel
-LEAF_TRAFFIC_BYTES = None
+# HBM bytes per leaf_potrf_kernel launch at n = 10^4 (mean over the leaf steps of
+# every factorisation of the chain solves), from FETCH_SIZE and WRITE_SIZE counter runs
+# scaled by a 1 GiB plain-copy calibration (profiles/traffic_leaf_chain10k.md)
+LEAF_TRAFFIC_BYTES = 12968851
 
 
 def log(*a):
