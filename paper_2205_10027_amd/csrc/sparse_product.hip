@@ -45,29 +45,40 @@ __global__ __launch_bounds__(256) void sparse_rows_kernel(const double* __restri
   int* colM = r.colM + ((int64_t)b * r.rows + i) * KM;
   const uint64_t below = (1ull << lane) - 1;
   int na = 0, nm = 0;
-  for (int64_t j0 = 0; j0 < n; j0 += 64) {
-    const int64_t j = j0 + lane;
-    double a = 0.0;
-    int8_t g = 0;
-    if (j < n) {
-      a = A[j];
-      g = GM[j];
+  // four 64-column chunks per round, all loaded before the first is compacted (the
+  // loads are unconditional: a column past n is read at a clamped in-row index and
+  // ignored), so a wave keeps four round trips in flight instead of one
+  constexpr int U = 4;
+  for (int64_t j0 = 0; j0 < n; j0 += 64 * U) {
+    double av[U];
+    int8_t gv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = min(j0 + 64 * u + lane, np - 1);
+      av[u] = A[j];
+      gv[u] = GM[j];
     }
-    const bool ka = (a != 0.0), km = (g != 0) && (j <= i);
-    const uint64_t ba = __ballot(ka), bm = __ballot(km);
-    if (ka) {
-      const int pos = na + __popcll(ba & below);
-      if (pos < KA) {
-        colA[pos] = (int)j;
-        valA[pos] = a;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + 64 * u + lane;
+      const bool in = j < n;
+      const double a = av[u];
+      const bool ka = in && (a != 0.0), km = in && (gv[u] != 0) && (j <= i);
+      const uint64_t ba = __ballot(ka), bm = __ballot(km);
+      if (ka) {
+        const int pos = na + __popcll(ba & below);
+        if (pos < KA) {
+          colA[pos] = (int)j;
+          valA[pos] = a;
+        }
       }
+      if (km) {
+        const int pos = nm + __popcll(bm & below);
+        if (pos < KM) colM[pos] = (int)j;
+      }
+      na += __popcll(ba);
+      nm += __popcll(bm);
     }
-    if (km) {
-      const int pos = nm + __popcll(bm & below);
-      if (pos < KM) colM[pos] = (int)j;
-    }
-    na += __popcll(ba);
-    nm += __popcll(bm);
   }
   if (lane == 0) {
     int* cnt = r.cnt + ((int64_t)b * r.rows + i) * 2;
