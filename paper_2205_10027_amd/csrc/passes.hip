@@ -208,6 +208,11 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
   __syncthreads();
 
   double s_tr = 0.0, s_l1 = 0.0, s_nnz = 0.0, s_w = 0.0, s_d2 = 0.0;
+  // the free-set flags of all 16 rows first (in-tile offsets are inside the padded
+  // matrix; flags past n are not used): one round trip instead of one per row group
+  int8_t gmv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) gmv[q] = GM[(i0 + rw + 4 * q) * np + j0 + c];
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int r = rw + 4 * q;
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(256) void pass_trial_kernel(const double* __restric
     if (!diag || c <= r) {
       if (i < n && j < n) {
         // off the free set A_ij = 0 and At_ij = 0: nothing else to read
-        const int8_t gm = GM[off];
+        const int8_t gm = gmv[q];
         if (gm != 0) {
           const double a = A[off];
           const double s = S[off];
