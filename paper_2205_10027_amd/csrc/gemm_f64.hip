@@ -231,14 +231,25 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
     mask_slice<TB, T>(n0, kbeg, tid, btri, rb[0]);
     store_slice<TA, T>(As[0], tid, ra[0]);
     store_slice<TB, T>(Bs[0], tid, rb[0]);
-    bool live = true;  // the slice in As[cur], Bs[cur] has a nonzero product
-    if (sparse) {
-      const bool za = __syncthreads_or(nonzero(ra[0]));
-      const bool zb = __syncthreads_or(nonzero(rb[0]));
-      live = za && zb;
-    } else {
+    // whether a stored slice has a nonzero in op(A) and in op(B): per wave a ballot
+    // each, bit 0 and bit 1 of the wave's word, read by all after the one barrier
+    // that publishes the slice (two words per wave used in turn: a wave can write
+    // the next slice's word only after every wave has passed this barrier)
+    __shared__ unsigned int zflags[2][4];
+    int zpar = 0;
+    auto publish = [&](const double (&xa)[R], const double (&xb)[R]) -> bool {
+      if (!sparse) {
+        __syncthreads();
+        return true;
+      }
+      const uint64_t ba = __ballot(nonzero(xa)), bb = __ballot(nonzero(xb));
+      if (lane == 0) zflags[zpar][wave] = (ba ? 1u : 0u) | (bb ? 2u : 0u);
       __syncthreads();
-    }
+      const unsigned int f = zflags[zpar][0] | zflags[zpar][1] | zflags[zpar][2] | zflags[zpar][3];
+      zpar ^= 1;
+      return f == 3u;
+    };
+    bool live = publish(ra[0], rb[0]);  // the slice in As[cur], Bs[cur] has a nonzero product
     // kq[s]: the slice register set s holds (kend: none); klast: the last one issued.
     // Past the last slice a set is loaded with the last valid one and never used: the
     // loads stay unconditional, so the compiler waits for each only where it is used.
@@ -300,13 +311,7 @@ __global__ __launch_bounds__(256, T == 128 ? 2 : 4) void gemm_f64_kernel(GemmF64
         mask_slice<TB, T>(n0, kq[s], tid, btri, rb[s]);
         store_slice<TA, T>(As[cur ^ 1], tid, ra[s]);
         store_slice<TB, T>(Bs[cur ^ 1], tid, rb[s]);
-        if (sparse) {
-          const bool za = __syncthreads_or(nonzero(ra[s]));
-          const bool zb = __syncthreads_or(nonzero(rb[s]));
-          live = za && zb;
-        } else {
-          __syncthreads();
-        }
+        live = publish(ra[s], rb[s]);
         // refill set s with the slice PD places further on
         klast = (klast < kend) ? next_k(klast) : kend;
         kq[s] = klast;
