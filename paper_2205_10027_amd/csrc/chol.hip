@@ -305,11 +305,14 @@ __global__ __launch_bounds__(256) void leaf_potrf_kernel(double* A, int64_t lda,
         else
           nz1 = nz1 || x[b][s] != 0.0;
       }
-    nz0 = __syncthreads_or(nz0);
-    nz1 = __syncthreads_or(nz1);
+    // per-wave ballots combined through LDS: one barrier for both bits
+    __shared__ unsigned int nzw[4];
+    const uint64_t b0 = __ballot(nz0), b1 = __ballot(nz1);
+    if (lane == 0) nzw[wave] = (b0 ? 1u : 0u) | (b1 ? 2u : 0u);
+    __syncthreads();
     if (tid == 0)
       fb.nz[blockIdx.y * fb.snz + (int64_t)(k0 / NB) * fb.nz_chunks + (k0 + NB) / 64 + (int)blockIdx.x - 1] =
-          (uint8_t)((nz0 ? 1 : 0) | (nz1 ? 2 : 0));
+          (uint8_t)(nzw[0] | nzw[1] | nzw[2] | nzw[3]);
   }
 }
 
