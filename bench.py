@@ -57,7 +57,7 @@ VTV_TRAFFIC_BYTES = 11511834624
 # HBM bytes per leaf_potrf_kernel launch at n = 10^4 (mean over the leaf steps of
 # every factorisation of the chain solves), from FETCH_SIZE and WRITE_SIZE counter runs
 # scaled by a 1 GiB plain-copy calibration (profiles/traffic_leaf_chain10k.md)
-LEAF_TRAFFIC_BYTES = 12968851
+LEAF_TRAFFIC_BYTES = 12934499
 
 
 def log(*a):
