@@ -45,10 +45,10 @@ __global__ __launch_bounds__(256) void sparse_rows_kernel(const double* __restri
   int* colM = r.colM + ((int64_t)b * r.rows + i) * KM;
   const uint64_t below = (1ull << lane) - 1;
   int na = 0, nm = 0;
-  // four 64-column chunks per round, all loaded before the first is compacted (the
+  // eight 64-column chunks per round, all loaded before the first is compacted (the
   // loads are unconditional: a column past n is read at a clamped in-row index and
-  // ignored), so a wave keeps four round trips in flight instead of one
-  constexpr int U = 4;
+  // ignored), so a wave keeps eight round trips in flight instead of one
+  constexpr int U = 8;
   for (int64_t j0 = 0; j0 < n; j0 += 64 * U) {
     double av[U];
     int8_t gv[U];
