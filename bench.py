@@ -193,7 +193,7 @@ def bench_config0(g, torch, dev, reps=5):
     return out
 
 
-def bench_config1(g, torch, dev, reps=3):
+def bench_config1(g, torch, dev, reps=10):
     """Random sparse n = 2000, m = 1000, seed 0, lambda frozen to give nnz(A*) ~ 5n,
     tol 1e-5: time-to-KKT of the FP64 path and both mixed forms, each result's error
     against the stored oracle solution."""
